@@ -1,0 +1,113 @@
+"""Seeded synthetic workloads shared by the oracle, the tests and the benchmark.
+
+This module holds only input descriptions: physical parameters of the cuvette,
+the particles, the beam and the detector, photon budgets and seeds.  It holds
+none of the method's arithmetic (no Mie series, no sampling, no transport), so
+both the oracle and the HIP path can read it without sharing any computation.
+
+The workloads stand in for the paper's experiment (Sec. 4, Sec. 5.2): 5 um
+polystyrene spheres in water, 532 nm light, optical depths of a few to ~10,
+1e8-scale photon counts per image.  The cuvette is a 10 mm cube rather than the
+paper's 30 x 10 x 45 mm cell; every size is a parameter.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+PHASE_MIE = 0
+PHASE_HG = 1
+
+
+@dataclass(frozen=True)
+class Particle:
+    """Sphere and host medium (Sec. 2.2, Eqs. 3-4; Sec. 2.5)."""
+    diameter_um: float = 5.0
+    m_re: float = 1.59           # particle index, real part
+    m_im: float = 0.0            # particle index, imaginary part (>= 0 absorbs)
+    n_medium: float = 1.33       # water
+    wavelength_nm: float = 532.0
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One forward run of the photon walk (Sec. 3.1.3)."""
+    name: str
+    particle: Particle = Particle()
+    tau: float = 1.0                      # optical depth along the beam (Eq. 1)
+    albedo: float = 0.9999                # single-scatter albedo mu_s / mu_ext
+    size_mm: tuple = (10.0, 10.0, 10.0)   # cuboid x, y, z
+    n_outside: float = 1.0                # index outside the walls (air)
+    src_pos_mm: tuple = (5.0, 5.0, 0.0)   # pencil beam at the z = 0 face centre
+    src_dir: tuple = (0.0, 0.0, 1.0)
+    n_angles: int = 1801                  # 0.1 degree phase table
+    n_cdf: int = 4096
+    phase: int = PHASE_MIE
+    side_px: int = 128                    # side image on the +x face (rows y, cols z)
+    trans_px: int = 128                   # transmitted image on the +z face (rows y, cols x)
+    n_photons: int = 100_000
+    seed: int = 1234
+    instance: int = 0
+    roulette_w: float = 1e-4
+    roulette_p: float = 0.1
+    max_steps: int = 1 << 20
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+# Plain forward, tiny: the parity workload.
+TINY = Workload(name="tiny_tau1_1e5", tau=1.0, n_cdf=4096, side_px=128,
+                trans_px=128, n_photons=100_000)
+
+# Plain forward at paper scale: tau in {1, 2, 4, 8}, 1e8 photons, 16384-entry
+# inverse CDF, 512 x 512 images; tau = 4 is the headline throughput workload.
+PAPER_TAUS = (1.0, 2.0, 4.0, 8.0)
+
+
+def paper_scale(tau: float = 4.0, phase: int = PHASE_MIE,
+                n_photons: int = 100_000_000) -> Workload:
+    tag = "mie" if phase == PHASE_MIE else "hg"
+    return Workload(name=f"paper_tau{tau:g}_{tag}_{n_photons:.0e}", tau=tau,
+                    n_cdf=16384, side_px=512, trans_px=512,
+                    n_photons=n_photons, phase=phase)
+
+
+HEADLINE = paper_scale(4.0)
+
+# Differentiation workload: tau = 4, 1e7 photons per evaluation; target image
+# at tau = 4.5 with seed 99.
+DIFF = paper_scale(4.0, n_photons=10_000_000).replace(name="diff_tau4_1e7")
+DIFF_TARGET = DIFF.replace(name="diff_target_tau4.5", tau=4.5, seed=99)
+
+
+@dataclass(frozen=True)
+class BatchInstance:
+    diameter_um: float
+    tau: float
+    albedo: float
+    n_photons: int
+
+
+def batch_instances(n: int = 256, seed: int = 2507) -> List[BatchInstance]:
+    """Batched media: d log-uniform 0.5-10 um, tau ~ U(0.5, 10),
+    albedo ~ U(0.95, 1), photons log-uniform 1e5-1e7 (numpy PCG64 seed 2507)."""
+    rng = np.random.default_rng(seed)
+    d = np.exp(rng.uniform(np.log(0.5), np.log(10.0), n))
+    tau = rng.uniform(0.5, 10.0, n)
+    alb = rng.uniform(0.95, 1.0, n)
+    nph = np.exp(rng.uniform(np.log(1e5), np.log(1e7), n)).astype(np.int64)
+    return [BatchInstance(float(a), float(b), float(c), int(e))
+            for a, b, c, e in zip(d, tau, alb, nph)]
+
+
+def sample_ids(n_total: int, n_sample: int, seed: int = 7) -> np.ndarray:
+    """Sorted distinct photon ids spread over [0, n_total) for sampled parity
+    at full size (numpy PCG64)."""
+    rng = np.random.default_rng(seed)
+    n_sample = min(n_sample, n_total)
+    ids = rng.choice(n_total, size=n_sample, replace=False)
+    return np.sort(ids.astype(np.uint64))
