@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Throughput of the Monte Carlo / rigorous-Mie photon walk on one MI355X.
+
+One step is one pass of the whole hot path on the headline workload: the Mie
+table build on the device (series, phase function, CDF, inverse table) and
+the photon walk of 1e8 photons through a 10 mm water cube holding 5 um
+polystyrene spheres at optical depth 4 (Philox seed 1234, 16384-entry inverse
+CDF, 512 x 512 side and transmitted images).  `value` is scatter events per
+second over the timed steps, inputs resident on the device.
+
+The JSON line also carries
+  roofline      the walk kernel's achieved issue rate from an operation census
+                of the method (counts of steps, interactions, boundary steps
+                and exits, each priced in FP32 VALU issue slots) over its
+                measured average duration (HIP events on the launch stream),
+                against the chip's FP32 VALU issue peak;
+  cpu_baseline  the FP64 oracle timed on this host on a bounded sample of the
+                same workload.
+
+    python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mie MC scatter events/s (τ=4, 1e8 photons); fwd+adjoint vs fwd-only time"
+
+# Issue slots per unit of work, counted from the walk's arithmetic (FP32/INT32
+# lane operations at 1 slot; transcendentals and 32x32->64-bit products at 4).
+CENSUS = {"step": 169, "interaction": 72, "boundary": 41, "exit": 30}
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes, 2.4 GHz peak engine clock.
+PEAK_SLOTS_PER_S = 256 * 64 * 2.4e9
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def census_slots(scal):
+    steps, events, photons = scal[14], scal[9], scal[10]
+    exits = photons - scal[11] - scal[12]
+    boundary = steps - events
+    return (CENSUS["step"] * steps + CENSUS["interaction"] * events + CENSUS["boundary"] * boundary
+            + CENSUS["exit"] * exits)
+
+
+def cpu_baseline(w, target_s: float):
+    """FP64 oracle on host threads over photons 0..n-1 of the same workload."""
+    from oracle import walk as owalk
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    wk = owalk.Walk(w)
+    pilot = wk.run(n_photons=20000, threads=threads)
+    rate = 20000 / max(pilot.seconds, 1e-6)
+    n = int(min(w.n_photons, max(20000, rate * target_s)))
+    res = wk.run(n_photons=n, threads=threads)
+    ev = res.scalars[9]
+    try:
+        cpu = open("/proc/cpuinfo").read().split("model name")[1].split("\n")[0].strip(" :\t")
+    except Exception:
+        cpu = "unknown"
+    return {"value": ev / res.seconds, "unit": "scatter events/s", "cores": threads, "kind": "oracle",
+            "sample": f"photons 0..{n - 1} of the same workload (same seed and draws), FP64 C oracle, "
+                      f"{threads} host threads, {res.seconds:.1f} s, {ev:.3e} events; host CPU: {cpu}"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tau", type=float, default=4.0)
+    ap.add_argument("--photons", type=int, default=100_000_000)
+    ap.add_argument("--phase", choices=("mie", "hg"), default="mie")
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--grid-blocks", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the walk shards by photon range across GPUs but this build runs on a single device.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2507_23189_amd as mc
+    import workloads as W
+
+    phase = W.PHASE_MIE if args.phase == "mie" else W.PHASE_HG
+    w = W.paper_scale(args.tau, phase=phase, n_photons=args.photons)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    spec, *_ = mc.args_from_workload(w)
+    stream = torch.cuda.current_stream()
+
+    det_probe = mc.args_from_workload(w)[4]
+    tallies = [mc.Tally.alloc(det_probe, dev) for _ in range(args.warmup + args.steps)]
+    walk_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.warmup + args.steps)]
+
+    def step(i):
+        table = mc.mie_table_build(spec, dev)                    # device kernel; returns after sync
+        _, med, src, geo, det, run = mc.args_from_workload(w, table, block_size=args.block_size,
+                                                           grid_blocks=args.grid_blocks)
+        e0, e1 = walk_ev[i]
+        e0.record(stream)
+        mc.mc_simulate(med, src, geo, det, run, tallies[i])
+        e1.record(stream)
+        return table
+
+    log(f"bench: workload {w.name}, warmup {args.warmup}, steps {args.steps}")
+    keep = []
+    for i in range(args.warmup):
+        keep.append(step(i))
+    torch.cuda.synchronize()
+    log("bench: warmup done")
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        keep.append(step(i))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log("bench: timed steps done")
+
+    scal = [t.scalars.cpu().numpy() for t in tallies[args.warmup:]]
+    events = float(sum(s[9] for s in scal))
+    photons = float(sum(s[10] for s in scal))
+    elapsed = t1 - t0
+    walk_ms = [walk_ev[i][0].elapsed_time(walk_ev[i][1]) for i in range(args.warmup, args.warmup + args.steps)]
+    walk_avg_s = sum(walk_ms) / len(walk_ms) * 1e-3
+    slots = census_slots(scal[-1])
+    achieved = slots / walk_avg_s
+    s_last = scal[-1]
+
+    out = {
+        "metric": METRIC,
+        "value": events / elapsed,
+        "unit": "scatter events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "tau": w.tau, "photons": w.n_photons, "phase": args.phase,
+                   "particle": "polystyrene d=5um n=1.59 in water n=1.33, lambda 532 nm",
+                   "cuboid_mm": list(w.size_mm), "n_cdf": w.n_cdf, "images": [w.side_px, w.trans_px],
+                   "seed": w.seed, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
+                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S, "traffic": None,
+                     "kernel": "walk_kernel<MIE>" if phase == W.PHASE_MIE else "walk_kernel<HG>",
+                     "kernel_ms": walk_avg_s * 1e3, "slots_per_launch": slots},
+        "photons_per_s": photons / elapsed,
+        "events_per_photon": s_last[9] / s_last[10],
+        "steps_per_photon": s_last[14] / s_last[10],
+        "adjoint_ratio": None,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

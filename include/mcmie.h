@@ -1,0 +1,229 @@
+/*
+ * mcmie.h -- C ABI of the MI355X Monte Carlo / rigorous-Mie photon-walk library.
+ *
+ * The library implements the GPU part of the Monte Carlo - rigorous Mie
+ * transport model (arXiv 2507.23189): the Mie table of Sec. 2.2-2.6 and
+ * Sec. 3.1.2 and the photon walk of Sec. 3.1.3, as hand-written HIP kernels
+ * for gfx950.  Every call is plain C: host structs in, caller-owned device
+ * buffers, an int status out.  No exception crosses this boundary.
+ *
+ * Conventions
+ *   Units: lengths in mm, particle diameter in um, wavelength in nm,
+ *          coefficients in 1/mm (Table 2, Eq. 14).
+ *   Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *          stream).  Work is enqueued on it and the call returns without
+ *          waiting unless stated otherwise; the caller keeps every buffer
+ *          alive until the stream has drained.
+ *   Ownership: the caller allocates every buffer.  The library keeps no
+ *          pointer after a call returns.  Its only device memory is a small
+ *          per-device scratch block for the table build.
+ *   Errors: functions return MC_OK (0) or a negative MC_E* code; the
+ *          message of the last failure on the calling thread is returned by
+ *          mc_last_error().  Arguments are validated on the host before any
+ *          work is enqueued; on an error nothing is enqueued.
+ */
+#ifndef MCMIE_H
+#define MCMIE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_OK 0
+#define MC_EINVAL (-1)        /* an argument is out of range or inconsistent */
+#define MC_EDEVICE (-2)       /* a HIP runtime call failed */
+#define MC_ENOMEM (-3)        /* device scratch could not be allocated */
+#define MC_EUNSUPPORTED (-4)  /* a valid request this build does not implement */
+
+#define MC_PHASE_MIE 0        /* polar angle from the inverse-CDF table */
+#define MC_PHASE_HG 1         /* polar angle from Henyey-Greenstein (Eq. 11) */
+
+/* Detector flags (mc_detector_t.flags). */
+#define MC_ACCUMULATE 1u      /* add into images and scalars instead of zeroing them first */
+#define MC_SIGMA 2u           /* also tally squared weights (side_w2, trans_w2) */
+#define MC_RECORD 4u          /* write per-photon end records (mc_tally_t.rec_*) */
+
+/* Scalar tallies: mc_tally_t.scalars holds MC_N_SCALARS doubles. */
+#define MC_S_FACE 0           /* 0..5: weight leaving faces -x, +x, -y, +y, -z, +z */
+#define MC_S_ABSORBED 6       /* weight absorbed at interactions (Eq. 16) */
+#define MC_S_ROULETTE_NET 7   /* sum of weight changes made by Russian roulette */
+#define MC_S_CAPPED_W 8       /* weight of photons stopped by the step cap */
+#define MC_S_EVENTS 9         /* scatter events (interactions) */
+#define MC_S_PHOTONS 10       /* photons finished */
+#define MC_S_ROULETTE_KILLS 11
+#define MC_S_CAPPED 12        /* photons stopped by the step cap */
+#define MC_S_REFLECTIONS 13   /* Fresnel / total internal reflections at walls */
+#define MC_S_STEPS 14         /* random-number blocks drawn (walk steps) */
+#define MC_S_WORK 15          /* reserved: the library's work counter */
+#define MC_N_SCALARS 16
+
+/* Per-photon record fields (structure of arrays, rec_rows rows per field). */
+#define MC_REC_I_FACE 0       /* exit face 0..5, or -1 */
+#define MC_REC_I_CAUSE 1      /* 0 exited, 1 roulette, 2 step cap */
+#define MC_REC_I_K 2          /* scatter events */
+#define MC_REC_I_STEPS 3      /* walk steps */
+#define MC_REC_I_N 4
+#define MC_REC_F_POS 0        /* 0..2: end position (on the face for exits) */
+#define MC_REC_F_DIR 3        /* 3..5: end direction (refracted outside for exits) */
+#define MC_REC_F_W 6          /* end weight (exit weight; 0 after a roulette kill) */
+#define MC_REC_F_L 7          /* path length */
+#define MC_REC_F_A 8          /* weight absorbed along the path */
+#define MC_REC_F_N 9
+
+#define MC_MAX_N_CDF 16384    /* largest inverse table (64 KB, held in LDS) */
+#define MC_MAX_N_ANGLES 3001  /* largest phase-function grid */
+#define MC_MAX_TERMS 1024     /* largest Mie series length (x up to ~980) */
+
+/* ------------------------------------------------------------------ Mie */
+
+/* Particle, host medium and table resolution (Sec. 2.2, Eqs. 3-4; Sec. 3.1.2). */
+typedef struct {
+    double n_medium;       /* real index of the host medium (> 0) */
+    double m_re, m_im;     /* particle index m = n + ik (Eq. 4), m_re > 0, m_im >= 0 absorbs */
+    double diameter_um;    /* sphere diameter d (> 0) */
+    double wavelength_nm;  /* vacuum wavelength (> 0); x = pi d n_medium / wavelength (Eq. 3) */
+    int32_t n_angles;      /* phase-table angles over [0, pi], ends included, 3..MC_MAX_N_ANGLES */
+    int32_t n_cdf;         /* inverse-table entries, 2..MC_MAX_N_CDF */
+} mie_spec_t;
+
+/* Results of mie_table_build.  Scalars are written on the host; the arrays
+ * are caller-owned DEVICE buffers (NULL to skip an optional one). */
+typedef struct {
+    double x;              /* size parameter (Eq. 3) */
+    double m_rel_re, m_rel_im;   /* m / n_medium */
+    double q_ext, q_sca, q_abs;  /* efficiencies (Eq. 13; Q_abs = Q_ext - Q_sca) */
+    double g;              /* asymmetry (Eq. 12) from the series */
+    double sigma_ext_mm2, sigma_sca_mm2, sigma_abs_mm2;   /* Q pi d^2 / 4 (Eq. 14) */
+    int32_t n_terms;       /* series terms used */
+    int32_t n_cdf;         /* entries written to inv_cdf */
+    float *inv_cdf;        /* device, n_cdf floats: v_i = 1 - cos(theta(u_i)), u_i = i/(n_cdf-1) (required) */
+    double *phase;         /* device, n_angles doubles: P(theta_j), (1/4pi) int P dOmega = 1 (Eqs. 9-10), optional */
+    double *cdf;           /* device, n_angles doubles: F(theta_j), trapezoid rule, F = 1 at pi, optional */
+    double *coef;          /* device, 4 * coef_capacity doubles: Re a_n, Im a_n, Re b_n, Im b_n per n (Eqs. 7-8), optional */
+    int32_t coef_capacity; /* terms coef can hold; must be >= n_terms when coef is set */
+} mie_table_t;
+
+/*
+ * Build the Mie phase-function table on the device (Sec. 2.2-2.6, Sec. 3.1.2):
+ * a_n, b_n by the Bohren-Huffman logarithmic-derivative recurrence (Sec. 2.5),
+ * Q_ext/Q_sca/g (Eqs. 12-13), S1/S2 (Eqs. 5-6) and the normalised phase
+ * function (Eqs. 9-10) on n_angles angles, its CDF in theta, and the inverse
+ * table sampled at n_cdf equally spaced probabilities.  All of it runs in one
+ * FP64 kernel on `stream`; the call then waits for the stream so the host
+ * scalars of `table` are valid on return.  The device buffers of `table`
+ * must hold the sizes stated above.  Returns MC_EINVAL on a bad spec or
+ * missing buffer, MC_EDEVICE / MC_ENOMEM on runtime failure.
+ */
+int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void *stream);
+
+/* -------------------------------------------------------------- the walk */
+
+/* Medium filling the cuboid (Eq. 1, Eq. 16). */
+typedef struct {
+    double tau;            /* optical depth along z: mu_ext = tau / size_z (Eq. 1), >= 0 */
+    double albedo;         /* mu_sca / mu_ext in [0, 1]; mu_abs = (1 - albedo) mu_ext */
+    int32_t phase;         /* MC_PHASE_MIE or MC_PHASE_HG */
+    int32_t n_cdf;         /* MIE: entries of inv_cdf, 2..MC_MAX_N_CDF */
+    const float *inv_cdf;  /* MIE: device inverse table as written by mie_table_build */
+    double g;              /* HG: asymmetry in (-1, 1) */
+} mc_medium_t;
+
+/* Collimated pencil beam entering the z = 0 face (Sec. 3.1.3: parallel beam,
+ * all photons with the same initial direction). */
+typedef struct {
+    double pos_mm[3];      /* entry point: z must be 0, x and y inside the face */
+    double dir[3];         /* incident direction outside the cuboid, dir[2] > 0 (normalised here) */
+} mc_source_t;
+
+/* Cuboid cuvette (Sec. 4.3) with one refractive-index step at every wall. */
+typedef struct {
+    double size_mm[3];     /* extent along x, y, z, each > 0 */
+    double n_medium;       /* index inside (> 0) */
+    double n_outside;      /* index outside (> 0); equal to n_medium means no Fresnel term */
+} mc_geometry_t;
+
+/* Detector images: side view on the +x face (rows y, columns z) and the
+ * transmitted image on the +z face (rows y, columns x); pixel index =
+ * floor(coord / size * n), clamped to n - 1 (Sec. 4.3, Sec. 5.2). */
+typedef struct {
+    int32_t side_nx, side_ny;     /* columns (z) and rows (y) of the side image, >= 1 */
+    int32_t trans_nx, trans_ny;   /* columns (x) and rows (y) of the transmitted image, >= 1 */
+    uint32_t flags;               /* MC_ACCUMULATE | MC_SIGMA | MC_RECORD */
+} mc_detector_t;
+
+/* Photon budget, random streams, termination and launch shape. */
+typedef struct {
+    uint64_t n_photons;    /* photons in this call (0 allowed: only zeroing happens) */
+    uint64_t photon_offset;/* id of the first photon; ids are offset .. offset + n - 1 */
+    uint64_t seed;         /* Philox4x32-10 key (seed_lo, seed_hi) */
+    uint32_t instance;     /* Philox counter word 1 (independent medium instances) */
+    uint32_t max_steps;    /* step cap per photon, >= 1 */
+    double roulette_w;     /* Russian roulette below this weight (0 disables) */
+    double roulette_p;     /* survival probability in (0, 1]; survivors' weight / p */
+    uint64_t record_stride;/* MC_RECORD: photon offset + r * stride goes to row r (>= 1) */
+    int32_t block_size;    /* threads per block, multiple of 64 in 64..1024; 0 = library choice */
+    int32_t grid_blocks;   /* blocks; 0 = library choice (enough to fill every CU) */
+} mc_run_t;
+
+/* Caller-owned DEVICE outputs. */
+typedef struct {
+    double *side;          /* side_ny * side_nx doubles, row-major (required) */
+    double *trans;         /* trans_ny * trans_nx doubles, row-major (required) */
+    double *side_w2;       /* MC_SIGMA: squared-weight image, same shape */
+    double *trans_w2;      /* MC_SIGMA */
+    double *scalars;       /* MC_N_SCALARS doubles (required); slot MC_S_WORK is scratch */
+    int32_t *rec_i;        /* MC_RECORD: MC_REC_I_N * rec_rows int32 */
+    float *rec_f;          /* MC_RECORD: MC_REC_F_N * rec_rows float */
+    uint64_t rec_rows;     /* MC_RECORD: rows available; photons beyond are not recorded */
+} mc_tally_t;
+
+/*
+ * Run the photon walk of Sec. 3.1.3 for run->n_photons photons: start at the
+ * source with the entry Fresnel loss, free paths from Eq. 15, boundary
+ * determination with Fresnel reflection / refraction at the walls, polar
+ * angle from the inverse CDF (Sec. 2.6) or HG (Eq. 11), uniform azimuth,
+ * the weight update of Eq. 16 with Russian roulette, and atomic tallies of
+ * exit positions into the detector images (Sec. 3.1.3, last paragraph).
+ * Photon i draws one Philox4x32-10 block per step with counter
+ * (step, instance, id_lo, id_hi) and key (seed_lo, seed_hi), so a run split
+ * into photon ranges with MC_ACCUMULATE equals one run up to tally rounding.
+ * Unless MC_ACCUMULATE is set the images, scalars and records are zeroed on
+ * `stream` first.  Asynchronous.  Calls that share a tally buffer must not
+ * overlap in time.
+ */
+int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
+                const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,
+                void *stream);
+
+/*
+ * Reserved for the perturbation Monte Carlo adjoint (derivatives of a loss
+ * on the side image with respect to mu_sca, mu_abs and concentration, Eq. 15
+ * to Eq. 17).  Not implemented in this build: validates nothing and returns
+ * MC_EUNSUPPORTED.
+ */
+int mc_grad(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
+            const mc_detector_t *detector, const mc_run_t *run, const double *dloss_dside,
+            double out_grad[3], void *stream);
+
+/*
+ * The random numbers the walk draws: for each of n_ids photon ids (device
+ * array) and steps step0 .. step0 + n_steps - 1, write the four 32-bit
+ * Philox4x32-10 words to out (device, n_ids * n_steps * 4 uint32, photon-major).
+ * Exposed so the generator can be checked word for word.  Asynchronous.
+ */
+int mc_philox_blocks(uint64_t seed, uint32_t instance, const uint64_t *ids, uint64_t n_ids,
+                     uint32_t step0, uint32_t n_steps, uint32_t *out, void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *mc_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int mc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCMIE_H */

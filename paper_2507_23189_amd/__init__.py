@@ -1,0 +1,14 @@
+"""MI355X-native Monte Carlo / rigorous-Mie photon walk (arXiv 2507.23189).
+
+The computation lives in libmcmie.so (hand-written HIP for gfx950, C ABI in
+include/mcmie.h); this package only marshals arguments to it.  Importing the
+package does not load the library; the first call does, and raises if it has
+not been built.
+"""
+from ._capi import (MC_ACCUMULATE, MC_EDEVICE, MC_EINVAL, MC_ENOMEM, MC_EUNSUPPORTED, MC_MAX_N_ANGLES,
+                    MC_MAX_N_CDF, MC_MAX_TERMS, MC_N_SCALARS, MC_OK, MC_PHASE_HG, MC_PHASE_MIE, MC_RECORD,
+                    MC_SIGMA, Detector, Geometry, McError, Medium, MieSpec, MieTable, Run, Source, Tally, lib,
+                    mc_grad, mc_philox_blocks, mc_simulate, mc_version, mie_table_build)
+from .args import args_from_workload
+
+__all__ = [n for n in dir() if not n.startswith("_")]

@@ -1,0 +1,214 @@
+"""ctypes binding of libmcmie.so (include/mcmie.h).  Argument marshalling only:
+every computation happens in the library's HIP kernels.  Device buffers are
+torch tensors; work is enqueued on torch's current HIP stream."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcmie.so")
+
+MC_OK, MC_EINVAL, MC_EDEVICE, MC_ENOMEM, MC_EUNSUPPORTED = 0, -1, -2, -3, -4
+MC_PHASE_MIE, MC_PHASE_HG = 0, 1
+MC_ACCUMULATE, MC_SIGMA, MC_RECORD = 1, 2, 4
+MC_N_SCALARS = 16
+MC_S_FACE, MC_S_ABSORBED, MC_S_ROULETTE_NET, MC_S_CAPPED_W, MC_S_EVENTS = 0, 6, 7, 8, 9
+MC_S_PHOTONS, MC_S_ROULETTE_KILLS, MC_S_CAPPED, MC_S_REFLECTIONS, MC_S_STEPS, MC_S_WORK = 10, 11, 12, 13, 14, 15
+MC_REC_I_N, MC_REC_F_N = 4, 9
+MC_MAX_N_CDF, MC_MAX_N_ANGLES, MC_MAX_TERMS = 16384, 3001, 1024
+
+
+class MieSpec(C.Structure):
+    _fields_ = [("n_medium", C.c_double), ("m_re", C.c_double), ("m_im", C.c_double),
+                ("diameter_um", C.c_double), ("wavelength_nm", C.c_double),
+                ("n_angles", C.c_int32), ("n_cdf", C.c_int32)]
+
+
+class _MieTableC(C.Structure):
+    _fields_ = [("x", C.c_double), ("m_rel_re", C.c_double), ("m_rel_im", C.c_double),
+                ("q_ext", C.c_double), ("q_sca", C.c_double), ("q_abs", C.c_double), ("g", C.c_double),
+                ("sigma_ext_mm2", C.c_double), ("sigma_sca_mm2", C.c_double), ("sigma_abs_mm2", C.c_double),
+                ("n_terms", C.c_int32), ("n_cdf", C.c_int32),
+                ("inv_cdf", C.c_void_p), ("phase", C.c_void_p), ("cdf", C.c_void_p), ("coef", C.c_void_p),
+                ("coef_capacity", C.c_int32)]
+
+
+class Medium(C.Structure):
+    _fields_ = [("tau", C.c_double), ("albedo", C.c_double), ("phase", C.c_int32), ("n_cdf", C.c_int32),
+                ("inv_cdf", C.c_void_p), ("g", C.c_double)]
+
+
+class Source(C.Structure):
+    _fields_ = [("pos_mm", C.c_double * 3), ("dir", C.c_double * 3)]
+
+
+class Geometry(C.Structure):
+    _fields_ = [("size_mm", C.c_double * 3), ("n_medium", C.c_double), ("n_outside", C.c_double)]
+
+
+class Detector(C.Structure):
+    _fields_ = [("side_nx", C.c_int32), ("side_ny", C.c_int32), ("trans_nx", C.c_int32),
+                ("trans_ny", C.c_int32), ("flags", C.c_uint32)]
+
+
+class Run(C.Structure):
+    _fields_ = [("n_photons", C.c_uint64), ("photon_offset", C.c_uint64), ("seed", C.c_uint64),
+                ("instance", C.c_uint32), ("max_steps", C.c_uint32), ("roulette_w", C.c_double),
+                ("roulette_p", C.c_double), ("record_stride", C.c_uint64), ("block_size", C.c_int32),
+                ("grid_blocks", C.c_int32)]
+
+
+class _TallyC(C.Structure):
+    _fields_ = [("side", C.c_void_p), ("trans", C.c_void_p), ("side_w2", C.c_void_p),
+                ("trans_w2", C.c_void_p), ("scalars", C.c_void_p), ("rec_i", C.c_void_p),
+                ("rec_f", C.c_void_p), ("rec_rows", C.c_uint64)]
+
+
+class McError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library.  Raises if it has not been built: there is no
+    fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2507_23189_amd.build` "
+                              "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        L.mie_table_build.argtypes = [C.POINTER(MieSpec), C.POINTER(_MieTableC), C.c_void_p]
+        L.mc_simulate.argtypes = [C.POINTER(Medium), C.POINTER(Source), C.POINTER(Geometry),
+                                  C.POINTER(Detector), C.POINTER(Run), C.POINTER(_TallyC), C.c_void_p]
+        L.mc_grad.argtypes = [C.POINTER(Medium), C.POINTER(Source), C.POINTER(Geometry), C.POINTER(Detector),
+                              C.POINTER(Run), C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
+        L.mc_philox_blocks.argtypes = [C.c_uint64, C.c_uint32, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
+                                       C.c_void_p, C.c_void_p]
+        L.mc_last_error.restype = C.c_char_p
+        L.mc_version.restype = C.c_int
+        for f in ("mie_table_build", "mc_simulate", "mc_grad", "mc_philox_blocks"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != MC_OK:
+        raise McError(rc, lib().mc_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class MieTable:
+    """Host scalars and device tensors written by mie_table_build."""
+    x: float
+    m_rel: complex
+    q_ext: float
+    q_sca: float
+    q_abs: float
+    g: float
+    sigma_ext_mm2: float
+    sigma_sca_mm2: float
+    sigma_abs_mm2: float
+    n_terms: int
+    inv_cdf: "object"              # torch float32 (n_cdf,)
+    phase: "object" = None         # torch float64 (n_angles,)
+    cdf: "object" = None           # torch float64 (n_angles,)
+    coef: "object" = None          # torch float64 (n_terms, 4): Re a, Im a, Re b, Im b
+
+
+def mie_table_build(spec: MieSpec, device="cuda", *, phase=False, cdf=False, coef=False,
+                    stream=None) -> MieTable:
+    """Build the Mie table on the device (blocks until the scalars are back)."""
+    import torch
+    dev = torch.device(device)
+    inv = torch.empty(max(int(spec.n_cdf), 1), dtype=torch.float32, device=dev)
+    ph = torch.empty(max(int(spec.n_angles), 1), dtype=torch.float64, device=dev) if phase else None
+    cd = torch.empty(max(int(spec.n_angles), 1), dtype=torch.float64, device=dev) if cdf else None
+    co = torch.empty((MC_MAX_TERMS, 4), dtype=torch.float64, device=dev) if coef else None
+    t = _MieTableC()
+    t.inv_cdf, t.phase, t.cdf, t.coef = _ptr(inv), _ptr(ph), _ptr(cd), _ptr(co)
+    t.coef_capacity = MC_MAX_TERMS if coef else 0
+    with torch.cuda.device(dev):
+        _check(lib().mie_table_build(C.byref(spec), C.byref(t), _stream(stream)))
+    return MieTable(t.x, complex(t.m_rel_re, t.m_rel_im), t.q_ext, t.q_sca, t.q_abs, t.g, t.sigma_ext_mm2,
+                    t.sigma_sca_mm2, t.sigma_abs_mm2, t.n_terms, inv, ph, cd,
+                    co[: t.n_terms] if co is not None else None)
+
+
+@dataclass
+class Tally:
+    """Caller-owned device outputs of mc_simulate."""
+    side: "object"
+    trans: "object"
+    scalars: "object"
+    side_w2: "object" = None
+    trans_w2: "object" = None
+    rec_i: "object" = None          # (MC_REC_I_N, rows) int32
+    rec_f: "object" = None          # (MC_REC_F_N, rows) float32
+
+    @staticmethod
+    def alloc(det: Detector, device="cuda", *, sigma=False, record_rows=0) -> "Tally":
+        import torch
+        dev = torch.device(device)
+        f64 = dict(dtype=torch.float64, device=dev)
+        t = Tally(torch.empty((det.side_ny, det.side_nx), **f64), torch.empty((det.trans_ny, det.trans_nx), **f64),
+                  torch.empty(MC_N_SCALARS, **f64))
+        if sigma:
+            t.side_w2 = torch.empty_like(t.side)
+            t.trans_w2 = torch.empty_like(t.trans)
+        if record_rows:
+            t.rec_i = torch.empty((MC_REC_I_N, record_rows), dtype=torch.int32, device=dev)
+            t.rec_f = torch.empty((MC_REC_F_N, record_rows), dtype=torch.float32, device=dev)
+        return t
+
+    def _c(self) -> _TallyC:
+        c = _TallyC()
+        c.side, c.trans, c.scalars = _ptr(self.side), _ptr(self.trans), _ptr(self.scalars)
+        c.side_w2, c.trans_w2 = _ptr(self.side_w2), _ptr(self.trans_w2)
+        c.rec_i, c.rec_f = _ptr(self.rec_i), _ptr(self.rec_f)
+        c.rec_rows = 0 if self.rec_i is None else int(self.rec_i.shape[1])
+        return c
+
+
+def mc_simulate(medium: Medium, source: Source, geometry: Geometry, detector: Detector, run: Run,
+                tally: Tally, stream=None) -> None:
+    """Enqueue the photon walk on the stream (asynchronous)."""
+    tc = tally._c()
+    _check(lib().mc_simulate(C.byref(medium), C.byref(source), C.byref(geometry), C.byref(detector),
+                             C.byref(run), C.byref(tc), _stream(stream)))
+
+
+def mc_grad(medium: Medium, source: Source, geometry: Geometry, detector: Detector, run: Run,
+            dloss_dside, stream=None):
+    out = (C.c_double * 3)()
+    _check(lib().mc_grad(C.byref(medium), C.byref(source), C.byref(geometry), C.byref(detector), C.byref(run),
+                         _ptr(dloss_dside), out, _stream(stream)))
+    return tuple(out)
+
+
+def mc_philox_blocks(seed: int, instance: int, ids, step0: int, n_steps: int, out, stream=None) -> None:
+    """Fill `out` (uint32 viewed as int32, len(ids) * n_steps * 4) with the walk's Philox words."""
+    _check(lib().mc_philox_blocks(seed, instance, _ptr(ids), int(ids.numel()), step0, n_steps, _ptr(out),
+                                  _stream(stream)))
+
+
+def mc_version() -> int:
+    return lib().mc_version()

@@ -1,0 +1,305 @@
+// Mie phase-function table on the device, FP64 (Sec. 2.2-2.6, Sec. 3.1.2).
+//
+// One workgroup builds one table:
+//   1. lane 0 runs the Bohren-Huffman series (Sec. 2.5): the logarithmic
+//      derivative D_n(mx) by downward recurrence, psi_n(x) and chi_n(x)
+//      upward, then a_n and b_n (Eqs. 7-8 divided through by psi_n(mx)),
+//      accumulating Q_ext (Eq. 13), Q_sca and the asymmetry sums (Eq. 12);
+//   2. every lane evaluates S1, S2 (Eqs. 5-6) at its share of the angle grid
+//      with the angular functions pi_n, tau_n by upward recurrence, giving the
+//      phase function normalised so that (1/4pi) int P dOmega = 1 (Eqs. 9-10);
+//   3. the trapezoid CDF of P sin(theta) is a chunked in-place block scan;
+//   4. each inverse-table entry u_i = i/(N-1) finds the first angle with
+//      F >= u_i by binary search and interpolates theta linearly; the table
+//      stores v = 1 - cos(theta) = 2 sin^2(theta/2) in FP32.
+// All arrays live in LDS (coefficients 32 KB, angle grid 24 KB at the limits).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <mutex>
+
+#include "common.hpp"
+
+namespace mcmie {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kChunk = (MC_MAX_N_ANGLES + kBlock - 1) / kBlock;
+
+struct cplx {
+    double re, im;
+};
+__device__ __forceinline__ cplx operator+(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cplx operator-(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cplx operator*(cplx a, cplx b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cplx operator*(double s, cplx a) { return {s * a.re, s * a.im}; }
+__device__ __forceinline__ cplx operator+(cplx a, double s) { return {a.re + s, a.im}; }
+// Smith's division: no overflow of |b|^2 for large operands.
+__device__ __forceinline__ cplx operator/(cplx a, cplx b)
+{
+    if (fabs(b.re) >= fabs(b.im)) {
+        const double r = b.im / b.re, den = b.re + b.im * r;
+        return {(a.re + a.im * r) / den, (a.im - a.re * r) / den};
+    }
+    const double r = b.re / b.im, den = b.re * r + b.im;
+    return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
+}
+__device__ __forceinline__ double norm2(cplx a) { return a.re * a.re + a.im * a.im; }
+
+struct MieArgs {
+    double x, m_re, m_im;
+    int n_terms, n_start, n_angles, n_cdf;
+    float *inv_cdf;
+    double *phase, *cdf, *coef;
+    double *result;          // q_ext, q_sca, g, n_terms
+};
+
+__global__ __launch_bounds__(kBlock) void mie_table_kernel(MieArgs a)
+{
+    __shared__ cplx s_a[MC_MAX_TERMS];
+    __shared__ cplx s_b[MC_MAX_TERMS];
+    __shared__ double s_ang[MC_MAX_N_ANGLES];
+    __shared__ double s_part[kBlock];
+    __shared__ double s_qsca;
+
+    const int tid = threadIdx.x;
+    const int N = a.n_terms;
+    const double x = a.x;
+
+    // ---- 1. series (one lane) ----------------------------------------
+    if (tid == 0) {
+        const cplx m = {a.m_re, a.m_im};
+        const cplx mx = x * m;
+        const cplx inv_mx = cplx{1.0, 0.0} / mx;
+        cplx D = {0.0, 0.0};
+        for (int n = a.n_start; n >= 1; --n) {
+            // D_{n-1} = n/(mx) - 1 / (D_n + n/(mx)); keep D_n for n <= N.
+            if (n <= N) s_a[n - 1] = D;
+            const cplx nmx = (double)n * inv_mx;
+            D = nmx - cplx{1.0, 0.0} / (D + nmx);
+        }
+        double psi_prev = cos(x), psi = sin(x);        // psi_{-1}, psi_0
+        double chi_prev = -sin(x), chi = cos(x);       // chi_{-1}, chi_0
+        double sum_ext = 0.0, sum_sca = 0.0, sum_g1 = 0.0, sum_g2 = 0.0;
+        cplx an_prev = {0.0, 0.0}, bn_prev = {0.0, 0.0};
+        const cplx inv_m = cplx{1.0, 0.0} / m;
+        for (int n = 1; n <= N; ++n) {
+            const double f = (2.0 * n - 1.0) / x;
+            const double psi_n = f * psi - psi_prev;
+            const double chi_n = f * chi - chi_prev;
+            const cplx xi_n = {psi_n, -chi_n};
+            const cplx xi_nm1 = {psi, -chi};
+            const cplx Dn = s_a[n - 1];
+            const double nx = (double)n / x;
+            const cplx da = Dn * inv_m + nx;
+            const cplx db = m * Dn + nx;
+            const cplx an = (psi_n * da - cplx{psi, 0.0}) / (da * xi_n - xi_nm1);
+            const cplx bn = (psi_n * db - cplx{psi, 0.0}) / (db * xi_n - xi_nm1);
+            s_a[n - 1] = an;
+            s_b[n - 1] = bn;
+            const double w = 2.0 * n + 1.0;
+            sum_ext += w * (an.re + bn.re);
+            sum_sca += w * (norm2(an) + norm2(bn));
+            // asymmetry: (n-1)(n+1)/n Re(a_{n-1} a_n* + b_{n-1} b_n*) + (2n+1)/(n(n+1)) Re(a_n b_n*)
+            if (n > 1) {
+                const double c = (double)(n - 1) * (n + 1) / n;
+                sum_g1 += c * (an_prev.re * an.re + an_prev.im * an.im + bn_prev.re * bn.re +
+                               bn_prev.im * bn.im);
+            }
+            sum_g2 += w / ((double)n * (n + 1)) * (an.re * bn.re + an.im * bn.im);
+            an_prev = an;
+            bn_prev = bn;
+            psi_prev = psi;
+            psi = psi_n;
+            chi_prev = chi;
+            chi = chi_n;
+        }
+        const double inv_x2 = 1.0 / (x * x);
+        const double q_ext = 2.0 * inv_x2 * sum_ext;
+        const double q_sca = 2.0 * inv_x2 * sum_sca;
+        const double g = 4.0 * inv_x2 * (sum_g1 + sum_g2) / q_sca;
+        s_qsca = q_sca;
+        a.result[0] = q_ext;
+        a.result[1] = q_sca;
+        a.result[2] = g;
+        a.result[3] = (double)N;
+    }
+    __syncthreads();
+
+    if (a.coef) {
+        for (int n = tid; n < N; n += kBlock) {
+            a.coef[4 * n + 0] = s_a[n].re;
+            a.coef[4 * n + 1] = s_a[n].im;
+            a.coef[4 * n + 2] = s_b[n].re;
+            a.coef[4 * n + 3] = s_b[n].im;
+        }
+    }
+
+    // ---- 2. phase function on the angle grid --------------------------
+    const int na = a.n_angles;
+    const double dth = M_PI / (double)(na - 1);
+    const double pnorm = 2.0 / (x * x * s_qsca);
+    for (int j = tid; j < na; j += kBlock) {
+        const double th = (double)j * dth;
+        const double mu = cos(th);
+        double pi_prev = 0.0, pi_n = 1.0;              // pi_0, pi_1
+        cplx S1 = {0.0, 0.0}, S2 = {0.0, 0.0};
+        for (int n = 1; n <= N; ++n) {
+            if (n > 1) {
+                const double p = ((2.0 * n - 1.0) * mu * pi_n - (double)n * pi_prev) / (double)(n - 1);
+                pi_prev = pi_n;
+                pi_n = p;
+            }
+            const double tau_n = (double)n * mu * pi_n - (double)(n + 1) * pi_prev;
+            const double c = (2.0 * n + 1.0) / ((double)n * (n + 1));
+            const cplx an = s_a[n - 1], bn = s_b[n - 1];
+            S1 = S1 + c * (pi_n * an + tau_n * bn);
+            S2 = S2 + c * (tau_n * an + pi_n * bn);
+        }
+        const double P = pnorm * (norm2(S1) + norm2(S2));
+        if (a.phase) a.phase[j] = P;
+        s_ang[j] = P * sin(th);
+    }
+    __syncthreads();
+
+    // ---- 3. trapezoid CDF, chunked in-place scan -----------------------
+    const int lo = tid * kChunk;
+    const int hi = min(lo + kChunk, na);
+    double f_left = (lo >= 1 && lo < na) ? s_ang[lo - 1] : 0.0;
+    double local = 0.0;
+    for (int j = max(lo, 1); j < hi; ++j) {
+        const double th_j = (double)j * dth, th_p = (double)(j - 1) * dth;
+        local += 0.5 * (th_j - th_p) * (s_ang[j - 1] + s_ang[j]);
+    }
+    s_part[tid] = local;
+    __syncthreads();
+    if (tid == 0) {   // exclusive scan of the per-lane sums (256 adds)
+        double run = 0.0;
+        for (int t = 0; t < kBlock; ++t) {
+            const double v = s_part[t];
+            s_part[t] = run;
+            run += v;
+        }
+        s_qsca = run;      // reuse: total integral
+    }
+    __syncthreads();
+    {
+        double acc = s_part[tid];
+        const double total = s_qsca;
+        double prev = f_left;
+        for (int j = lo; j < hi; ++j) {
+            const double f = s_ang[j];
+            if (j >= 1) {
+                const double th_j = (double)j * dth, th_p = (double)(j - 1) * dth;
+                acc += 0.5 * (th_j - th_p) * (prev + f);
+            }
+            prev = f;
+            s_ang[j] = (j == na - 1) ? 1.0 : acc / total;
+        }
+    }
+    __syncthreads();
+    if (a.cdf)
+        for (int j = tid; j < na; j += kBlock) a.cdf[j] = s_ang[j];
+
+    // ---- 4. inverse table ----------------------------------------------
+    const int nc = a.n_cdf;
+    for (int i = tid; i < nc; i += kBlock) {
+        const double u = (double)i / (double)(nc - 1);
+        int l = 0, r = na;                 // first j with F_j >= u
+        while (l < r) {
+            const int mid = (l + r) >> 1;
+            if (s_ang[mid] < u) l = mid + 1;
+            else r = mid;
+        }
+        l = min(l, na - 1);                // u <= 1 = F at pi, so only rounding could get here
+        double th = 0.0;
+        if (l > 0) {
+            const int j = l;
+            const double th_j = (double)j * dth, th_p = (double)(j - 1) * dth;
+            th = th_p + (u - s_ang[j - 1]) / (s_ang[j] - s_ang[j - 1]) * (th_j - th_p);
+        }
+        const double sh = sin(0.5 * th);
+        a.inv_cdf[i] = (float)(2.0 * sh * sh);
+    }
+}
+
+// Per-device scratch for the four scalar results (allocated once, kept).
+std::mutex g_scratch_mu;
+double *g_scratch[64] = {nullptr};
+
+}  // namespace
+}  // namespace mcmie
+
+extern "C" int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void *stream)
+{
+    using namespace mcmie;
+    clear_error();
+    if (!spec || !table) return fail(MC_EINVAL, "mie_table_build: null spec or table");
+    const mie_spec_t s = *spec;
+    if (!(s.n_medium > 0) || !(s.m_re > 0) || !(s.m_im >= 0) || !(s.diameter_um > 0) ||
+        !(s.wavelength_nm > 0) || !std::isfinite(s.n_medium * s.m_re * s.m_im * s.diameter_um *
+                                                   s.wavelength_nm))
+        return fail(MC_EINVAL, "mie_table_build: indices, diameter and wavelength must be finite, "
+                               "positive (m_im >= 0)");
+    if (s.n_angles < 3 || s.n_angles > MC_MAX_N_ANGLES)
+        return fail(MC_EINVAL, "mie_table_build: n_angles %d outside 3..%d", s.n_angles, MC_MAX_N_ANGLES);
+    if (s.n_cdf < 2 || s.n_cdf > MC_MAX_N_CDF)
+        return fail(MC_EINVAL, "mie_table_build: n_cdf %d outside 2..%d", s.n_cdf, MC_MAX_N_CDF);
+    if (!table->inv_cdf) return fail(MC_EINVAL, "mie_table_build: inv_cdf buffer is required");
+
+    // Parameter processing (Sec. 3.1.1): x = pi d n_med / lambda0 (Eq. 3 with
+    // the wavelength in the medium), m relative to the medium (Eq. 4).
+    const double x = M_PI * s.diameter_um * 1e3 * s.n_medium / s.wavelength_nm;
+    const double m_re = s.m_re / s.n_medium, m_im = s.m_im / s.n_medium;
+    const double mx_abs = x * std::hypot(m_re, m_im);
+    if (!(x >= 1e-6)) return fail(MC_EINVAL, "mie_table_build: size parameter %g below 1e-6", x);
+    const int n_terms = (int)std::lround(x + 4.0 * std::cbrt(x) + 2.0);   // Wiscombe 1980
+    if (n_terms > MC_MAX_TERMS)
+        return fail(MC_EINVAL, "mie_table_build: %d series terms exceed %d (x = %g)", n_terms,
+                    MC_MAX_TERMS, x);
+    if (table->coef && table->coef_capacity < n_terms)
+        return fail(MC_EINVAL, "mie_table_build: coef holds %d terms, %d needed", table->coef_capacity,
+                    n_terms);
+    // Downward start: the start error decays slowly across the turning point
+    // n ~ |mx|, whose width grows like |mx|^(1/3).
+    const int n_start = (int)std::ceil(std::max((double)n_terms, mx_abs)) + 16 +
+                        (int)std::ceil(8.0 * std::cbrt(mx_abs));
+
+    int dev = 0;
+    MC_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(MC_EDEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipMalloc(&p, 8 * sizeof(double)) != hipSuccess)
+            return fail(MC_ENOMEM, "mie_table_build: scratch allocation failed");
+        g_scratch[dev] = (double *)p;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    MieArgs args{x, m_re, m_im, n_terms, n_start, s.n_angles, s.n_cdf,
+                 table->inv_cdf, table->phase, table->cdf, table->coef, g_scratch[dev]};
+    hipLaunchKernelGGL(mie_table_kernel, dim3(1), dim3(kBlock), 0, st, args);
+    MC_HIP_CHECK(hipGetLastError());
+    double res[4];
+    MC_HIP_CHECK(hipMemcpyAsync(res, g_scratch[dev], sizeof res, hipMemcpyDeviceToHost, st));
+    MC_HIP_CHECK(hipStreamSynchronize(st));
+
+    const double geo_mm2 = M_PI * (s.diameter_um * 1e-3) * (s.diameter_um * 1e-3) / 4.0;   // Eq. 14
+    table->x = x;
+    table->m_rel_re = m_re;
+    table->m_rel_im = m_im;
+    table->q_ext = res[0];
+    table->q_sca = res[1];
+    table->q_abs = res[0] - res[1];
+    table->g = res[2];
+    table->sigma_ext_mm2 = res[0] * geo_mm2;
+    table->sigma_sca_mm2 = res[1] * geo_mm2;
+    table->sigma_abs_mm2 = (res[0] - res[1]) * geo_mm2;
+    table->n_terms = n_terms;
+    table->n_cdf = s.n_cdf;
+    return MC_OK;
+}

@@ -1,0 +1,536 @@
+// The photon walk of Sec. 3.1.3 on gfx950.
+//
+// Each lane carries one photon at a time in registers (position, direction,
+// weight, path length, scatter count, step) and runs the walk one step per
+// loop trip.  When a lane's photon ends it takes the next photon id from its
+// wave's current id range; a wave claims ranges of `chunk` ids from a global
+// counter with one atomic, so lanes stay busy until the budget is spent and
+// the work counter sees one atomic per chunk rather than per photon.
+//
+// One step: a Philox4x32-10 block (counter = step, instance, id_lo, id_hi;
+// key = seed) gives four uniforms u0..u3; the free path s = -ln(u0)/mu_ext
+// (Eq. 15) is compared with the distance to the nearest wall.  Reaching the
+// wall first, the photon moves there and is reflected with the unpolarised
+// Fresnel reflectance (u3) or leaves and is tallied.  Otherwise it interacts:
+// the weight update of Eq. 16 (implicit capture), Russian roulette (u3), and
+// a new direction at the polar angle read from the LDS-resident inverse CDF
+// (u1, direct index and linear interpolation of v = 1 - cos(theta)) or from
+// Henyey-Greenstein (Eq. 11), with azimuth 2 pi u2, built in the orthonormal
+// basis of Duff et al. 2017 around the old direction.
+//
+// Transport runs in FP32; tallies accumulate in FP64 (global atomics for the
+// images, LDS atomics per block for the scalars, flushed once per block).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace mcmie {
+namespace {
+
+constexpr float kInf = __builtin_huge_valf();
+
+struct WalkArgs {
+    float size[3];
+    float neg_ln2_over_mu;    // s = log2(u0) * neg_ln2_over_mu  (= -ln(u0) / mu_ext)
+    float albedo, absorb;     // albedo and 1 - albedo
+    float n21, n12sq;         // n_out / n_med and (n_med / n_out)^2
+    float n12;                // n_med / n_out (exit refraction, records only)
+    int matched;              // n_out == n_med: no Fresnel term
+    float pos0[3], dir0[3], w0;
+    float roulette_w, roulette_p, inv_roulette_p;
+    int phase, n_cdf;
+    const float *inv_cdf;
+    float hg_a, hg_b, hg_c, hg_d;   // 1 + g, 2g, 1 - g^2, 1 - g
+    uint32_t key0, key1, instance, max_steps;
+    uint64_t n_photons, photon_offset;
+    uint32_t chunk;
+    uint32_t flags;
+    int side_nx, side_ny, trans_nx, trans_ny;
+    double *side, *trans, *side_w2, *trans_w2, *scalars;
+    int32_t *rec_i;
+    float *rec_f;
+    uint64_t rec_rows, record_stride;
+};
+
+// Pixel = floor(coord / size * n), clamped to the image (IEEE division, so a
+// coordinate on a pixel edge lands where the FP64 definition puts it).
+__device__ __forceinline__ int pixel(float coord, float size, int n)
+{
+    const int i = (int)floorf(coord / size * (float)n);
+    return min(max(i, 0), n - 1);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int PHASE>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void walk_kernel(WalkArgs a)
+{
+    extern __shared__ float s_table[];          // n_cdf floats (MIE), then 16 doubles
+    double *s_scal = (double *)(s_table + ((a.n_cdf + 1) & ~1));
+
+    if (PHASE == MC_PHASE_MIE)
+        for (int i = threadIdx.x; i < a.n_cdf; i += blockDim.x) s_table[i] = a.inv_cdf[i];
+    if (threadIdx.x < MC_N_SCALARS) s_scal[threadIdx.x] = 0.0;
+    __syncthreads();
+
+    const int lane = __lane_id();
+    unsigned long long *work = (unsigned long long *)(a.scalars + MC_S_WORK);
+    const float tab_scale = (float)(a.n_cdf - 1);
+    const int tab_last = a.n_cdf - 2;
+
+    // Wave-uniform id range [next, end) and exhaustion flag.
+    uint64_t next = 0, end = 0;
+    bool exhausted = false;
+
+    // Lane state.
+    bool alive = false;
+    uint64_t id = 0;
+    float px = 0.f, py = 0.f, pz = 0.f, dx = 0.f, dy = 0.f, dz = 1.f;
+    float w = 0.f, L = 0.f, A = 0.f;
+    uint32_t k = 0, step = 0;
+    // Lane accumulators.
+    double acc_abs = 0.0;
+    uint32_t acc_events = 0, acc_steps = 0, acc_refl = 0, acc_photons = 0;
+
+    for (;;) {
+        // ---- refill lanes whose photon has ended -------------------------
+        const uint64_t need = __ballot(!alive);
+        if (need) {
+            if (next == end && !exhausted) {
+                unsigned long long base = 0;
+                const int leader = __ffsll((unsigned long long)need) - 1;
+                if (lane == leader) base = atomicAdd(work, (unsigned long long)a.chunk);
+                base = __shfl(base, leader, 64);
+                if (base >= a.n_photons) {
+                    exhausted = true;
+                } else {
+                    next = base;
+                    end = min((uint64_t)base + a.chunk, a.n_photons);
+                }
+            }
+            const uint64_t avail = end - next;
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            const uint32_t cnt = __popcll(need);
+            if (!alive && rank < avail) {
+                id = a.photon_offset + next + rank;
+                alive = true;
+                px = a.pos0[0]; py = a.pos0[1]; pz = a.pos0[2];
+                dx = a.dir0[0]; dy = a.dir0[1]; dz = a.dir0[2];
+                w = a.w0; L = 0.f; A = 0.f; k = 0; step = 0;
+            }
+            next += min((uint64_t)cnt, avail);
+        }
+        if (__ballot(alive) == 0) break;
+        if (!alive) continue;
+
+        // ---- one step -----------------------------------------------------
+        const Block4 r = philox4x32_10(step, a.instance, (uint32_t)id, (uint32_t)(id >> 32), a.key0, a.key1);
+        const float u0 = uniform01(r.r0), u1 = uniform01(r.r1);
+        const float u2 = uniform01(r.r2), u3 = uniform01(r.r3);
+        const float s = __builtin_amdgcn_logf(u0) * a.neg_ln2_over_mu;     // Eq. 15
+
+        // Nearest wall along the direction (ties go to the lower axis).
+        float tx = (dx > 0.f ? a.size[0] - px : -px) * __builtin_amdgcn_rcpf(dx);
+        float ty = (dy > 0.f ? a.size[1] - py : -py) * __builtin_amdgcn_rcpf(dy);
+        float tz = (dz > 0.f ? a.size[2] - pz : -pz) * __builtin_amdgcn_rcpf(dz);
+        tx = dx == 0.f ? kInf : fmaxf(tx, 0.f);
+        ty = dy == 0.f ? kInf : fmaxf(ty, 0.f);
+        tz = dz == 0.f ? kInf : fmaxf(tz, 0.f);
+        float db = tx;
+        int axis = 0;
+        if (ty < db) { db = ty; axis = 1; }
+        if (tz < db) { db = tz; axis = 2; }
+
+        int end_cause = -1;     // -1 still walking, 0 exit, 1 roulette, 2 cap
+        int face = -1;
+        ++step;
+        if (s >= db) {
+            // Boundary: move to the wall, then reflect or leave.
+            px = fmaf(db, dx, px); py = fmaf(db, dy, py); pz = fmaf(db, dz, pz);
+            L += db;
+            const float da = axis == 0 ? dx : (axis == 1 ? dy : dz);
+            const float wall = da > 0.f ? (axis == 0 ? a.size[0] : (axis == 1 ? a.size[1] : a.size[2])) : 0.f;
+            if (axis == 0) px = wall; else if (axis == 1) py = wall; else pz = wall;
+            float R = 0.f;
+            if (!a.matched) {
+                const float ci = fabsf(da);
+                const float st2 = a.n12sq * fmaf(-ci, ci, 1.f);
+                if (st2 >= 1.f) {
+                    R = 1.f;
+                } else {
+                    const float ct = __builtin_amdgcn_sqrtf(1.f - st2);
+                    const float rs = (ci - a.n21 * ct) * __builtin_amdgcn_rcpf(ci + a.n21 * ct);
+                    const float rp = (a.n21 * ci - ct) * __builtin_amdgcn_rcpf(a.n21 * ci + ct);
+                    R = 0.5f * fmaf(rs, rs, rp * rp);
+                }
+            }
+            if (u3 < R) {
+                if (axis == 0) dx = -dx; else if (axis == 1) dy = -dy; else dz = -dz;
+                ++acc_refl;
+            } else {
+                end_cause = 0;
+                face = 2 * axis + (da > 0.f ? 1 : 0);
+            }
+        } else {
+            // Interaction: move, count, absorb (Eq. 16), roulette, scatter.
+            px = fmaf(s, dx, px); py = fmaf(s, dy, py); pz = fmaf(s, dz, pz);
+            L += s;
+            ++k;
+            A = fmaf(w, a.absorb, A);
+            w *= a.albedo;
+            if (w < a.roulette_w) {
+                if (u3 < a.roulette_p) {
+                    const float wn = w * a.inv_roulette_p;
+                    atomicAdd(&s_scal[MC_S_ROULETTE_NET], (double)(wn - w));
+                    w = wn;
+                } else {
+                    atomicAdd(&s_scal[MC_S_ROULETTE_NET], -(double)w);
+                    atomicAdd(&s_scal[MC_S_ROULETTE_KILLS], 1.0);
+                    w = 0.f;
+                    end_cause = 1;
+                }
+            }
+            if (end_cause < 0) {
+                float v;
+                if (PHASE == MC_PHASE_MIE) {
+                    const float t = u1 * tab_scale;
+                    const int i = min((int)t, tab_last);
+                    const float f = t - (float)i;
+                    const float t0 = s_table[i], t1 = s_table[i + 1];
+                    v = fmaf(f, t1 - t0, t0);
+                } else {
+                    const float D = fmaf(-a.hg_b, u1, a.hg_a);
+                    const float rD = __builtin_amdgcn_rcpf(D);
+                    v = a.hg_d * u1 * fmaf(a.hg_c, rD, a.hg_d) * rD;
+                }
+                const float ct = 1.f - v;
+                const float st = __builtin_amdgcn_sqrtf(fmaxf(v * (2.f - v), 0.f));
+                const float cp = __builtin_amdgcn_cosf(u2);        // cos(2 pi u2)
+                const float sp = __builtin_amdgcn_sinf(u2);        // sin(2 pi u2)
+                // Orthonormal basis around d (Duff et al. 2017).
+                const float sg = copysignf(1.f, dz);
+                const float ia = -__builtin_amdgcn_rcpf(sg + dz);
+                const float b = dx * dy * ia;
+                const float e1x = fmaf(sg * dx * dx, ia, 1.f), e1y = sg * b, e1z = -sg * dx;
+                const float e2x = b, e2y = fmaf(dy * dy, ia, sg), e2z = -dy;
+                const float qx = fmaf(cp, e1x, sp * e2x), qy = fmaf(cp, e1y, sp * e2y),
+                            qz = fmaf(cp, e1z, sp * e2z);
+                float nx = fmaf(ct, dx, st * qx), ny = fmaf(ct, dy, st * qy), nz = fmaf(ct, dz, st * qz);
+                const float inv = __builtin_amdgcn_rsqf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
+                dx = nx * inv; dy = ny * inv; dz = nz * inv;
+            }
+        }
+        if (end_cause < 0 && step >= a.max_steps) {
+            end_cause = 2;
+            atomicAdd(&s_scal[MC_S_CAPPED_W], (double)w);
+            atomicAdd(&s_scal[MC_S_CAPPED], 1.0);
+        }
+        if (end_cause >= 0) {
+            // ---- photon ends: tallies and optional record ---------------
+            if (end_cause == 0) {
+                atomicAdd(&s_scal[MC_S_FACE + face], (double)w);
+                if (face == 1) {
+                    const size_t at = (size_t)pixel(py, a.size[1], a.side_ny) * a.side_nx +
+                                      pixel(pz, a.size[2], a.side_nx);
+                    atomicAdd(&a.side[at], (double)w);
+                    if (a.flags & MC_SIGMA) atomicAdd(&a.side_w2[at], (double)w * (double)w);
+                } else if (face == 5) {
+                    const size_t at = (size_t)pixel(py, a.size[1], a.trans_ny) * a.trans_nx +
+                                      pixel(px, a.size[0], a.trans_nx);
+                    atomicAdd(&a.trans[at], (double)w);
+                    if (a.flags & MC_SIGMA) atomicAdd(&a.trans_w2[at], (double)w * (double)w);
+                }
+            }
+            acc_abs += (double)A;
+            acc_events += k;
+            acc_steps += step;
+            ++acc_photons;
+            if (a.flags & MC_RECORD) {
+                const uint64_t rel = id - a.photon_offset;
+                if (rel % a.record_stride == 0) {
+                    const uint64_t row = rel / a.record_stride;
+                    if (row < a.rec_rows) {
+                        float ox = dx, oy = dy, oz = dz;
+                        if (end_cause == 0 && !a.matched) {
+                            // Refracted direction outside the wall (Snell).
+                            ox *= a.n12; oy *= a.n12; oz *= a.n12;
+                            const float t2 = (axis == 0 ? oy * oy + oz * oz
+                                                        : (axis == 1 ? ox * ox + oz * oz : ox * ox + oy * oy));
+                            const float on = copysignf(sqrtf(fmaxf(1.f - t2, 0.f)),
+                                                       axis == 0 ? dx : (axis == 1 ? dy : dz));
+                            if (axis == 0) ox = on; else if (axis == 1) oy = on; else oz = on;
+                        }
+                        const uint64_t n = a.rec_rows;
+                        a.rec_i[MC_REC_I_FACE * n + row] = face;
+                        a.rec_i[MC_REC_I_CAUSE * n + row] = end_cause;
+                        a.rec_i[MC_REC_I_K * n + row] = (int32_t)k;
+                        a.rec_i[MC_REC_I_STEPS * n + row] = (int32_t)step;
+                        a.rec_f[(MC_REC_F_POS + 0) * n + row] = px;
+                        a.rec_f[(MC_REC_F_POS + 1) * n + row] = py;
+                        a.rec_f[(MC_REC_F_POS + 2) * n + row] = pz;
+                        a.rec_f[(MC_REC_F_DIR + 0) * n + row] = ox;
+                        a.rec_f[(MC_REC_F_DIR + 1) * n + row] = oy;
+                        a.rec_f[(MC_REC_F_DIR + 2) * n + row] = oz;
+                        a.rec_f[MC_REC_F_W * n + row] = w;
+                        a.rec_f[MC_REC_F_L * n + row] = L;
+                        a.rec_f[MC_REC_F_A * n + row] = A;
+                    }
+                }
+            }
+            alive = false;
+        }
+    }
+
+    // ---- block-level flush of the scalar tallies ----------------------------
+    const double wabs = wave_sum(acc_abs);
+    const uint32_t wev = wave_sum(acc_events), wst = wave_sum(acc_steps), wrf = wave_sum(acc_refl),
+                   wph = wave_sum(acc_photons);
+    if (lane == 0) {
+        atomicAdd(&s_scal[MC_S_ABSORBED], wabs);
+        atomicAdd(&s_scal[MC_S_EVENTS], (double)wev);
+        atomicAdd(&s_scal[MC_S_STEPS], (double)wst);
+        atomicAdd(&s_scal[MC_S_REFLECTIONS], (double)wrf);
+        atomicAdd(&s_scal[MC_S_PHOTONS], (double)wph);
+    }
+    __syncthreads();
+    if (threadIdx.x < MC_S_WORK) {
+        const double v = s_scal[threadIdx.x];
+        if (v != 0.0) atomicAdd(&a.scalars[threadIdx.x], v);
+    }
+}
+
+// Zero the outputs (unless accumulating) and always reset the work counter.
+__global__ void init_kernel(double *side, size_t n_side, double *trans, size_t n_trans, double *side_w2,
+                            double *trans_w2, double *scalars, int32_t *rec_i, float *rec_f, size_t n_rec,
+                            int zero_all)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t0 == 0) ((unsigned long long *)scalars)[MC_S_WORK] = 0ull;
+    if (!zero_all) return;
+    for (size_t i = t0; i < n_side; i += stride) {
+        side[i] = 0.0;
+        if (side_w2) side_w2[i] = 0.0;
+    }
+    for (size_t i = t0; i < n_trans; i += stride) {
+        trans[i] = 0.0;
+        if (trans_w2) trans_w2[i] = 0.0;
+    }
+    if (t0 < MC_S_WORK) scalars[t0] = 0.0;
+    for (size_t i = t0; i < (size_t)MC_REC_I_N * n_rec; i += stride) rec_i[i] = (i / n_rec == MC_REC_I_FACE) ? -1 : 0;
+    for (size_t i = t0; i < (size_t)MC_REC_F_N * n_rec; i += stride) rec_f[i] = 0.f;
+}
+
+__global__ void philox_blocks_kernel(uint32_t k0, uint32_t k1, uint32_t instance, const uint64_t *ids,
+                                     uint64_t n_ids, uint32_t step0, uint32_t n_steps, uint32_t *out)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_ids * (uint64_t)n_steps) return;
+    const uint64_t i = t / n_steps;
+    const uint32_t st = step0 + (uint32_t)(t % n_steps);
+    const uint64_t id = ids[i];
+    const Block4 r = philox4x32_10(st, instance, (uint32_t)id, (uint32_t)(id >> 32), k0, k1);
+    out[4 * t + 0] = r.r0;
+    out[4 * t + 1] = r.r1;
+    out[4 * t + 2] = r.r2;
+    out[4 * t + 3] = r.r3;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+}  // namespace mcmie
+
+extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
+                           const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,
+                           void *stream)
+{
+    using namespace mcmie;
+    clear_error();
+    if (!medium || !source || !geometry || !detector || !run || !tally)
+        return fail(MC_EINVAL, "mc_simulate: null argument");
+    const mc_medium_t m = *medium;
+    const mc_source_t src = *source;
+    const mc_geometry_t geo = *geometry;
+    const mc_detector_t det = *detector;
+    const mc_run_t rn = *run;
+    const mc_tally_t t = *tally;
+
+    // ---- parameter checks (Sec. 3.1.1) ----
+    for (int i = 0; i < 3; ++i)
+        if (!finite_pos(geo.size_mm[i])) return fail(MC_EINVAL, "mc_simulate: size_mm[%d] must be > 0", i);
+    if (!finite_pos(geo.n_medium) || !finite_pos(geo.n_outside))
+        return fail(MC_EINVAL, "mc_simulate: refractive indices must be > 0");
+    if (!(m.tau >= 0.0) || !std::isfinite(m.tau)) return fail(MC_EINVAL, "mc_simulate: tau must be >= 0");
+    if (!(m.albedo >= 0.0 && m.albedo <= 1.0)) return fail(MC_EINVAL, "mc_simulate: albedo must be in [0, 1]");
+    if (m.phase == MC_PHASE_MIE) {
+        if (m.n_cdf < 2 || m.n_cdf > MC_MAX_N_CDF)
+            return fail(MC_EINVAL, "mc_simulate: n_cdf %d outside 2..%d", m.n_cdf, MC_MAX_N_CDF);
+        if (!m.inv_cdf) return fail(MC_EINVAL, "mc_simulate: inv_cdf is required for MC_PHASE_MIE");
+    } else if (m.phase == MC_PHASE_HG) {
+        if (!(m.g > -1.0 && m.g < 1.0)) return fail(MC_EINVAL, "mc_simulate: HG g must be in (-1, 1)");
+    } else {
+        return fail(MC_EINVAL, "mc_simulate: unknown phase %d", m.phase);
+    }
+    if (!(src.pos_mm[2] == 0.0) || !(src.pos_mm[0] >= 0.0 && src.pos_mm[0] <= geo.size_mm[0]) ||
+        !(src.pos_mm[1] >= 0.0 && src.pos_mm[1] <= geo.size_mm[1]))
+        return fail(MC_EINVAL, "mc_simulate: the source must lie on the z = 0 face");
+    const double dl = std::sqrt(src.dir[0] * src.dir[0] + src.dir[1] * src.dir[1] + src.dir[2] * src.dir[2]);
+    if (!(dl > 0.0) || !std::isfinite(dl) || !(src.dir[2] > 0.0))
+        return fail(MC_EINVAL, "mc_simulate: the source direction must point into the cuboid (dir[2] > 0)");
+    if (det.side_nx < 1 || det.side_ny < 1 || det.trans_nx < 1 || det.trans_ny < 1)
+        return fail(MC_EINVAL, "mc_simulate: image dimensions must be >= 1");
+    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD))
+        return fail(MC_EINVAL, "mc_simulate: unknown detector flags 0x%x", det.flags);
+    if (!t.side || !t.trans || !t.scalars) return fail(MC_EINVAL, "mc_simulate: side, trans and scalars are required");
+    if ((det.flags & MC_SIGMA) && (!t.side_w2 || !t.trans_w2))
+        return fail(MC_EINVAL, "mc_simulate: MC_SIGMA needs side_w2 and trans_w2");
+    if ((det.flags & MC_RECORD) && (!t.rec_i || !t.rec_f || rn.record_stride < 1))
+        return fail(MC_EINVAL, "mc_simulate: MC_RECORD needs rec_i, rec_f and record_stride >= 1");
+    if (rn.max_steps < 1) return fail(MC_EINVAL, "mc_simulate: max_steps must be >= 1");
+    if (!(rn.roulette_w >= 0.0) || !(rn.roulette_p > 0.0 && rn.roulette_p <= 1.0))
+        return fail(MC_EINVAL, "mc_simulate: roulette_w >= 0 and roulette_p in (0, 1] required");
+    if (rn.photon_offset > UINT64_MAX - rn.n_photons) return fail(MC_EINVAL, "mc_simulate: photon ids overflow");
+    if (rn.block_size != 0 && (rn.block_size < 64 || rn.block_size > 1024 || rn.block_size % 64))
+        return fail(MC_EINVAL, "mc_simulate: block_size must be a multiple of 64 in 64..1024");
+    if (rn.grid_blocks < 0) return fail(MC_EINVAL, "mc_simulate: grid_blocks must be >= 0");
+
+    // ---- derived coefficients (Eq. 1, Eq. 16) and the entry beam ----
+    WalkArgs a{};
+    for (int i = 0; i < 3; ++i) a.size[i] = (float)geo.size_mm[i];
+    const double mu_t = m.tau / geo.size_mm[2];
+    a.neg_ln2_over_mu = mu_t > 0.0 ? (float)(-M_LN2 / mu_t) : -__builtin_huge_valf();
+    a.albedo = (float)m.albedo;
+    a.absorb = (float)(1.0 - m.albedo);
+    a.matched = geo.n_outside == geo.n_medium;
+    a.n21 = (float)(geo.n_outside / geo.n_medium);
+    a.n12 = (float)(geo.n_medium / geo.n_outside);
+    a.n12sq = (float)((geo.n_medium / geo.n_outside) * (geo.n_medium / geo.n_outside));
+    // The beam refracts into the medium at the z = 0 face and keeps 1 - R.
+    double din[3] = {src.dir[0] / dl, src.dir[1] / dl, src.dir[2] / dl};
+    const double eta = geo.n_outside / geo.n_medium;
+    double d0[3] = {eta * din[0], eta * din[1], 0.0};
+    d0[2] = std::sqrt(std::max(0.0, 1.0 - d0[0] * d0[0] - d0[1] * d0[1]));
+    double R0 = 0.0;
+    if (!a.matched) {
+        const double n1 = geo.n_outside, n2 = geo.n_medium, ci = din[2];
+        const double si = std::sqrt(std::max(0.0, 1.0 - ci * ci)), st = n1 / n2 * si;
+        if (st >= 1.0) {
+            R0 = 1.0;
+        } else {
+            const double ct = std::sqrt(1.0 - st * st);
+            const double rs = (n1 * ci - n2 * ct) / (n1 * ci + n2 * ct);
+            const double rp = (n2 * ci - n1 * ct) / (n2 * ci + n1 * ct);
+            R0 = 0.5 * (rs * rs + rp * rp);
+        }
+    }
+    for (int i = 0; i < 3; ++i) {
+        a.pos0[i] = (float)src.pos_mm[i];
+        a.dir0[i] = (float)d0[i];
+    }
+    a.w0 = (float)(1.0 - R0);
+    a.roulette_w = (float)rn.roulette_w;
+    a.roulette_p = (float)rn.roulette_p;
+    a.inv_roulette_p = (float)(1.0 / rn.roulette_p);
+    a.phase = m.phase;
+    a.n_cdf = m.phase == MC_PHASE_MIE ? m.n_cdf : 0;
+    a.inv_cdf = m.inv_cdf;
+    a.hg_a = (float)(1.0 + m.g);
+    a.hg_b = (float)(2.0 * m.g);
+    a.hg_c = (float)(1.0 - m.g * m.g);
+    a.hg_d = (float)(1.0 - m.g);
+    a.key0 = (uint32_t)rn.seed;
+    a.key1 = (uint32_t)(rn.seed >> 32);
+    a.instance = rn.instance;
+    a.max_steps = rn.max_steps;
+    a.n_photons = rn.n_photons;
+    a.photon_offset = rn.photon_offset;
+    a.flags = det.flags;
+    a.side_nx = det.side_nx; a.side_ny = det.side_ny;
+    a.trans_nx = det.trans_nx; a.trans_ny = det.trans_ny;
+    a.side = t.side; a.trans = t.trans;
+    a.side_w2 = (det.flags & MC_SIGMA) ? t.side_w2 : nullptr;
+    a.trans_w2 = (det.flags & MC_SIGMA) ? t.trans_w2 : nullptr;
+    a.scalars = t.scalars;
+    a.rec_i = t.rec_i; a.rec_f = t.rec_f;
+    a.rec_rows = (det.flags & MC_RECORD) ? t.rec_rows : 0;
+    a.record_stride = rn.record_stride >= 1 ? rn.record_stride : 1;
+
+    // ---- launch shape: enough resident waves to fill every CU ----
+    int cus = 0;
+    if (int rc = device_cu_count(&cus)) return rc;
+    const size_t lds = (size_t)((a.n_cdf + 1) & ~1) * sizeof(float) + MC_N_SCALARS * sizeof(double);
+    const size_t lds_per_cu = 160 * 1024;
+    int blocks_per_cu = (int)std::min<size_t>(lds_per_cu / lds, 32);
+    int block = rn.block_size;
+    if (block == 0) {
+        const int waves = (32 + blocks_per_cu - 1) / blocks_per_cu;       // 32 waves per CU
+        block = std::min(1024, std::max(256, 64 * waves));
+    }
+    blocks_per_cu = std::max(1, std::min(blocks_per_cu, 32 / (block / 64)));
+    int grid = rn.grid_blocks > 0 ? rn.grid_blocks : cus * blocks_per_cu;
+    const uint64_t waves_total = (uint64_t)grid * (block / 64);
+    uint64_t chunk = rn.n_photons / std::max<uint64_t>(1, waves_total * 16);
+    chunk = std::max<uint64_t>(64, std::min<uint64_t>(1024, (chunk + 63) / 64 * 64));
+    a.chunk = (uint32_t)chunk;
+
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n_side = (size_t)det.side_nx * det.side_ny, n_trans = (size_t)det.trans_nx * det.trans_ny;
+    const int zero_all = (det.flags & MC_ACCUMULATE) ? 0 : 1;
+    hipLaunchKernelGGL(init_kernel, dim3(256), dim3(256), 0, st, t.side, n_side, t.trans, n_trans, a.side_w2,
+                       a.trans_w2, t.scalars, a.rec_i, a.rec_f, (size_t)a.rec_rows, zero_all);
+    MC_HIP_CHECK(hipGetLastError());
+    if (rn.n_photons == 0) return MC_OK;
+    if (m.phase == MC_PHASE_MIE) {
+        MC_HIP_CHECK(hipFuncSetAttribute((const void *)walk_kernel<MC_PHASE_MIE>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(walk_kernel<MC_PHASE_MIE>, dim3(grid), dim3(block), lds, st, a);
+    } else {
+        MC_HIP_CHECK(hipFuncSetAttribute((const void *)walk_kernel<MC_PHASE_HG>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(walk_kernel<MC_PHASE_HG>, dim3(grid), dim3(block), lds, st, a);
+    }
+    MC_HIP_CHECK(hipGetLastError());
+    return MC_OK;
+}
+
+extern "C" int mc_grad(const mc_medium_t *, const mc_source_t *, const mc_geometry_t *, const mc_detector_t *,
+                       const mc_run_t *, const double *, double *, void *)
+{
+    mcmie::clear_error();
+    return mcmie::fail(MC_EUNSUPPORTED, "mc_grad: the adjoint walk is not implemented in this build");
+}
+
+extern "C" int mc_philox_blocks(uint64_t seed, uint32_t instance, const uint64_t *ids, uint64_t n_ids,
+                                uint32_t step0, uint32_t n_steps, uint32_t *out, void *stream)
+{
+    using namespace mcmie;
+    clear_error();
+    if (n_ids == 0 || n_steps == 0) return MC_OK;
+    if (!ids || !out) return fail(MC_EINVAL, "mc_philox_blocks: null buffer");
+    if ((uint64_t)step0 + n_steps > (1ull << 32)) return fail(MC_EINVAL, "mc_philox_blocks: step range overflows");
+    const uint64_t total = n_ids * (uint64_t)n_steps;
+    if (total / n_steps != n_ids || total > (1ull << 40)) return fail(MC_EINVAL, "mc_philox_blocks: too many blocks");
+    const uint64_t grid = (total + 255) / 256;
+    hipLaunchKernelGGL(philox_blocks_kernel, dim3((uint32_t)grid), dim3(256), 0, (hipStream_t)stream,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), instance, ids, n_ids, step0, n_steps, out);
+    MC_HIP_CHECK(hipGetLastError());
+    return MC_OK;
+}

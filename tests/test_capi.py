@@ -1,0 +1,122 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/mcmie.h declares, and rejects invalid arguments with
+MC_EINVAL before any device work is enqueued."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcmie.h")
+
+
+def _lib_path():
+    import paper_2507_23189_amd._capi as cap
+    if not os.path.exists(cap.LIB_PATH):
+        from paper_2507_23189_amd import build
+        build.build()
+    return cap.LIB_PATH
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\([^;]*\)\s*;", text, flags=re.M)
+
+
+def test_header_declares_the_entry_points():
+    names = set(_declared_functions())
+    assert {"mie_table_build", "mc_simulate", "mc_grad", "mc_last_error", "mc_philox_blocks",
+            "mc_version"} <= names
+
+
+def test_library_exports_every_declared_symbol():
+    path = _lib_path()
+    L = C.CDLL(path)
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    assert set(_declared_functions()) <= exported
+
+
+def test_version_and_empty_error():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    assert mc.mc_version() == 100
+    assert mc.lib().mc_last_error() == b""
+
+
+def _valid_args():
+    import paper_2507_23189_amd as mc
+    import workloads as W
+    spec, med, src, geo, det, run = mc.args_from_workload(W.TINY.replace(phase=mc.MC_PHASE_HG), g=0.8)
+    return spec, med, src, geo, det, run
+
+
+@pytest.mark.parametrize("field,value", [
+    ("tau", -1.0), ("albedo", 1.5), ("g", 1.0), ("phase", 7),
+    ("src_z", 0.5), ("src_x", 11.0), ("dir_z", -1.0), ("size", 0.0), ("n_out", 0.0),
+    ("side_nx", 0), ("max_steps", 0), ("roulette_p", 0.0), ("block_size", 100), ("flags", 64),
+])
+def test_mc_simulate_rejects_invalid_arguments(field, value):
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, med, src, geo, det, run = _valid_args()
+    tal = mc._capi._TallyC()
+    tal.side = tal.trans = tal.scalars = 0x1000      # never dereferenced: validation fails first
+    if field in ("tau", "albedo", "g", "phase"):
+        setattr(med, field, value)
+    elif field == "src_z":
+        src.pos_mm[2] = value
+    elif field == "src_x":
+        src.pos_mm[0] = value
+    elif field == "dir_z":
+        src.dir[2] = value
+    elif field == "size":
+        geo.size_mm[1] = value
+    elif field == "n_out":
+        geo.n_outside = value
+    elif field in ("side_nx", "flags"):
+        setattr(det, field, value)
+    else:
+        setattr(run, field, value)
+    rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                              C.byref(tal), None)
+    assert rc == mc.MC_EINVAL
+    assert mc.lib().mc_last_error().startswith(b"mc_simulate")
+
+
+def test_mc_simulate_requires_tally_buffers():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, med, src, geo, det, run = _valid_args()
+    tal = mc._capi._TallyC()
+    rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                              C.byref(tal), None)
+    assert rc == mc.MC_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n_medium", 0.0), ("m_re", -1.0), ("m_im", -0.1), ("diameter_um", 0.0), ("wavelength_nm", float("nan")),
+    ("n_angles", 2), ("n_angles", 3002), ("n_cdf", 1), ("n_cdf", 16385), ("diameter_um", 500.0),
+])
+def test_mie_table_build_rejects_invalid_spec(field, value):
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, *_ = _valid_args()
+    setattr(spec, field, value)
+    t = mc._capi._MieTableC()
+    t.inv_cdf = 0x1000
+    rc = mc.lib().mie_table_build(C.byref(spec), C.byref(t), None)
+    assert rc == mc.MC_EINVAL
+    assert mc.lib().mc_last_error().startswith(b"mie_table_build")
+
+
+def test_mc_grad_reports_unsupported():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    out = (C.c_double * 3)()
+    assert mc.lib().mc_grad(None, None, None, None, None, None, out, None) == mc.MC_EUNSUPPORTED

@@ -1,0 +1,205 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars: Philox words bit-exact; Mie coefficients, efficiencies and phase table
+to FP64 rounding, inverse table to one FP32 ulp; per-photon trajectories
+(face, cause, scatter count, end position, direction, weight, path length)
+within 1e-4 for at least 99.9 % of photons; every image bin within 3 sigma of
+Monte Carlo noise at matched seeds; launch-shape and photon-range invariance
+bit-exact on records."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from _helpers import gpu_run, image_within_3sigma, oracle_rec, trajectory_match
+from oracle import mie, philox
+from oracle import walk as owalk
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mc():
+    import paper_2507_23189_amd as m
+    m.lib()
+    return m
+
+
+# ---------------------------------------------------------------- Philox
+
+def test_philox_words_bit_exact(mc, cuda_device):
+    torch = _torch()
+    rng = np.random.default_rng(11)
+    ids = np.concatenate([np.arange(5, dtype=np.uint64), rng.integers(0, 2**40, 27, dtype=np.uint64),
+                          np.array([2**32 - 1, 2**32, 2**63 + 7], dtype=np.uint64)])
+    for seed, inst, step0, nst in [(1234, 0, 0, 9), (2**40 + 99, 3, 1 << 20, 4), (0, 0, 2**32 - 3, 3)]:
+        ids_t = torch.tensor(ids.view(np.int64), device=cuda_device)
+        out = torch.empty(len(ids) * nst * 4, dtype=torch.int32, device=cuda_device)
+        mc.mc_philox_blocks(seed, inst, ids_t, step0, nst, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint32).reshape(len(ids), nst, 4)
+        for i, pid in enumerate(ids):
+            for s in range(nst):
+                ref = philox.step_block(seed, int(pid), step0 + s, instance=inst)
+                assert tuple(int(v) for v in got[i, s]) == ref, (seed, pid, step0 + s)
+
+
+# ------------------------------------------------------------- Mie table
+
+TABLE_CASES = [
+    dict(d=5.0, m_re=1.59, m_im=0.0, n_med=1.33, lam=532.0, na=1801, nc=4096),      # tiny workload
+    dict(d=5.0, m_re=1.59, m_im=0.0, n_med=1.33, lam=532.0, na=1801, nc=16384),     # paper scale
+    dict(d=5.0, m_re=1.594, m_im=0.00033, n_med=1.333, lam=532.0, na=3001, nc=4096),  # printed indices, 3000-point grid
+    dict(d=0.5, m_re=1.59, m_im=0.0, n_med=1.33, lam=532.0, na=1801, nc=4096),      # x ~ 3.9
+    dict(d=10.0, m_re=1.59, m_im=0.0, n_med=1.33, lam=532.0, na=1801, nc=2),        # x ~ 78.5, smallest table
+    dict(d=0.02, m_re=1.5, m_im=0.1, n_med=1.0, lam=532.0, na=3, nc=5),             # Rayleigh, smallest grid
+]
+
+
+@pytest.mark.parametrize("case", TABLE_CASES)
+def test_mie_table_parity(mc, cuda_device, case):
+    c = case
+    spec = mc.MieSpec(n_medium=c["n_med"], m_re=c["m_re"], m_im=c["m_im"], diameter_um=c["d"],
+                      wavelength_nm=c["lam"], n_angles=c["na"], n_cdf=c["nc"])
+    t = mc.mie_table_build(spec, cuda_device, phase=True, cdf=True, coef=True)
+    o = mie.build_table(c["d"], c["m_re"], c["m_im"], c["n_med"], c["lam"], c["na"], c["nc"])
+    assert t.x == pytest.approx(o.x, rel=1e-15)
+    assert t.n_terms == len(o.a)
+    coef = t.coef.cpu().numpy()
+    ga = coef[:, 0] + 1j * coef[:, 1]
+    gb = coef[:, 2] + 1j * coef[:, 3]
+    big = max(np.abs(o.a).max(), np.abs(o.b).max())
+    assert np.abs(ga - o.a).max() <= 1e-12 * big
+    assert np.abs(gb - o.b).max() <= 1e-12 * big
+    for name in ("q_ext", "q_sca", "g", "sigma_ext_mm2"):
+        assert getattr(t, name) == pytest.approx(getattr(o, name), rel=1e-11, abs=1e-300)
+    assert t.q_abs == pytest.approx(o.q_abs, abs=1e-11 * o.q_ext)
+    np.testing.assert_allclose(t.phase.cpu().numpy(), o.P, rtol=1e-10, atol=1e-14 * o.P.max())
+    np.testing.assert_allclose(t.cdf.cpu().numpy(), o.F, rtol=0, atol=1e-13)
+    inv = t.inv_cdf.cpu().numpy()
+    ref32 = o.v.astype(np.float32)
+    ulp = np.spacing(np.abs(ref32)).astype(np.float64)
+    assert np.all(np.abs(inv.astype(np.float64) - ref32.astype(np.float64)) <= ulp + 1e-30)
+
+
+# ------------------------------------------------------- trajectories, images
+
+def _oracle(w, records=True, ids=None, g=None):
+    return owalk.Walk(w, g=g).run(records=records, ids=ids)
+
+
+@pytest.mark.parametrize("phase", [W.PHASE_MIE, W.PHASE_HG])
+def test_tiny_workload_trajectories_and_images(mc, cuda_device, phase):
+    w = W.TINY.replace(phase=phase)
+    g = gpu_run(w, records=True)
+    o = _oracle(w, g=None if phase == W.PHASE_MIE else mie.table_from_workload(w).g)
+    ok = trajectory_match(g["rec"], oracle_rec(o), box=10.0)
+    assert ok.mean() >= 0.999, (ok.mean(), np.flatnonzero(~ok)[:10])
+    assert image_within_3sigma(g["side"], o.side, o.side_w2, w.n_photons).all()
+    assert image_within_3sigma(g["trans"], o.trans, o.trans_w2, w.n_photons).all()
+    gs, os_ = g["scalars"], o.scalars
+    assert gs[10] == w.n_photons
+    np.testing.assert_allclose(gs[:7], os_[:7], rtol=2e-3, atol=2.0)
+    assert abs(gs[9] - os_[9]) <= 1e-3 * os_[9]                 # scatter events
+    # Squared-weight images against the oracle too.
+    assert image_within_3sigma(g["side_w2"], o.side_w2, o.side_w2, w.n_photons).all()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(tau=4.0, n_cdf=16384, side_px=512, trans_px=512, n_photons=20000),
+    dict(tau=8.0, n_photons=20000, albedo=0.9),
+    dict(tau=6.0, albedo=0.5, roulette_w=0.01, n_photons=20000),          # roulette fires often
+    dict(tau=2.0, n_outside=1.33, n_photons=20000),                       # index-matched walls
+    dict(tau=3.0, n_photons=12345, side_px=3, trans_px=5, size_mm=(4.0, 7.0, 10.0),
+         src_pos_mm=(1.0, 2.0, 0.0), src_dir=(0.3, -0.2, 0.9)),            # ragged, oblique beam
+    dict(tau=8.0, max_steps=4, n_photons=5000),                            # step cap
+])
+def test_trajectory_parity_variants(mc, cuda_device, kw):
+    w = W.TINY.replace(**kw)
+    g = gpu_run(w, records=True)
+    o = _oracle(w)
+    ok = trajectory_match(g["rec"], oracle_rec(o), box=max(w.size_mm))
+    assert ok.mean() >= 0.999, (kw, ok.mean())
+    assert image_within_3sigma(g["side"], o.side, o.side_w2, w.n_photons, max_w=10.0).all()
+    assert image_within_3sigma(g["trans"], o.trans, o.trans_w2, w.n_photons, max_w=10.0).all()
+
+
+def test_full_size_sampled_trajectories(mc, cuda_device):
+    """Headline workload at full size, default launch shape: every 50 000th
+    photon is recorded and replayed one by one in the oracle."""
+    w = W.HEADLINE
+    stride = 50_000
+    g = gpu_run(w, records=True, record_stride=stride, sigma=False)
+    ids = np.arange(0, w.n_photons, stride, dtype=np.uint64)
+    o = _oracle(w, ids=ids)
+    ok = trajectory_match(g["rec"], oracle_rec(o), box=10.0)
+    assert ok.mean() >= 0.999, ok.mean()
+    s = g["scalars"]
+    assert s[10] == w.n_photons
+    # Energy bookkeeping at full size: start weight + roulette = exits + absorbed + capped.
+    w0 = 1.0 - ((1.0 - 1.33) / 2.33) ** 2
+    assert s[0:6].sum() + s[6] + s[8] == pytest.approx(w.n_photons * w0 + s[7], rel=1e-5)
+    # Events per photon agree with the oracle's sample within 4 sigma.
+    k = o.rec("k").astype(float)
+    assert abs(s[9] / s[10] - k.mean()) <= 4 * k.std() / math.sqrt(len(k))
+
+
+# ------------------------------------------------------------ invariances
+
+def test_launch_shape_and_photon_ranges_are_invariant(mc, cuda_device):
+    torch = _torch()
+    w = W.TINY.replace(tau=3.0, n_photons=30000)
+    a = gpu_run(w, records=True)
+    b = gpu_run(w, records=True, block_size=64, grid_blocks=7, table=a["table"])
+    for k in a["rec"]:
+        np.testing.assert_array_equal(a["rec"][k], b["rec"][k])
+    np.testing.assert_allclose(a["side"], b["side"], rtol=1e-12, atol=1e-12)
+    # Two photon ranges accumulated into one tally equal the single run.
+    t = a["tally"]
+    c1 = gpu_run(w, records=False, n_photons=11111, table=a["table"])
+    tal = c1["tally"]
+    gpu_run(w, records=False, n_photons=w.n_photons - 11111, photon_offset=11111, table=a["table"],
+            tally=tal, flags_extra=1)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(tal.side.cpu().numpy(), a["side"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(tal.trans.cpu().numpy(), a["trans"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(tal.scalars.cpu().numpy()[:15], a["scalars"][:15], rtol=1e-12, atol=1e-9)
+
+
+def test_zero_and_single_photon(mc, cuda_device):
+    w = W.TINY
+    z = gpu_run(w, n_photons=0, records=True)
+    assert np.all(z["side"] == 0) and np.all(z["trans"] == 0) and np.all(z["scalars"][:15] == 0)
+    one = gpu_run(w, n_photons=1, records=True)
+    o = _oracle(w.replace(n_photons=1))
+    assert trajectory_match(one["rec"], oracle_rec(o), box=10.0).all()
+    assert one["scalars"][10] == 1
+
+
+def test_gpu_physics_pins(mc, cuda_device):
+    # Beer-Lambert ballistic fraction and the pure absorber on the HIP path.
+    tau = 1.0
+    w = W.TINY.replace(tau=tau, n_outside=1.33, n_photons=200000)
+    g = gpu_run(w, records=True)
+    ball = (g["rec"]["k"] == 0) & (g["rec"]["face"] == 5)
+    p = math.exp(-tau)
+    assert abs(ball.sum() - w.n_photons * p) <= 4 * math.sqrt(w.n_photons * p * (1 - p))
+    wa = W.TINY.replace(tau=1.5, n_outside=1.33, albedo=0.0, roulette_w=0.0, n_photons=200000)
+    ga = gpu_run(wa)
+    assert ga["side"].sum() == 0.0
+    p = math.exp(-1.5)
+    assert abs(ga["trans"].sum() - wa.n_photons * p) <= 4 * math.sqrt(wa.n_photons * p * (1 - p))
+    # HG sampling: mean cosine of the first scatter is g (single-scatter setup).
+    big = 1e6
+    wh = W.TINY.replace(size_mm=(big, big, big), src_pos_mm=(big / 2, big / 2, 0.0), tau=big, max_steps=1,
+                        phase=W.PHASE_HG, n_photons=200000, roulette_w=0.0)
+    gh = gpu_run(wh, records=True, g=0.8668)
+    mu = gh["rec"]["dz"]
+    assert abs(mu.mean() - 0.8668) <= 4 * mu.std() / math.sqrt(len(mu))
