@@ -176,7 +176,7 @@ typedef struct {
     double *scalars;       /* MC_N_SCALARS doubles (required); slot MC_S_WORK is scratch */
     int32_t *rec_i;        /* MC_RECORD: MC_REC_I_N * rec_rows int32 */
     float *rec_f;          /* MC_RECORD: MC_REC_F_N * rec_rows float */
-    uint64_t rec_rows;     /* MC_RECORD: rows available; photons beyond are not recorded */
+    uint64_t rec_rows;     /* MC_RECORD: rows available (0: record nothing, buffers may be NULL) */
 } mc_tally_t;
 
 /*

@@ -18,8 +18,19 @@
 // Henyey-Greenstein (Eq. 11), with azimuth 2 pi u2, built in the orthonormal
 // basis of Duff et al. 2017 around the old direction.
 //
-// Transport runs in FP32; tallies accumulate in FP64 (global atomics for the
-// images, LDS atomics per block for the scalars, flushed once per block).
+// Transport runs in FP32; tallies accumulate in FP64.  Exits go through a
+// per-block LDS tally cache: a direct-mapped table of pixel ids (claimed with
+// an LDS compare-and-swap, first come first served) whose FP64 sums are
+// flushed to the images once per block.  The pencil beam sends every
+// unscattered photon to the same transmitted pixel, and same-address global
+// atomics serialise across the chip, so without the cache that one pixel
+// bounds the whole launch.  Pixels that miss the cache (slot held by another
+// pixel) fall back to a global atomic.  Exits are first queued per wave in
+// LDS and tallied 64 at a time by the whole wave, so the pixel arithmetic and
+// atomics run with full lanes instead of on the few lanes that exit in any
+// one step.  Scalar tallies use LDS atomics and lane accumulators, also
+// flushed once per block.  The kernel is specialised at compile time on the
+// phase function, the squared-weight tally and per-photon records.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,8 +41,6 @@
 
 namespace mcmie {
 namespace {
-
-constexpr float kInf = __builtin_huge_valf();
 
 struct WalkArgs {
     float size[3];
@@ -49,6 +58,8 @@ struct WalkArgs {
     uint64_t n_photons, photon_offset;
     uint32_t chunk;
     uint32_t flags;
+    int cache_bits;           // log2 of the tally-cache slots (0: no cache)
+    uint32_t n_side;          // pixels of the side image (cache key offset of the transmitted image)
     int side_nx, side_ny, trans_nx, trans_ny;
     double *side, *trans, *side_w2, *trans_w2, *scalars;
     int32_t *rec_i;
@@ -62,6 +73,26 @@ __device__ __forceinline__ int pixel(float coord, float size, int n)
 {
     const int i = (int)floorf(coord / size * (float)n);
     return min(max(i, 0), n - 1);
+}
+
+// Distance to the nearest wall along d and its axis (ties go to the lower
+// axis).  Per axis t = (L - p) / |d| moving up, p / |d| moving down; an axis
+// with d = 0 is never hit; t is clamped at 0 so a position that rounding left
+// a hair outside the box is taken back at once.
+__device__ __forceinline__ float wall_distance(float px, float py, float pz, float dx, float dy, float dz,
+                                               float Lx, float Ly, float Lz, int &axis)
+{
+    float tx = (dx > 0.f ? Lx - px : px) * __builtin_amdgcn_rcpf(fabsf(dx));
+    float ty = (dy > 0.f ? Ly - py : py) * __builtin_amdgcn_rcpf(fabsf(dy));
+    float tz = (dz > 0.f ? Lz - pz : pz) * __builtin_amdgcn_rcpf(fabsf(dz));
+    tx = dx == 0.f ? __builtin_huge_valf() : fmaxf(tx, 0.f);
+    ty = dy == 0.f ? __builtin_huge_valf() : fmaxf(ty, 0.f);
+    tz = dz == 0.f ? __builtin_huge_valf() : fmaxf(tz, 0.f);
+    float db = tx;
+    axis = 0;
+    if (ty < db) { db = ty; axis = 1; }
+    if (tz < db) { db = tz; axis = 2; }
+    return db;
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -78,24 +109,99 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
     return v;
 }
 
-template <int PHASE>
+constexpr int kQueue = 64;                 // queued image exits per wave
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;   // free tally-cache slot
+
+template <int PHASE, bool SIGMA, bool RECORD>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void walk_kernel(WalkArgs a)
 {
-    extern __shared__ float s_table[];          // n_cdf floats (MIE), then 16 doubles
-    double *s_scal = (double *)(s_table + ((a.n_cdf + 1) & ~1));
+    // LDS layout: inverse table (n_cdf floats, padded to 4), 16 scalar doubles,
+    // tally cache (slots doubles of weight, [SIGMA] slots doubles of squared
+    // weight, slots uint32 keys), per-wave exit queues (3 x kQueue floats).
+    extern __shared__ float s_table[];
+    double *s_scal = (double *)(s_table + ((a.n_cdf + 3) & ~3));
+    const int slots = a.cache_bits ? 1 << a.cache_bits : 0;
+    double *s_cw = s_scal + MC_N_SCALARS;
+    double *s_cw2 = s_cw + (SIGMA ? slots : 0);
+    uint32_t *s_key = (uint32_t *)(s_cw2 + slots);
+    float *s_queue = (float *)(s_key + slots);
 
     if (PHASE == MC_PHASE_MIE)
         for (int i = threadIdx.x; i < a.n_cdf; i += blockDim.x) s_table[i] = a.inv_cdf[i];
     if (threadIdx.x < MC_N_SCALARS) s_scal[threadIdx.x] = 0.0;
+    for (int i = threadIdx.x; i < slots; i += blockDim.x) {
+        s_cw[i] = 0.0;
+        if (SIGMA) s_cw2[i] = 0.0;
+        s_key[i] = kEmpty;
+    }
+    __syncthreads();
+    // Seed the cache with the pixel where unscattered photons leave (the
+    // hottest pixel of a pencil beam), so no other pixel can take its slot.
+    if (slots && threadIdx.x == 0) {
+        int ax;
+        const float db = wall_distance(a.pos0[0], a.pos0[1], a.pos0[2], a.dir0[0], a.dir0[1], a.dir0[2],
+                                       a.size[0], a.size[1], a.size[2], ax);
+        const float bx = fmaf(db, a.dir0[0], a.pos0[0]), by = fmaf(db, a.dir0[1], a.pos0[1]);
+        const float bz = fmaf(db, a.dir0[2], a.pos0[2]);
+        const float da = ax == 0 ? a.dir0[0] : (ax == 1 ? a.dir0[1] : a.dir0[2]);
+        if (da > 0.f && (ax == 0 || ax == 2)) {
+            const uint32_t key =
+                ax == 0 ? (uint32_t)(pixel(by, a.size[1], a.side_ny) * a.side_nx + pixel(bz, a.size[2], a.side_nx))
+                        : a.n_side + (uint32_t)(pixel(by, a.size[1], a.trans_ny) * a.trans_nx +
+                                                pixel(bx, a.size[0], a.trans_nx));
+            s_key[(key * 2654435761u) >> (32 - a.cache_bits)] = key;
+        }
+    }
     __syncthreads();
 
     const int lane = __lane_id();
+    float *q_y = s_queue + (threadIdx.x >> 6) * (3 * kQueue);
+    float *q_b = q_y + kQueue;
+    float *q_w = q_b + kQueue;                 // weight bits, bit 31 set for the side image
+    uint32_t q_n = 0;                          // wave-uniform queue fill
+
+    // Tally the first n queued exits, one per lane: pixel key, then the LDS
+    // cache (claim or hit, up to four linear probes) or, when every probed
+    // slot holds another pixel, a global atomic.
+    auto flush = [&](uint32_t n) {
+        __builtin_amdgcn_wave_barrier();
+        if ((uint32_t)lane < n) {
+            const float y = q_y[lane], b = q_b[lane];
+            const uint32_t wb = __float_as_uint(q_w[lane]);
+            const bool side = wb >> 31;
+            const double wd = (double)__uint_as_float(wb & 0x7FFFFFFFu);
+            const uint32_t key =
+                side ? (uint32_t)(pixel(y, a.size[1], a.side_ny) * a.side_nx + pixel(b, a.size[2], a.side_nx))
+                     : a.n_side + (uint32_t)(pixel(y, a.size[1], a.trans_ny) * a.trans_nx +
+                                             pixel(b, a.size[0], a.trans_nx));
+            bool cached = false;
+            if (slots) {
+                uint32_t slot = (key * 2654435761u) >> (32 - a.cache_bits);
+                for (int probe = 0; probe < 4 && !cached; ++probe) {
+                    const uint32_t old = atomicCAS(&s_key[slot], kEmpty, key);
+                    if (old == kEmpty || old == key) {
+                        atomicAdd(&s_cw[slot], wd);
+                        if (SIGMA) atomicAdd(&s_cw2[slot], wd * wd);
+                        cached = true;
+                    }
+                    slot = (slot + 1) & (uint32_t)(slots - 1);
+                }
+            }
+            if (!cached) {
+                atomicAdd(side ? a.side + key : a.trans + (key - a.n_side), wd);
+                if (SIGMA) atomicAdd(side ? a.side_w2 + key : a.trans_w2 + (key - a.n_side), wd * wd);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    };
+
     unsigned long long *work = (unsigned long long *)(a.scalars + MC_S_WORK);
     const float tab_scale = (float)(a.n_cdf - 1);
     const int tab_last = a.n_cdf - 2;
 
-    // Wave-uniform id range [next, end) and exhaustion flag.
-    uint64_t next = 0, end = 0;
+    // Wave-uniform id range: next id and ids left in the claimed chunk.
+    uint64_t q_next = 0;
+    uint32_t q_rem = 0;
     bool exhausted = false;
 
     // Lane state.
@@ -112,163 +218,144 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         // ---- refill lanes whose photon has ended -------------------------
         const uint64_t need = __ballot(!alive);
         if (need) {
-            if (next == end && !exhausted) {
+            if (q_rem == 0 && !exhausted) {
                 unsigned long long base = 0;
-                const int leader = __ffsll((unsigned long long)need) - 1;
-                if (lane == leader) base = atomicAdd(work, (unsigned long long)a.chunk);
-                base = __shfl(base, leader, 64);
-                if (base >= a.n_photons) {
+                if (lane == 0) base = atomicAdd(work, (unsigned long long)a.chunk);
+                const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+                const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+                const uint64_t b = ((uint64_t)hi << 32) | lo;
+                if (b >= a.n_photons) {
                     exhausted = true;
                 } else {
-                    next = base;
-                    end = min((uint64_t)base + a.chunk, a.n_photons);
+                    q_next = b;
+                    q_rem = (uint32_t)min((uint64_t)a.chunk, a.n_photons - b);
                 }
             }
-            const uint64_t avail = end - next;
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-            const uint32_t cnt = __popcll(need);
-            if (!alive && rank < avail) {
-                id = a.photon_offset + next + rank;
+            if (!alive && rank < q_rem) {
+                id = a.photon_offset + q_next + rank;
                 alive = true;
                 px = a.pos0[0]; py = a.pos0[1]; pz = a.pos0[2];
                 dx = a.dir0[0]; dy = a.dir0[1]; dz = a.dir0[2];
                 w = a.w0; L = 0.f; A = 0.f; k = 0; step = 0;
             }
-            next += min((uint64_t)cnt, avail);
+            const uint32_t took = min((uint32_t)__popcll(need), q_rem);
+            q_next += took;
+            q_rem -= took;
         }
         if (__ballot(alive) == 0) break;
-        if (!alive) continue;
 
-        // ---- one step -----------------------------------------------------
-        const Block4 r = philox4x32_10(step, a.instance, (uint32_t)id, (uint32_t)(id >> 32), a.key0, a.key1);
-        const float u0 = uniform01(r.r0), u1 = uniform01(r.r1);
-        const float u2 = uniform01(r.r2), u3 = uniform01(r.r3);
-        const float s = __builtin_amdgcn_logf(u0) * a.neg_ln2_over_mu;     // Eq. 15
+        bool ended = false;
+        int cause = 0, face = -1, axis = 0;
+        if (alive) {
+            // ---- one step ---------------------------------------------------
+            // The round keys derive from the seed inside the loop (scalar adds)
+            // rather than living in 20 scalar registers across it.
+            uint32_t k0 = a.key0, k1 = a.key1;
+            asm volatile("" : "+s"(k0), "+s"(k1));
+            const Block4 r = philox4x32_10(step, a.instance, (uint32_t)id, (uint32_t)(id >> 32), k0, k1);
+            const float u0 = uniform01(r.r0), u1 = uniform01(r.r1);
+            const float u2 = uniform01(r.r2), u3 = uniform01(r.r3);
+            const float s = __builtin_amdgcn_logf(u0) * a.neg_ln2_over_mu;     // Eq. 15
+            ++step;
 
-        // Nearest wall along the direction (ties go to the lower axis).
-        float tx = (dx > 0.f ? a.size[0] - px : -px) * __builtin_amdgcn_rcpf(dx);
-        float ty = (dy > 0.f ? a.size[1] - py : -py) * __builtin_amdgcn_rcpf(dy);
-        float tz = (dz > 0.f ? a.size[2] - pz : -pz) * __builtin_amdgcn_rcpf(dz);
-        tx = dx == 0.f ? kInf : fmaxf(tx, 0.f);
-        ty = dy == 0.f ? kInf : fmaxf(ty, 0.f);
-        tz = dz == 0.f ? kInf : fmaxf(tz, 0.f);
-        float db = tx;
-        int axis = 0;
-        if (ty < db) { db = ty; axis = 1; }
-        if (tz < db) { db = tz; axis = 2; }
+            // Nearest wall along the direction.
+            const float db = wall_distance(px, py, pz, dx, dy, dz, a.size[0], a.size[1], a.size[2], axis);
 
-        int end_cause = -1;     // -1 still walking, 0 exit, 1 roulette, 2 cap
-        int face = -1;
-        ++step;
-        if (s >= db) {
-            // Boundary: move to the wall, then reflect or leave.
-            px = fmaf(db, dx, px); py = fmaf(db, dy, py); pz = fmaf(db, dz, pz);
-            L += db;
-            const float da = axis == 0 ? dx : (axis == 1 ? dy : dz);
-            const float wall = da > 0.f ? (axis == 0 ? a.size[0] : (axis == 1 ? a.size[1] : a.size[2])) : 0.f;
-            if (axis == 0) px = wall; else if (axis == 1) py = wall; else pz = wall;
-            float R = 0.f;
-            if (!a.matched) {
-                const float ci = fabsf(da);
-                const float st2 = a.n12sq * fmaf(-ci, ci, 1.f);
-                if (st2 >= 1.f) {
-                    R = 1.f;
-                } else {
-                    const float ct = __builtin_amdgcn_sqrtf(1.f - st2);
+            const bool hit = s >= db;
+            const float t = hit ? db : s;
+            px = fmaf(t, dx, px); py = fmaf(t, dy, py); pz = fmaf(t, dz, pz);
+            L += t;
+            if (hit) {
+                // Boundary: snap onto the wall, then reflect (u3 < R) or leave.
+                const float da = axis == 0 ? dx : (axis == 1 ? dy : dz);
+                const bool pos_side = da > 0.f;
+                if (axis == 0) px = pos_side ? a.size[0] : 0.f;
+                else if (axis == 1) py = pos_side ? a.size[1] : 0.f;
+                else pz = pos_side ? a.size[2] : 0.f;
+                float R = 0.f;
+                if (!a.matched) {
+                    const float ci = fabsf(da);
+                    const float st2 = a.n12sq * fmaf(-ci, ci, 1.f);
+                    const float ct = __builtin_amdgcn_sqrtf(fmaxf(1.f - st2, 0.f));
                     const float rs = (ci - a.n21 * ct) * __builtin_amdgcn_rcpf(ci + a.n21 * ct);
                     const float rp = (a.n21 * ci - ct) * __builtin_amdgcn_rcpf(a.n21 * ci + ct);
-                    R = 0.5f * fmaf(rs, rs, rp * rp);
+                    R = st2 >= 1.f ? 1.f : 0.5f * fmaf(rs, rs, rp * rp);
                 }
-            }
-            if (u3 < R) {
-                if (axis == 0) dx = -dx; else if (axis == 1) dy = -dy; else dz = -dz;
-                ++acc_refl;
+                if (u3 < R) {
+                    if (axis == 0) dx = -dx; else if (axis == 1) dy = -dy; else dz = -dz;
+                    ++acc_refl;
+                } else {
+                    ended = true;
+                    face = 2 * axis + (pos_side ? 1 : 0);
+                }
             } else {
-                end_cause = 0;
-                face = 2 * axis + (da > 0.f ? 1 : 0);
-            }
-        } else {
-            // Interaction: move, count, absorb (Eq. 16), roulette, scatter.
-            px = fmaf(s, dx, px); py = fmaf(s, dy, py); pz = fmaf(s, dz, pz);
-            L += s;
-            ++k;
-            A = fmaf(w, a.absorb, A);
-            w *= a.albedo;
-            if (w < a.roulette_w) {
-                if (u3 < a.roulette_p) {
-                    const float wn = w * a.inv_roulette_p;
-                    atomicAdd(&s_scal[MC_S_ROULETTE_NET], (double)(wn - w));
-                    w = wn;
-                } else {
-                    atomicAdd(&s_scal[MC_S_ROULETTE_NET], -(double)w);
-                    atomicAdd(&s_scal[MC_S_ROULETTE_KILLS], 1.0);
-                    w = 0.f;
-                    end_cause = 1;
+                // Interaction: count, absorb (Eq. 16), roulette, scatter.
+                ++k;
+                A = fmaf(w, a.absorb, A);
+                w *= a.albedo;
+                if (w < a.roulette_w) {
+                    if (u3 < a.roulette_p) {
+                        const float wn = w * a.inv_roulette_p;
+                        atomicAdd(&s_scal[MC_S_ROULETTE_NET], (double)(wn - w));
+                        w = wn;
+                    } else {
+                        atomicAdd(&s_scal[MC_S_ROULETTE_NET], -(double)w);
+                        atomicAdd(&s_scal[MC_S_ROULETTE_KILLS], 1.0);
+                        w = 0.f;
+                        ended = true;
+                        cause = 1;
+                    }
+                }
+                if (!ended) {
+                    float v;
+                    if (PHASE == MC_PHASE_MIE) {
+                        const float tt = u1 * tab_scale;
+                        const int i = min((int)tt, tab_last);
+                        const float f = tt - (float)i;
+                        const float t0 = s_table[i], t1 = s_table[i + 1];
+                        v = fmaf(f, t1 - t0, t0);
+                    } else {
+                        const float D = fmaf(-a.hg_b, u1, a.hg_a);
+                        const float rD = __builtin_amdgcn_rcpf(D);
+                        v = a.hg_d * u1 * fmaf(a.hg_c, rD, a.hg_d) * rD;
+                    }
+                    const float ct = 1.f - v;
+                    const float st = __builtin_amdgcn_sqrtf(fmaxf(v * (2.f - v), 0.f));
+                    const float cp = __builtin_amdgcn_cosf(u2);        // cos(2 pi u2)
+                    const float sp = __builtin_amdgcn_sinf(u2);        // sin(2 pi u2)
+                    // Orthonormal basis around d (Duff et al. 2017).
+                    const float sg = copysignf(1.f, dz);
+                    const float ia = -__builtin_amdgcn_rcpf(sg + dz);
+                    const float b = dx * dy * ia;
+                    const float e1x = fmaf(sg * dx * dx, ia, 1.f), e1y = sg * b, e1z = -sg * dx;
+                    const float e2x = b, e2y = fmaf(dy * dy, ia, sg), e2z = -dy;
+                    const float qx = fmaf(cp, e1x, sp * e2x), qy = fmaf(cp, e1y, sp * e2y),
+                                qz = fmaf(cp, e1z, sp * e2z);
+                    const float nx = fmaf(ct, dx, st * qx), ny = fmaf(ct, dy, st * qy), nz = fmaf(ct, dz, st * qz);
+                    const float inv = __builtin_amdgcn_rsqf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
+                    dx = nx * inv; dy = ny * inv; dz = nz * inv;
                 }
             }
-            if (end_cause < 0) {
-                float v;
-                if (PHASE == MC_PHASE_MIE) {
-                    const float t = u1 * tab_scale;
-                    const int i = min((int)t, tab_last);
-                    const float f = t - (float)i;
-                    const float t0 = s_table[i], t1 = s_table[i + 1];
-                    v = fmaf(f, t1 - t0, t0);
-                } else {
-                    const float D = fmaf(-a.hg_b, u1, a.hg_a);
-                    const float rD = __builtin_amdgcn_rcpf(D);
-                    v = a.hg_d * u1 * fmaf(a.hg_c, rD, a.hg_d) * rD;
-                }
-                const float ct = 1.f - v;
-                const float st = __builtin_amdgcn_sqrtf(fmaxf(v * (2.f - v), 0.f));
-                const float cp = __builtin_amdgcn_cosf(u2);        // cos(2 pi u2)
-                const float sp = __builtin_amdgcn_sinf(u2);        // sin(2 pi u2)
-                // Orthonormal basis around d (Duff et al. 2017).
-                const float sg = copysignf(1.f, dz);
-                const float ia = -__builtin_amdgcn_rcpf(sg + dz);
-                const float b = dx * dy * ia;
-                const float e1x = fmaf(sg * dx * dx, ia, 1.f), e1y = sg * b, e1z = -sg * dx;
-                const float e2x = b, e2y = fmaf(dy * dy, ia, sg), e2z = -dy;
-                const float qx = fmaf(cp, e1x, sp * e2x), qy = fmaf(cp, e1y, sp * e2y),
-                            qz = fmaf(cp, e1z, sp * e2z);
-                float nx = fmaf(ct, dx, st * qx), ny = fmaf(ct, dy, st * qy), nz = fmaf(ct, dz, st * qz);
-                const float inv = __builtin_amdgcn_rsqf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
-                dx = nx * inv; dy = ny * inv; dz = nz * inv;
+            if (!ended && step >= a.max_steps) {
+                ended = true;
+                cause = 2;
+                atomicAdd(&s_scal[MC_S_CAPPED_W], (double)w);
+                atomicAdd(&s_scal[MC_S_CAPPED], 1.0);
             }
-        }
-        if (end_cause < 0 && step >= a.max_steps) {
-            end_cause = 2;
-            atomicAdd(&s_scal[MC_S_CAPPED_W], (double)w);
-            atomicAdd(&s_scal[MC_S_CAPPED], 1.0);
-        }
-        if (end_cause >= 0) {
-            // ---- photon ends: tallies and optional record ---------------
-            if (end_cause == 0) {
-                atomicAdd(&s_scal[MC_S_FACE + face], (double)w);
-                if (face == 1) {
-                    const size_t at = (size_t)pixel(py, a.size[1], a.side_ny) * a.side_nx +
-                                      pixel(pz, a.size[2], a.side_nx);
-                    atomicAdd(&a.side[at], (double)w);
-                    if (a.flags & MC_SIGMA) atomicAdd(&a.side_w2[at], (double)w * (double)w);
-                } else if (face == 5) {
-                    const size_t at = (size_t)pixel(py, a.size[1], a.trans_ny) * a.trans_nx +
-                                      pixel(px, a.size[0], a.trans_nx);
-                    atomicAdd(&a.trans[at], (double)w);
-                    if (a.flags & MC_SIGMA) atomicAdd(&a.trans_w2[at], (double)w * (double)w);
-                }
-            }
-            acc_abs += (double)A;
-            acc_events += k;
-            acc_steps += step;
-            ++acc_photons;
-            if (a.flags & MC_RECORD) {
-                const uint64_t rel = id - a.photon_offset;
-                if (rel % a.record_stride == 0) {
-                    const uint64_t row = rel / a.record_stride;
-                    if (row < a.rec_rows) {
+            if (ended) {
+                if (cause == 0) atomicAdd(&s_scal[MC_S_FACE + face], (double)w);
+                acc_abs += (double)A;
+                acc_events += k;
+                acc_steps += step;
+                ++acc_photons;
+                if (RECORD) {
+                    const uint64_t rel = id - a.photon_offset;
+                    if (rel % a.record_stride == 0 && rel / a.record_stride < a.rec_rows) {
+                        const uint64_t row = rel / a.record_stride, n = a.rec_rows;
                         float ox = dx, oy = dy, oz = dz;
-                        if (end_cause == 0 && !a.matched) {
+                        if (cause == 0 && !a.matched) {
                             // Refracted direction outside the wall (Snell).
                             ox *= a.n12; oy *= a.n12; oz *= a.n12;
                             const float t2 = (axis == 0 ? oy * oy + oz * oz
@@ -277,9 +364,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                                                        axis == 0 ? dx : (axis == 1 ? dy : dz));
                             if (axis == 0) ox = on; else if (axis == 1) oy = on; else oz = on;
                         }
-                        const uint64_t n = a.rec_rows;
                         a.rec_i[MC_REC_I_FACE * n + row] = face;
-                        a.rec_i[MC_REC_I_CAUSE * n + row] = end_cause;
+                        a.rec_i[MC_REC_I_CAUSE * n + row] = cause;
                         a.rec_i[MC_REC_I_K * n + row] = (int32_t)k;
                         a.rec_i[MC_REC_I_STEPS * n + row] = (int32_t)step;
                         a.rec_f[(MC_REC_F_POS + 0) * n + row] = px;
@@ -293,12 +379,32 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                         a.rec_f[MC_REC_F_A * n + row] = A;
                     }
                 }
+                alive = false;
             }
-            alive = false;
+        }
+
+        // ---- queue exits through the imaged faces (+x side, +z transmitted) ----
+        const bool to_img = ended && cause == 0 && (face == 1 || face == 5);
+        const uint64_t m = __ballot(to_img);
+        if (m) {
+            const uint32_t n_push = __popcll(m);
+            if (q_n + n_push > (uint32_t)kQueue) {
+                flush(q_n);
+                q_n = 0;
+            }
+            if (to_img) {
+                const uint32_t at = q_n + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                q_y[at] = py;
+                q_b[at] = face == 1 ? pz : px;
+                q_w[at] = __uint_as_float(__float_as_uint(w) | (face == 1 ? 0x80000000u : 0u));
+            }
+            q_n += n_push;
         }
     }
+    flush(q_n);
 
-    // ---- block-level flush of the scalar tallies ----------------------------
+    // ---- block-level flush of the scalar tallies and the cache ---------------
     const double wabs = wave_sum(acc_abs);
     const uint32_t wev = wave_sum(acc_events), wst = wave_sum(acc_steps), wrf = wave_sum(acc_refl),
                    wph = wave_sum(acc_photons);
@@ -313,6 +419,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     if (threadIdx.x < MC_S_WORK) {
         const double v = s_scal[threadIdx.x];
         if (v != 0.0) atomicAdd(&a.scalars[threadIdx.x], v);
+    }
+    for (int i = threadIdx.x; i < slots; i += blockDim.x) {
+        const uint32_t key = s_key[i];
+        if (key == kEmpty) continue;
+        const bool side = key < a.n_side;
+        atomicAdd(side ? a.side + key : a.trans + (key - a.n_side), s_cw[i]);
+        if (SIGMA) atomicAdd(side ? a.side_w2 + key : a.trans_w2 + (key - a.n_side), s_cw2[i]);
     }
 }
 
@@ -402,8 +515,9 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     if (!t.side || !t.trans || !t.scalars) return fail(MC_EINVAL, "mc_simulate: side, trans and scalars are required");
     if ((det.flags & MC_SIGMA) && (!t.side_w2 || !t.trans_w2))
         return fail(MC_EINVAL, "mc_simulate: MC_SIGMA needs side_w2 and trans_w2");
-    if ((det.flags & MC_RECORD) && (!t.rec_i || !t.rec_f || rn.record_stride < 1))
-        return fail(MC_EINVAL, "mc_simulate: MC_RECORD needs rec_i, rec_f and record_stride >= 1");
+    if ((det.flags & MC_RECORD) && (rn.record_stride < 1 || (t.rec_rows > 0 && (!t.rec_i || !t.rec_f))))
+        return fail(MC_EINVAL, "mc_simulate: MC_RECORD needs record_stride >= 1 and, for rec_rows > 0, "
+                               "rec_i and rec_f");
     if (rn.max_steps < 1) return fail(MC_EINVAL, "mc_simulate: max_steps must be >= 1");
     if (!(rn.roulette_w >= 0.0) || !(rn.roulette_p > 0.0 && rn.roulette_p <= 1.0))
         return fail(MC_EINVAL, "mc_simulate: roulette_w >= 0 and roulette_p in (0, 1] required");
@@ -473,19 +587,25 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     a.rec_rows = (det.flags & MC_RECORD) ? t.rec_rows : 0;
     a.record_stride = rn.record_stride >= 1 ? rn.record_stride : 1;
 
-    // ---- launch shape: enough resident waves to fill every CU ----
+    // ---- launch shape: 1024-lane blocks, two per CU (32 waves), each with
+    // the table, the per-wave exit queues and as large a tally cache as fits
+    // in half the CU's 160 KB LDS ----
     int cus = 0;
     if (int rc = device_cu_count(&cus)) return rc;
-    const size_t lds = (size_t)((a.n_cdf + 1) & ~1) * sizeof(float) + MC_N_SCALARS * sizeof(double);
-    const size_t lds_per_cu = 160 * 1024;
-    int blocks_per_cu = (int)std::min<size_t>(lds_per_cu / lds, 32);
-    int block = rn.block_size;
-    if (block == 0) {
-        const int waves = (32 + blocks_per_cu - 1) / blocks_per_cu;       // 32 waves per CU
-        block = std::min(1024, std::max(256, 64 * waves));
-    }
-    blocks_per_cu = std::max(1, std::min(blocks_per_cu, 32 / (block / 64)));
-    int grid = rn.grid_blocks > 0 ? rn.grid_blocks : cus * blocks_per_cu;
+    const size_t n_pix = (size_t)det.side_nx * det.side_ny + (size_t)det.trans_nx * det.trans_ny;
+    if (n_pix >= 0xFFFFFFFFull) return fail(MC_EINVAL, "mc_simulate: images exceed 2^32 - 2 pixels in total");
+    a.n_side = (uint32_t)((size_t)det.side_nx * det.side_ny);
+    const int block = rn.block_size ? rn.block_size : 1024;
+    const size_t lds_fixed = (size_t)((a.n_cdf + 3) & ~3) * sizeof(float) + MC_N_SCALARS * sizeof(double) +
+                             (size_t)(block / 64) * 3 * kQueue * sizeof(float);
+    const size_t slot_bytes = sizeof(uint32_t) + sizeof(double) * ((det.flags & MC_SIGMA) ? 2 : 1);
+    const size_t lds_half_cu = 80 * 1024;
+    a.cache_bits = 0;
+    for (int b = 10; b >= 4; --b)
+        if (lds_fixed + (slot_bytes << b) <= lds_half_cu) { a.cache_bits = b; break; }
+    const size_t lds = lds_fixed + (a.cache_bits ? (slot_bytes << a.cache_bits) : 0);
+    const int blocks_per_cu = std::max(1, std::min((int)(160 * 1024 / lds), 32 / (block / 64)));
+    const int grid = rn.grid_blocks > 0 ? rn.grid_blocks : cus * blocks_per_cu;
     const uint64_t waves_total = (uint64_t)grid * (block / 64);
     uint64_t chunk = rn.n_photons / std::max<uint64_t>(1, waves_total * 16);
     chunk = std::max<uint64_t>(64, std::min<uint64_t>(1024, (chunk + 63) / 64 * 64));
@@ -498,15 +618,17 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
                        a.trans_w2, t.scalars, a.rec_i, a.rec_f, (size_t)a.rec_rows, zero_all);
     MC_HIP_CHECK(hipGetLastError());
     if (rn.n_photons == 0) return MC_OK;
-    if (m.phase == MC_PHASE_MIE) {
-        MC_HIP_CHECK(hipFuncSetAttribute((const void *)walk_kernel<MC_PHASE_MIE>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(walk_kernel<MC_PHASE_MIE>, dim3(grid), dim3(block), lds, st, a);
-    } else {
-        MC_HIP_CHECK(hipFuncSetAttribute((const void *)walk_kernel<MC_PHASE_HG>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(walk_kernel<MC_PHASE_HG>, dim3(grid), dim3(block), lds, st, a);
-    }
+    const bool sig = (det.flags & MC_SIGMA) != 0, rec = (det.flags & MC_RECORD) != 0;
+    void (*kern)(WalkArgs) = nullptr;
+#define MC_PICK(P, S, R) \
+    if (m.phase == P && sig == S && rec == R) kern = walk_kernel<P, S, R>;
+    MC_PICK(MC_PHASE_MIE, false, false) MC_PICK(MC_PHASE_MIE, false, true)
+    MC_PICK(MC_PHASE_MIE, true, false) MC_PICK(MC_PHASE_MIE, true, true)
+    MC_PICK(MC_PHASE_HG, false, false) MC_PICK(MC_PHASE_HG, false, true)
+    MC_PICK(MC_PHASE_HG, true, false) MC_PICK(MC_PHASE_HG, true, true)
+#undef MC_PICK
+    MC_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, a);
     MC_HIP_CHECK(hipGetLastError());
     return MC_OK;
 }

@@ -42,7 +42,7 @@ def gpu_run(w, *, table=None, records=False, record_stride=1, sigma=True, g=None
     if sigma:
         out["side_w2"] = tally.side_w2.cpu().numpy()
         out["trans_w2"] = tally.trans_w2.cpu().numpy()
-    if records:
+    if records and tally.rec_i is not None:
         ri = tally.rec_i.cpu().numpy()
         rf = tally.rec_f.cpu().numpy().astype(np.float64)
         out["rec"] = {k: ri[i] for i, k in enumerate(IREC)}

@@ -75,9 +75,13 @@ def test_mie_table_parity(mc, cuda_device, case):
     coef = t.coef.cpu().numpy()
     ga = coef[:, 0] + 1j * coef[:, 1]
     gb = coef[:, 2] + 1j * coef[:, 3]
+    # Two FP64 evaluations of the same recurrence agree to ~1e-14 of the largest
+    # coefficient, except on a sharp resonance (a term whose |b_n| swings by ~1
+    # over dx ~ 1e-3), where rounding is amplified by the term's conditioning;
+    # 1e-11 covers that without hiding a wrong term (those are O(1) off).
     big = max(np.abs(o.a).max(), np.abs(o.b).max())
-    assert np.abs(ga - o.a).max() <= 1e-12 * big
-    assert np.abs(gb - o.b).max() <= 1e-12 * big
+    assert np.abs(ga - o.a).max() <= 1e-11 * big
+    assert np.abs(gb - o.b).max() <= 1e-11 * big
     for name in ("q_ext", "q_sca", "g", "sigma_ext_mm2"):
         assert getattr(t, name) == pytest.approx(getattr(o, name), rel=1e-11, abs=1e-300)
     assert t.q_abs == pytest.approx(o.q_abs, abs=1e-11 * o.q_ext)
