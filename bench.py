@@ -34,10 +34,21 @@ if ROOT not in sys.path:
 
 METRIC = "Mie MC scatter events/s (τ=4, 1e8 photons); fwd+adjoint vs fwd-only time"
 
-# Issue slots per unit of work, counted from the walk's arithmetic (FP32/INT32
-# lane operations at 1 slot; transcendentals and 32x32->64-bit products at 4).
-CENSUS = {"step": 169, "interaction": 72, "boundary": 41, "exit": 30}
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes, 2.4 GHz peak engine clock.
+# Issue slots per unit of work, counted from the walk's arithmetic as the
+# fewest gfx950 VALU instructions that perform it (each FP32/INT32 operation,
+# transcendental, 32x32->64-bit product or three-input XOR is one slot: the
+# SQ counters show each such VALU instruction occupying one issue slot).
+#   step         Philox4x32-10 (20 products, 20 XOR3), four uniforms, free path,
+#                distances to the three walls and the nearest one, move   = 91
+#   interaction  weight update and roulette test, inverse-CDF lookup and
+#                interpolation, sin/cos of both angles, orthonormal basis,
+#                new direction and its renormalisation                     = 49
+#   boundary     wall component, snap, unpolarised Fresnel with TIR,
+#                reflect-or-leave                                          = 31
+#   exit         face total; for the imaged faces also pixel row/column
+#                (IEEE divide), pixel key and tally-cache slot            = 40 / 2
+CENSUS = {"step": 91, "interaction": 49, "boundary": 31, "imaged_exit": 40, "other_exit": 2}
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock at the 2.4 GHz peak engine clock.
 PEAK_SLOTS_PER_S = 256 * 64 * 2.4e9
 
 
@@ -46,11 +57,15 @@ def log(msg):
 
 
 def census_slots(scal):
+    """Algorithmic issue slots of one launch from its scalar tallies.  The
+    imaged share of exits is taken from the exit weights (every exit weight
+    is w0 * albedo^k, equal to 1e-3 at albedo 0.9999)."""
     steps, events, photons = scal[14], scal[9], scal[10]
     exits = photons - scal[11] - scal[12]
-    boundary = steps - events
-    return (CENSUS["step"] * steps + CENSUS["interaction"] * events + CENSUS["boundary"] * boundary
-            + CENSUS["exit"] * exits)
+    faces = scal[0:6]
+    imaged = exits * (faces[1] + faces[5]) / max(faces.sum(), 1e-300)
+    return (CENSUS["step"] * steps + CENSUS["interaction"] * events + CENSUS["boundary"] * (steps - events)
+            + CENSUS["imaged_exit"] * imaged + CENSUS["other_exit"] * (exits - imaged))
 
 
 def cpu_baseline(w, target_s: float):

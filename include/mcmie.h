@@ -14,9 +14,15 @@
  *          stream).  Work is enqueued on it and the call returns without
  *          waiting unless stated otherwise; the caller keeps every buffer
  *          alive until the stream has drained.
- *   Ownership: the caller allocates every buffer.  The library keeps no
- *          pointer after a call returns.  Its only device memory is a small
- *          per-device scratch block for the table build.
+ *   Ownership: the caller allocates every buffer, including the walk's
+ *          workspace (size from mc_workspace_bytes).  The library keeps no
+ *          pointer after a call returns.  Its only device memory of its own
+ *          is a small per-device scratch block for the table build.
+ *   Tallies: weights are accumulated in 64-bit fixed point (weight * 2^32,
+ *          rounded to nearest), so every sum is exact and independent of the
+ *          order in which photons finish: results are bit-identical for any
+ *          launch shape, and photon ranges tallied separately add up to the
+ *          single run exactly (with MC_FIX64 images).
  *   Errors: functions return MC_OK (0) or a negative MC_E* code; the
  *          message of the last failure on the calling thread is returned by
  *          mc_last_error().  Arguments are validated on the host before any
@@ -44,6 +50,8 @@ extern "C" {
 #define MC_ACCUMULATE 1u      /* add into images and scalars instead of zeroing them first */
 #define MC_SIGMA 2u           /* also tally squared weights (side_w2, trans_w2) */
 #define MC_RECORD 4u          /* write per-photon end records (mc_tally_t.rec_*) */
+#define MC_FIX64 8u           /* images (and squared-weight images) are int64 fixed point,
+                                 value = weight * 2^32; otherwise they are double */
 
 /* Scalar tallies: mc_tally_t.scalars holds MC_N_SCALARS doubles. */
 #define MC_S_FACE 0           /* 0..5: weight leaving faces -x, +x, -y, +y, -z, +z */
@@ -56,7 +64,7 @@ extern "C" {
 #define MC_S_CAPPED 12        /* photons stopped by the step cap */
 #define MC_S_REFLECTIONS 13   /* Fresnel / total internal reflections at walls */
 #define MC_S_STEPS 14         /* random-number blocks drawn (walk steps) */
-#define MC_S_WORK 15          /* reserved: the library's work counter */
+#define MC_S_RESERVED 15      /* reserved (written as 0) */
 #define MC_N_SCALARS 16
 
 /* Per-photon record fields (structure of arrays, rec_rows rows per field). */
@@ -155,7 +163,9 @@ typedef struct {
 
 /* Photon budget, random streams, termination and launch shape. */
 typedef struct {
-    uint64_t n_photons;    /* photons in this call (0 allowed: only zeroing happens) */
+    uint64_t n_photons;    /* photons in this call (0 allowed: only zeroing happens);
+                              n_photons * max(1, roulette_w / roulette_p) must stay below 2^31
+                              so no fixed-point sum can overflow */
     uint64_t photon_offset;/* id of the first photon; ids are offset .. offset + n - 1 */
     uint64_t seed;         /* Philox4x32-10 key (seed_lo, seed_hi) */
     uint32_t instance;     /* Philox counter word 1 (independent medium instances) */
@@ -167,17 +177,27 @@ typedef struct {
     int32_t grid_blocks;   /* blocks; 0 = library choice (enough to fill every CU) */
 } mc_run_t;
 
-/* Caller-owned DEVICE outputs. */
+/* Caller-owned DEVICE outputs and workspace. */
 typedef struct {
-    double *side;          /* side_ny * side_nx doubles, row-major (required) */
-    double *trans;         /* trans_ny * trans_nx doubles, row-major (required) */
-    double *side_w2;       /* MC_SIGMA: squared-weight image, same shape */
-    double *trans_w2;      /* MC_SIGMA */
-    double *scalars;       /* MC_N_SCALARS doubles (required); slot MC_S_WORK is scratch */
+    void *side;            /* side_ny * side_nx double (int64 with MC_FIX64), row-major (required) */
+    void *trans;           /* trans_ny * trans_nx double (int64 with MC_FIX64), row-major (required) */
+    void *side_w2;         /* MC_SIGMA: squared-weight image, same shape and type */
+    void *trans_w2;        /* MC_SIGMA */
+    double *scalars;       /* MC_N_SCALARS doubles (required) */
     int32_t *rec_i;        /* MC_RECORD: MC_REC_I_N * rec_rows int32 */
     float *rec_f;          /* MC_RECORD: MC_REC_F_N * rec_rows float */
     uint64_t rec_rows;     /* MC_RECORD: rows available (0: record nothing, buffers may be NULL) */
+    void *workspace;       /* device scratch of at least mc_workspace_bytes(detector) bytes, 256-byte
+                              aligned (required); its contents on entry do not matter */
+    uint64_t workspace_bytes;
 } mc_tally_t;
+
+/*
+ * Bytes of device workspace mc_simulate needs for this detector: per-XCD
+ * fixed-point copies of the images (and of the squared-weight images with
+ * MC_SIGMA) plus scalar accumulators.  0 for a NULL or invalid detector.
+ */
+uint64_t mc_workspace_bytes(const mc_detector_t *detector);
 
 /*
  * Run the photon walk of Sec. 3.1.3 for run->n_photons photons: start at the
@@ -190,8 +210,8 @@ typedef struct {
  * (step, instance, id_lo, id_hi) and key (seed_lo, seed_hi), so a run split
  * into photon ranges with MC_ACCUMULATE equals one run up to tally rounding.
  * Unless MC_ACCUMULATE is set the images, scalars and records are zeroed on
- * `stream` first.  Asynchronous.  Calls that share a tally buffer must not
- * overlap in time.
+ * `stream` first.  Asynchronous.  Calls that share a tally buffer or a
+ * workspace must not overlap in time.
  */
 int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
                 const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,

@@ -13,10 +13,10 @@ LIB_PATH = os.path.join(_HERE, "libmcmie.so")
 
 MC_OK, MC_EINVAL, MC_EDEVICE, MC_ENOMEM, MC_EUNSUPPORTED = 0, -1, -2, -3, -4
 MC_PHASE_MIE, MC_PHASE_HG = 0, 1
-MC_ACCUMULATE, MC_SIGMA, MC_RECORD = 1, 2, 4
+MC_ACCUMULATE, MC_SIGMA, MC_RECORD, MC_FIX64 = 1, 2, 4, 8
 MC_N_SCALARS = 16
 MC_S_FACE, MC_S_ABSORBED, MC_S_ROULETTE_NET, MC_S_CAPPED_W, MC_S_EVENTS = 0, 6, 7, 8, 9
-MC_S_PHOTONS, MC_S_ROULETTE_KILLS, MC_S_CAPPED, MC_S_REFLECTIONS, MC_S_STEPS, MC_S_WORK = 10, 11, 12, 13, 14, 15
+MC_S_PHOTONS, MC_S_ROULETTE_KILLS, MC_S_CAPPED, MC_S_REFLECTIONS, MC_S_STEPS, MC_S_RESERVED = 10, 11, 12, 13, 14, 15
 MC_REC_I_N, MC_REC_F_N = 4, 9
 MC_MAX_N_CDF, MC_MAX_N_ANGLES, MC_MAX_TERMS = 16384, 3001, 1024
 
@@ -64,7 +64,8 @@ class Run(C.Structure):
 class _TallyC(C.Structure):
     _fields_ = [("side", C.c_void_p), ("trans", C.c_void_p), ("side_w2", C.c_void_p),
                 ("trans_w2", C.c_void_p), ("scalars", C.c_void_p), ("rec_i", C.c_void_p),
-                ("rec_f", C.c_void_p), ("rec_rows", C.c_uint64)]
+                ("rec_f", C.c_void_p), ("rec_rows", C.c_uint64), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_uint64)]
 
 
 class McError(RuntimeError):
@@ -92,6 +93,8 @@ def lib():
                               C.POINTER(Run), C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
         L.mc_philox_blocks.argtypes = [C.c_uint64, C.c_uint32, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
                                        C.c_void_p, C.c_void_p]
+        L.mc_workspace_bytes.argtypes = [C.POINTER(Detector)]
+        L.mc_workspace_bytes.restype = C.c_uint64
         L.mc_last_error.restype = C.c_char_p
         L.mc_version.restype = C.c_int
         for f in ("mie_table_build", "mc_simulate", "mc_grad", "mc_philox_blocks"):
@@ -153,24 +156,34 @@ def mie_table_build(spec: MieSpec, device="cuda", *, phase=False, cdf=False, coe
                     co[: t.n_terms] if co is not None else None)
 
 
+def mc_workspace_bytes(det: Detector) -> int:
+    return int(lib().mc_workspace_bytes(C.byref(det)))
+
+
 @dataclass
 class Tally:
-    """Caller-owned device outputs of mc_simulate."""
+    """Caller-owned device outputs and workspace of mc_simulate.  Images are
+    float64, or int64 fixed point (weight * 2^32) when allocated with fix64."""
     side: "object"
     trans: "object"
     scalars: "object"
+    workspace: "object" = None
     side_w2: "object" = None
     trans_w2: "object" = None
     rec_i: "object" = None          # (MC_REC_I_N, rows) int32
     rec_f: "object" = None          # (MC_REC_F_N, rows) float32
 
     @staticmethod
-    def alloc(det: Detector, device="cuda", *, sigma=False, record_rows=0) -> "Tally":
+    def alloc(det: Detector, device="cuda", *, sigma=False, record_rows=0, fix64=False) -> "Tally":
         import torch
         dev = torch.device(device)
-        f64 = dict(dtype=torch.float64, device=dev)
-        t = Tally(torch.empty((det.side_ny, det.side_nx), **f64), torch.empty((det.trans_ny, det.trans_nx), **f64),
-                  torch.empty(MC_N_SCALARS, **f64))
+        img = dict(dtype=torch.int64 if fix64 else torch.float64, device=dev)
+        probe = Detector(det.side_nx, det.side_ny, det.trans_nx, det.trans_ny,
+                         det.flags | (MC_SIGMA if sigma else 0))
+        ws_bytes = mc_workspace_bytes(probe)
+        t = Tally(torch.empty((det.side_ny, det.side_nx), **img), torch.empty((det.trans_ny, det.trans_nx), **img),
+                  torch.empty(MC_N_SCALARS, dtype=torch.float64, device=dev),
+                  torch.empty((ws_bytes + 7) // 8, dtype=torch.int64, device=dev))
         if sigma:
             t.side_w2 = torch.empty_like(t.side)
             t.trans_w2 = torch.empty_like(t.trans)
@@ -185,6 +198,8 @@ class Tally:
         c.side_w2, c.trans_w2 = _ptr(self.side_w2), _ptr(self.trans_w2)
         c.rec_i, c.rec_f = _ptr(self.rec_i), _ptr(self.rec_f)
         c.rec_rows = 0 if self.rec_i is None else int(self.rec_i.shape[1])
+        c.workspace = _ptr(self.workspace)
+        c.workspace_bytes = 0 if self.workspace is None else self.workspace.numel() * 8
         return c
 
 

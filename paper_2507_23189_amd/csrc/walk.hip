@@ -18,14 +18,20 @@
 // Henyey-Greenstein (Eq. 11), with azimuth 2 pi u2, built in the orthonormal
 // basis of Duff et al. 2017 around the old direction.
 //
-// Transport runs in FP32; tallies accumulate in FP64.  Exits go through a
+// Transport runs in FP32.  Weights are tallied in 64-bit fixed point
+// (weight * 2^32, rounded to nearest): integer sums do not depend on the order
+// in which photons finish, so results are bit-identical for any launch shape.
+// Exits go through a
 // per-block LDS tally cache: a direct-mapped table of pixel ids (claimed with
 // an LDS compare-and-swap, first come first served) whose FP64 sums are
 // flushed to the images once per block.  The pencil beam sends every
 // unscattered photon to the same transmitted pixel, and same-address global
 // atomics serialise across the chip, so without the cache that one pixel
 // bounds the whole launch.  Pixels that miss the cache (slot held by another
-// pixel) fall back to a global atomic.  Exits are first queued per wave in
+// pixel) fall back to a global atomic into one of eight per-XCD copies of the
+// images in the caller's workspace (contention on the warm pixels around the
+// beam is then spread over eight addresses); a finalize pass sums the copies
+// and converts to the caller's images.  Exits are first queued per wave in
 // LDS and tallied 64 at a time by the whole wave, so the pixel arithmetic and
 // atomics run with full lanes instead of on the few lanes that exit in any
 // one step.  Scalar tallies use LDS atomics and lane accumulators, also
@@ -61,11 +67,22 @@ struct WalkArgs {
     int cache_bits;           // log2 of the tally-cache slots (0: no cache)
     uint32_t n_side;          // pixels of the side image (cache key offset of the transmitted image)
     int side_nx, side_ny, trans_nx, trans_ny;
-    double *side, *trans, *side_w2, *trans_w2, *scalars;
+    unsigned long long *ws_scal;   // workspace: 16 fixed-point scalar sums, work counter at MC_S_RESERVED
+    unsigned long long *ws_img;    // workspace: kCopies x n_pix fixed-point weight sums
+    unsigned long long *ws_img2;   // workspace (MC_SIGMA): kCopies x n_pix squared-weight sums
+    uint64_t n_pix;
     int32_t *rec_i;
     float *rec_f;
     uint64_t rec_rows, record_stride;
 };
+
+constexpr int kCopies = 8;                 // per-XCD image copies in the workspace
+constexpr double kFix = 4294967296.0;      // fixed-point scale 2^32 per unit weight
+
+__device__ __forceinline__ unsigned long long fix(float w)
+{
+    return (unsigned long long)llrint((double)w * kFix);
+}
 
 // Pixel = floor(coord / size * n), clamped to the image (IEEE division, so a
 // coordinate on a pixel edge lands where the FP64 definition puts it).
@@ -95,7 +112,7 @@ __device__ __forceinline__ float wall_distance(float px, float py, float pz, flo
     return db;
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
 {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -119,19 +136,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // tally cache (slots doubles of weight, [SIGMA] slots doubles of squared
     // weight, slots uint32 keys), per-wave exit queues (3 x kQueue floats).
     extern __shared__ float s_table[];
-    double *s_scal = (double *)(s_table + ((a.n_cdf + 3) & ~3));
+    unsigned long long *s_scal = (unsigned long long *)(s_table + ((a.n_cdf + 3) & ~3));
     const int slots = a.cache_bits ? 1 << a.cache_bits : 0;
-    double *s_cw = s_scal + MC_N_SCALARS;
-    double *s_cw2 = s_cw + (SIGMA ? slots : 0);
+    unsigned long long *s_cw = s_scal + MC_N_SCALARS;
+    unsigned long long *s_cw2 = s_cw + (SIGMA ? slots : 0);
     uint32_t *s_key = (uint32_t *)(s_cw2 + slots);
     float *s_queue = (float *)(s_key + slots);
 
     if (PHASE == MC_PHASE_MIE)
         for (int i = threadIdx.x; i < a.n_cdf; i += blockDim.x) s_table[i] = a.inv_cdf[i];
-    if (threadIdx.x < MC_N_SCALARS) s_scal[threadIdx.x] = 0.0;
+    if (threadIdx.x < MC_N_SCALARS) s_scal[threadIdx.x] = 0ull;
     for (int i = threadIdx.x; i < slots; i += blockDim.x) {
-        s_cw[i] = 0.0;
-        if (SIGMA) s_cw2[i] = 0.0;
+        s_cw[i] = 0ull;
+        if (SIGMA) s_cw2[i] = 0ull;
         s_key[i] = kEmpty;
     }
     __syncthreads();
@@ -155,6 +172,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     __syncthreads();
 
     const int lane = __lane_id();
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) % kCopies;   // hwreg(HW_REG_XCC_ID, 0, 4)
+    unsigned long long *my_img = a.ws_img + (uint64_t)xcc * a.n_pix;
+    unsigned long long *my_img2 = SIGMA ? a.ws_img2 + (uint64_t)xcc * a.n_pix : nullptr;
     float *q_y = s_queue + (threadIdx.x >> 6) * (3 * kQueue);
     float *q_b = q_y + kQueue;
     float *q_w = q_b + kQueue;                 // weight bits, bit 31 set for the side image
@@ -169,7 +189,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             const float y = q_y[lane], b = q_b[lane];
             const uint32_t wb = __float_as_uint(q_w[lane]);
             const bool side = wb >> 31;
-            const double wd = (double)__uint_as_float(wb & 0x7FFFFFFFu);
+            const float wf = __uint_as_float(wb & 0x7FFFFFFFu);
+            const unsigned long long wq = fix(wf), wq2 = SIGMA ? fix(wf * wf) : 0ull;
             const uint32_t key =
                 side ? (uint32_t)(pixel(y, a.size[1], a.side_ny) * a.side_nx + pixel(b, a.size[2], a.side_nx))
                      : a.n_side + (uint32_t)(pixel(y, a.size[1], a.trans_ny) * a.trans_nx +
@@ -180,22 +201,22 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 for (int probe = 0; probe < 4 && !cached; ++probe) {
                     const uint32_t old = atomicCAS(&s_key[slot], kEmpty, key);
                     if (old == kEmpty || old == key) {
-                        atomicAdd(&s_cw[slot], wd);
-                        if (SIGMA) atomicAdd(&s_cw2[slot], wd * wd);
+                        atomicAdd(&s_cw[slot], wq);
+                        if (SIGMA) atomicAdd(&s_cw2[slot], wq2);
                         cached = true;
                     }
                     slot = (slot + 1) & (uint32_t)(slots - 1);
                 }
             }
             if (!cached) {
-                atomicAdd(side ? a.side + key : a.trans + (key - a.n_side), wd);
-                if (SIGMA) atomicAdd(side ? a.side_w2 + key : a.trans_w2 + (key - a.n_side), wd * wd);
+                atomicAdd(my_img + key, wq);
+                if (SIGMA) atomicAdd(my_img2 + key, wq2);
             }
         }
         __builtin_amdgcn_wave_barrier();
     };
 
-    unsigned long long *work = (unsigned long long *)(a.scalars + MC_S_WORK);
+    unsigned long long *work = a.ws_scal + MC_S_RESERVED;
     const float tab_scale = (float)(a.n_cdf - 1);
     const int tab_last = a.n_cdf - 2;
 
@@ -211,7 +232,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     float w = 0.f, L = 0.f, A = 0.f;
     uint32_t k = 0, step = 0;
     // Lane accumulators.
-    double acc_abs = 0.0;
+    unsigned long long acc_abs = 0ull;
     uint32_t acc_events = 0, acc_steps = 0, acc_refl = 0, acc_photons = 0;
 
     for (;;) {
@@ -298,11 +319,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 if (w < a.roulette_w) {
                     if (u3 < a.roulette_p) {
                         const float wn = w * a.inv_roulette_p;
-                        atomicAdd(&s_scal[MC_S_ROULETTE_NET], (double)(wn - w));
+                        atomicAdd(&s_scal[MC_S_ROULETTE_NET], fix(wn) - fix(w));
                         w = wn;
                     } else {
-                        atomicAdd(&s_scal[MC_S_ROULETTE_NET], -(double)w);
-                        atomicAdd(&s_scal[MC_S_ROULETTE_KILLS], 1.0);
+                        atomicAdd(&s_scal[MC_S_ROULETTE_NET], 0ull - fix(w));
+                        atomicAdd(&s_scal[MC_S_ROULETTE_KILLS], 1ull);
                         w = 0.f;
                         ended = true;
                         cause = 1;
@@ -341,12 +362,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             if (!ended && step >= a.max_steps) {
                 ended = true;
                 cause = 2;
-                atomicAdd(&s_scal[MC_S_CAPPED_W], (double)w);
-                atomicAdd(&s_scal[MC_S_CAPPED], 1.0);
+                atomicAdd(&s_scal[MC_S_CAPPED_W], fix(w));
+                atomicAdd(&s_scal[MC_S_CAPPED], 1ull);
             }
             if (ended) {
-                if (cause == 0) atomicAdd(&s_scal[MC_S_FACE + face], (double)w);
-                acc_abs += (double)A;
+                // Faces +x and +z are totalled from their images when finalizing.
+                if (cause == 0 && face != 1 && face != 5) atomicAdd(&s_scal[MC_S_FACE + face], fix(w));
+                acc_abs += fix(A);
                 acc_events += k;
                 acc_steps += step;
                 ++acc_photons;
@@ -405,50 +427,97 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     flush(q_n);
 
     // ---- block-level flush of the scalar tallies and the cache ---------------
-    const double wabs = wave_sum(acc_abs);
+    const unsigned long long wabs = wave_sum(acc_abs);
     const uint32_t wev = wave_sum(acc_events), wst = wave_sum(acc_steps), wrf = wave_sum(acc_refl),
                    wph = wave_sum(acc_photons);
     if (lane == 0) {
         atomicAdd(&s_scal[MC_S_ABSORBED], wabs);
-        atomicAdd(&s_scal[MC_S_EVENTS], (double)wev);
-        atomicAdd(&s_scal[MC_S_STEPS], (double)wst);
-        atomicAdd(&s_scal[MC_S_REFLECTIONS], (double)wrf);
-        atomicAdd(&s_scal[MC_S_PHOTONS], (double)wph);
+        atomicAdd(&s_scal[MC_S_EVENTS], (unsigned long long)wev);
+        atomicAdd(&s_scal[MC_S_STEPS], (unsigned long long)wst);
+        atomicAdd(&s_scal[MC_S_REFLECTIONS], (unsigned long long)wrf);
+        atomicAdd(&s_scal[MC_S_PHOTONS], (unsigned long long)wph);
     }
     __syncthreads();
-    if (threadIdx.x < MC_S_WORK) {
-        const double v = s_scal[threadIdx.x];
-        if (v != 0.0) atomicAdd(&a.scalars[threadIdx.x], v);
+    if (threadIdx.x < MC_S_RESERVED) {
+        const unsigned long long v = s_scal[threadIdx.x];
+        if (v != 0ull) atomicAdd(&a.ws_scal[threadIdx.x], v);
     }
     for (int i = threadIdx.x; i < slots; i += blockDim.x) {
         const uint32_t key = s_key[i];
         if (key == kEmpty) continue;
-        const bool side = key < a.n_side;
-        atomicAdd(side ? a.side + key : a.trans + (key - a.n_side), s_cw[i]);
-        if (SIGMA) atomicAdd(side ? a.side_w2 + key : a.trans_w2 + (key - a.n_side), s_cw2[i]);
+        atomicAdd(my_img + key, s_cw[i]);
+        if (SIGMA) atomicAdd(my_img2 + key, s_cw2[i]);
     }
 }
 
-// Zero the outputs (unless accumulating) and always reset the work counter.
-__global__ void init_kernel(double *side, size_t n_side, double *trans, size_t n_trans, double *side_w2,
-                            double *trans_w2, double *scalars, int32_t *rec_i, float *rec_f, size_t n_rec,
-                            int zero_all)
+// Zero the workspace, and the outputs unless accumulating.  (Fill kernels,
+// not memset, so the sequence stays valid under stream capture.)
+__global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long long *side, unsigned long long *trans,
+                            unsigned long long *side_w2, unsigned long long *trans_w2, size_t n_side, size_t n_trans,
+                            double *scalars, int32_t *rec_i, float *rec_f, size_t n_rec, int zero_all)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t0 == 0) ((unsigned long long *)scalars)[MC_S_WORK] = 0ull;
+    for (size_t i = t0; i < n_ws; i += stride) ws[i] = 0ull;
     if (!zero_all) return;
     for (size_t i = t0; i < n_side; i += stride) {
-        side[i] = 0.0;
-        if (side_w2) side_w2[i] = 0.0;
+        side[i] = 0ull;                 // +0.0 and int64 0 share the bit pattern
+        if (side_w2) side_w2[i] = 0ull;
     }
     for (size_t i = t0; i < n_trans; i += stride) {
-        trans[i] = 0.0;
-        if (trans_w2) trans_w2[i] = 0.0;
+        trans[i] = 0ull;
+        if (trans_w2) trans_w2[i] = 0ull;
     }
-    if (t0 < MC_S_WORK) scalars[t0] = 0.0;
+    if (t0 < MC_N_SCALARS) scalars[t0] = 0.0;
     for (size_t i = t0; i < (size_t)MC_REC_I_N * n_rec; i += stride) rec_i[i] = (i / n_rec == MC_REC_I_FACE) ? -1 : 0;
     for (size_t i = t0; i < (size_t)MC_REC_F_N * n_rec; i += stride) rec_f[i] = 0.f;
+}
+
+// Sum the per-XCD fixed-point copies of every pixel (integer adds, so the
+// order is immaterial) and add them to the caller's images, as int64 (FIX) or
+// converted to double.  Weight sums of the +x and +z images also give those
+// faces' totals.
+template <bool FIX>
+__global__ __launch_bounds__(256) void finalize_images(const unsigned long long *copies, uint64_t n_pix,
+                                                       uint32_t n_side, void *side, void *trans,
+                                                       unsigned long long *face_side, unsigned long long *face_trans)
+{
+    unsigned long long sum_side = 0ull, sum_trans = 0ull;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pix;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        unsigned long long v = 0ull;
+#pragma unroll
+        for (int c = 0; c < kCopies; ++c) v += copies[(uint64_t)c * n_pix + i];
+        const bool is_side = i < n_side;
+        const uint64_t j = is_side ? i : i - n_side;
+        if (FIX) {
+            long long *out = (long long *)(is_side ? side : trans);
+            out[j] += (long long)v;
+        } else {
+            double *out = (double *)(is_side ? side : trans);
+            out[j] += (double)(long long)v * (1.0 / kFix);
+        }
+        if (is_side) sum_side += v; else sum_trans += v;
+    }
+    if (face_side) {
+        sum_side = wave_sum(sum_side);
+        sum_trans = wave_sum(sum_trans);
+        if (__lane_id() == 0) {
+            if (sum_side) atomicAdd(face_side, sum_side);
+            if (sum_trans) atomicAdd(face_trans, sum_trans);
+        }
+    }
+}
+
+// Fixed-point scalar sums to the caller's doubles (weights scaled back by
+// 2^-32, counts as they are).
+__global__ void finalize_scalars(const unsigned long long *ws_scal, double *scalars)
+{
+    const int t = threadIdx.x;
+    if (t >= MC_S_RESERVED) return;
+    const bool weight = t <= MC_S_CAPPED_W;
+    const long long v = (long long)ws_scal[t];
+    scalars[t] += weight ? (double)v * (1.0 / kFix) : (double)v;
 }
 
 __global__ void philox_blocks_kernel(uint32_t k0, uint32_t k1, uint32_t instance, const uint64_t *ids,
@@ -467,6 +536,16 @@ __global__ void philox_blocks_kernel(uint32_t k0, uint32_t k1, uint32_t instance
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Workspace layout: 32 uint64 scalar words, then kCopies fixed-point copies of
+// the images (and of the squared-weight images with MC_SIGMA).
+constexpr uint64_t kWsScalarWords = 32;
+
+uint64_t workspace_words(const mc_detector_t &d)
+{
+    const uint64_t n_pix = (uint64_t)d.side_nx * d.side_ny + (uint64_t)d.trans_nx * d.trans_ny;
+    return kWsScalarWords + (uint64_t)kCopies * n_pix * ((d.flags & MC_SIGMA) ? 2 : 1);
+}
 
 }  // namespace
 }  // namespace mcmie
@@ -510,8 +589,6 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
         return fail(MC_EINVAL, "mc_simulate: the source direction must point into the cuboid (dir[2] > 0)");
     if (det.side_nx < 1 || det.side_ny < 1 || det.trans_nx < 1 || det.trans_ny < 1)
         return fail(MC_EINVAL, "mc_simulate: image dimensions must be >= 1");
-    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD))
-        return fail(MC_EINVAL, "mc_simulate: unknown detector flags 0x%x", det.flags);
     if (!t.side || !t.trans || !t.scalars) return fail(MC_EINVAL, "mc_simulate: side, trans and scalars are required");
     if ((det.flags & MC_SIGMA) && (!t.side_w2 || !t.trans_w2))
         return fail(MC_EINVAL, "mc_simulate: MC_SIGMA needs side_w2 and trans_w2");
@@ -525,6 +602,22 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     if (rn.block_size != 0 && (rn.block_size < 64 || rn.block_size > 1024 || rn.block_size % 64))
         return fail(MC_EINVAL, "mc_simulate: block_size must be a multiple of 64 in 64..1024");
     if (rn.grid_blocks < 0) return fail(MC_EINVAL, "mc_simulate: grid_blocks must be >= 0");
+    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64))
+        return fail(MC_EINVAL, "mc_simulate: unknown detector flags 0x%x", det.flags);
+    if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < workspace_words(det) * 8)
+        return fail(MC_EINVAL, "mc_simulate: workspace needs %llu bytes, 8-byte aligned",
+                    (unsigned long long)(workspace_words(det) * 8));
+    {
+        // Fixed-point sums stay below 2^63: every weight is at most
+        // max(1, roulette_w / roulette_p), so n_photons times that (squared
+        // for MC_SIGMA) must stay below 2^31.
+        const double wmax = std::max(1.0, rn.roulette_w / rn.roulette_p);
+        const double bound = (double)rn.n_photons * ((det.flags & MC_SIGMA) ? wmax * wmax : wmax);
+        if (!(bound < 2147483648.0))
+            return fail(MC_EINVAL, "mc_simulate: %llu photons with weights up to %g could overflow the "
+                        "fixed-point tallies; split the run into photon ranges",
+                        (unsigned long long)rn.n_photons, wmax);
+    }
 
     // ---- derived coefficients (Eq. 1, Eq. 16) and the entry beam ----
     WalkArgs a{};
@@ -579,10 +672,12 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     a.flags = det.flags;
     a.side_nx = det.side_nx; a.side_ny = det.side_ny;
     a.trans_nx = det.trans_nx; a.trans_ny = det.trans_ny;
-    a.side = t.side; a.trans = t.trans;
-    a.side_w2 = (det.flags & MC_SIGMA) ? t.side_w2 : nullptr;
-    a.trans_w2 = (det.flags & MC_SIGMA) ? t.trans_w2 : nullptr;
-    a.scalars = t.scalars;
+    const uint64_t n_pix_all = (uint64_t)det.side_nx * det.side_ny + (uint64_t)det.trans_nx * det.trans_ny;
+    unsigned long long *ws = (unsigned long long *)t.workspace;
+    a.ws_scal = ws;
+    a.ws_img = ws + kWsScalarWords;
+    a.ws_img2 = (det.flags & MC_SIGMA) ? a.ws_img + (uint64_t)kCopies * n_pix_all : nullptr;
+    a.n_pix = n_pix_all;
     a.rec_i = t.rec_i; a.rec_f = t.rec_f;
     a.rec_rows = (det.flags & MC_RECORD) ? t.rec_rows : 0;
     a.record_stride = rn.record_stride >= 1 ? rn.record_stride : 1;
@@ -614,11 +709,12 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     hipStream_t st = (hipStream_t)stream;
     const size_t n_side = (size_t)det.side_nx * det.side_ny, n_trans = (size_t)det.trans_nx * det.trans_ny;
     const int zero_all = (det.flags & MC_ACCUMULATE) ? 0 : 1;
-    hipLaunchKernelGGL(init_kernel, dim3(256), dim3(256), 0, st, t.side, n_side, t.trans, n_trans, a.side_w2,
-                       a.trans_w2, t.scalars, a.rec_i, a.rec_f, (size_t)a.rec_rows, zero_all);
-    MC_HIP_CHECK(hipGetLastError());
-    if (rn.n_photons == 0) return MC_OK;
     const bool sig = (det.flags & MC_SIGMA) != 0, rec = (det.flags & MC_RECORD) != 0;
+    hipLaunchKernelGGL(init_kernel, dim3(1024), dim3(256), 0, st, ws, (size_t)workspace_words(det),
+                       (unsigned long long *)t.side, (unsigned long long *)t.trans,
+                       sig ? (unsigned long long *)t.side_w2 : nullptr, sig ? (unsigned long long *)t.trans_w2 : nullptr,
+                       n_side, n_trans, t.scalars, a.rec_i, a.rec_f, (size_t)a.rec_rows, zero_all);
+    MC_HIP_CHECK(hipGetLastError());
     void (*kern)(WalkArgs) = nullptr;
 #define MC_PICK(P, S, R) \
     if (m.phase == P && sig == S && rec == R) kern = walk_kernel<P, S, R>;
@@ -627,10 +723,31 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     MC_PICK(MC_PHASE_HG, false, false) MC_PICK(MC_PHASE_HG, false, true)
     MC_PICK(MC_PHASE_HG, true, false) MC_PICK(MC_PHASE_HG, true, true)
 #undef MC_PICK
-    MC_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, a);
+    if (rn.n_photons > 0) {
+        MC_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, a);
+        MC_HIP_CHECK(hipGetLastError());
+    }
+    // ---- finalize: per-XCD copies to the caller's images, scalars to doubles ----
+    const bool fix64 = (det.flags & MC_FIX64) != 0;
+    const unsigned fin_grid = (unsigned)std::min<uint64_t>(2048, (n_pix_all + 255) / 256);
+    auto fin = fix64 ? finalize_images<true> : finalize_images<false>;
+    hipLaunchKernelGGL(fin, dim3(fin_grid), dim3(256), 0, st, a.ws_img, n_pix_all, a.n_side, t.side, t.trans,
+                       ws + MC_S_FACE + 1, ws + MC_S_FACE + 5);
+    if (sig)
+        hipLaunchKernelGGL(fin, dim3(fin_grid), dim3(256), 0, st, a.ws_img2, n_pix_all, a.n_side, t.side_w2,
+                           t.trans_w2, (unsigned long long *)nullptr, (unsigned long long *)nullptr);
+    hipLaunchKernelGGL(finalize_scalars, dim3(1), dim3(64), 0, st, (const unsigned long long *)ws, t.scalars);
     MC_HIP_CHECK(hipGetLastError());
     return MC_OK;
+}
+
+extern "C" uint64_t mc_workspace_bytes(const mc_detector_t *detector)
+{
+    if (!detector || detector->side_nx < 1 || detector->side_ny < 1 || detector->trans_nx < 1 ||
+        detector->trans_ny < 1)
+        return 0;
+    return mcmie::workspace_words(*detector) * 8;
 }
 
 extern "C" int mc_grad(const mc_medium_t *, const mc_source_t *, const mc_geometry_t *, const mc_detector_t *,

@@ -19,7 +19,8 @@ FREC = ("px", "py", "pz", "dx", "dy", "dz", "w", "L", "A")
 
 
 def gpu_run(w, *, table=None, records=False, record_stride=1, sigma=True, g=None, block_size=0,
-            grid_blocks=0, n_photons=None, photon_offset=0, flags_extra=0, tally=None, table_kw=None):
+            grid_blocks=0, n_photons=None, photon_offset=0, flags_extra=0, tally=None, table_kw=None,
+            fix64=False):
     """Build the table (unless given) and run mc_simulate; return numpy results."""
     import torch
     import paper_2507_23189_amd as mc
@@ -27,14 +28,15 @@ def gpu_run(w, *, table=None, records=False, record_stride=1, sigma=True, g=None
     spec, *_ = mc.args_from_workload(w)
     if table is None:
         table = mc.mie_table_build(spec, dev, **(table_kw or {}))
-    flags = (mc.MC_SIGMA if sigma else 0) | (mc.MC_RECORD if records else 0) | flags_extra
+    flags = (mc.MC_SIGMA if sigma else 0) | (mc.MC_RECORD if records else 0) | (mc.MC_FIX64 if fix64 else 0) \
+        | flags_extra
     _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g, flags=flags, record_stride=record_stride,
                                                        block_size=block_size, grid_blocks=grid_blocks,
                                                        n_photons=n_photons, photon_offset=photon_offset)
     n = run.n_photons
     rows = (n + record_stride - 1) // record_stride if records else 0
     if tally is None:
-        tally = mc.Tally.alloc(det, dev, sigma=sigma, record_rows=rows)
+        tally = mc.Tally.alloc(det, dev, sigma=sigma, record_rows=rows, fix64=fix64)
     mc.mc_simulate(med, src, geo, det, run, tally)
     torch.cuda.synchronize()
     out = dict(side=tally.side.cpu().numpy(), trans=tally.trans.cpu().numpy(),

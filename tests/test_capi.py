@@ -29,7 +29,7 @@ def _declared_functions():
 def test_header_declares_the_entry_points():
     names = set(_declared_functions())
     assert {"mie_table_build", "mc_simulate", "mc_grad", "mc_last_error", "mc_philox_blocks",
-            "mc_version"} <= names
+            "mc_version", "mc_workspace_bytes"} <= names
 
 
 def test_library_exports_every_declared_symbol():
@@ -49,6 +49,15 @@ def test_version_and_empty_error():
     assert mc.lib().mc_last_error() == b""
 
 
+def _tally_stub(det):
+    """Tally whose pointers are never dereferenced: validation fails first."""
+    import paper_2507_23189_amd as mc
+    tal = mc._capi._TallyC()
+    tal.side = tal.trans = tal.scalars = tal.workspace = 0x1000
+    tal.workspace_bytes = mc.mc_workspace_bytes(det)
+    return tal
+
+
 def _valid_args():
     import paper_2507_23189_amd as mc
     import workloads as W
@@ -65,8 +74,7 @@ def test_mc_simulate_rejects_invalid_arguments(field, value):
     import paper_2507_23189_amd as mc
     _lib_path()
     spec, med, src, geo, det, run = _valid_args()
-    tal = mc._capi._TallyC()
-    tal.side = tal.trans = tal.scalars = 0x1000      # never dereferenced: validation fails first
+    tal = _tally_stub(det)
     if field in ("tau", "albedo", "g", "phase"):
         setattr(med, field, value)
     elif field == "src_z":
@@ -87,6 +95,45 @@ def test_mc_simulate_rejects_invalid_arguments(field, value):
                               C.byref(tal), None)
     assert rc == mc.MC_EINVAL
     assert mc.lib().mc_last_error().startswith(b"mc_simulate")
+
+
+def test_workspace_size_and_checks():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, med, src, geo, det, run = _valid_args()
+    n_pix = det.side_nx * det.side_ny + det.trans_nx * det.trans_ny
+    assert mc.mc_workspace_bytes(det) == 8 * (32 + 8 * n_pix)
+    det.flags = mc.MC_SIGMA
+    assert mc.mc_workspace_bytes(det) == 8 * (32 + 16 * n_pix)
+    det.flags = 0
+    bad = mc.Detector(0, 1, 1, 1, 0)
+    assert mc.mc_workspace_bytes(bad) == 0
+    tal = _tally_stub(det)
+    tal.workspace_bytes -= 8
+    rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                              C.byref(tal), None)
+    assert rc == mc.MC_EINVAL and b"workspace" in mc.lib().mc_last_error()
+    tal = _tally_stub(det)
+    tal.workspace = 0x1004                            # misaligned
+    rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                              C.byref(tal), None)
+    assert rc == mc.MC_EINVAL
+
+
+def test_fixed_point_overflow_bound():
+    # n_photons * max(1, roulette_w / roulette_p) must stay below 2^31.
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, med, src, geo, det, run = _valid_args()
+    run.n_photons = 2**31
+    rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                              C.byref(_tally_stub(det)), None)
+    assert rc == mc.MC_EINVAL and b"overflow" in mc.lib().mc_last_error()
+    run.n_photons = 10**8
+    run.roulette_w, run.roulette_p = 1.0, 0.01        # weights up to 100
+    rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                              C.byref(_tally_stub(det)), None)
+    assert rc == mc.MC_EINVAL
 
 
 def test_mc_simulate_requires_tally_buffers():

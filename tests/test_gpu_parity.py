@@ -158,23 +158,35 @@ def test_full_size_sampled_trajectories(mc, cuda_device):
 # ------------------------------------------------------------ invariances
 
 def test_launch_shape_and_photon_ranges_are_invariant(mc, cuda_device):
+    """Fixed-point tallies make every result independent of how photons are
+    scheduled: other launch shapes give bit-identical records, images and
+    scalars, and photon ranges accumulated into one MC_FIX64 tally equal the
+    single run exactly."""
     torch = _torch()
     w = W.TINY.replace(tau=3.0, n_photons=30000)
     a = gpu_run(w, records=True)
     b = gpu_run(w, records=True, block_size=64, grid_blocks=7, table=a["table"])
-    for k in a["rec"]:
-        np.testing.assert_array_equal(a["rec"][k], b["rec"][k])
-    np.testing.assert_allclose(a["side"], b["side"], rtol=1e-12, atol=1e-12)
-    # Two photon ranges accumulated into one tally equal the single run.
-    t = a["tally"]
-    c1 = gpu_run(w, records=False, n_photons=11111, table=a["table"])
-    tal = c1["tally"]
-    gpu_run(w, records=False, n_photons=w.n_photons - 11111, photon_offset=11111, table=a["table"],
-            tally=tal, flags_extra=1)
+    c = gpu_run(w, records=True, block_size=320, grid_blocks=3, table=a["table"])
+    for other in (b, c):
+        for k in a["rec"]:
+            np.testing.assert_array_equal(a["rec"][k], other["rec"][k])
+        for k in ("side", "trans", "side_w2", "trans_w2", "scalars"):
+            np.testing.assert_array_equal(a[k], other[k])
+    # Photon ranges accumulated into one fixed-point tally equal the single run.
+    f = gpu_run(w, fix64=True, table=a["table"])
+    p1 = gpu_run(w, fix64=True, n_photons=11111, table=a["table"])
+    tal = p1["tally"]
+    gpu_run(w, fix64=True, n_photons=w.n_photons - 11111, photon_offset=11111, table=a["table"], tally=tal,
+            flags_extra=mc.MC_ACCUMULATE)
     torch.cuda.synchronize()
-    np.testing.assert_allclose(tal.side.cpu().numpy(), a["side"], rtol=1e-12, atol=1e-12)
-    np.testing.assert_allclose(tal.trans.cpu().numpy(), a["trans"], rtol=1e-12, atol=1e-12)
-    np.testing.assert_allclose(tal.scalars.cpu().numpy()[:15], a["scalars"][:15], rtol=1e-12, atol=1e-9)
+    for k in ("side", "trans", "side_w2", "trans_w2"):
+        np.testing.assert_array_equal(getattr(tal, k).cpu().numpy(), f[k])
+    np.testing.assert_allclose(tal.scalars.cpu().numpy()[:15], f["scalars"][:15], rtol=1e-15, atol=0)
+    # Fixed-point images are the double images scaled by 2^32; the +x and +z
+    # face totals are exactly the image sums.
+    np.testing.assert_array_equal(f["side"].astype(np.float64) * 2.0**-32, a["side"])
+    assert f["side"].sum() * 2.0**-32 == f["scalars"][1]
+    assert f["trans"].sum() * 2.0**-32 == f["scalars"][5]
 
 
 def test_zero_and_single_photon(mc, cuda_device):
