@@ -51,6 +51,25 @@ CENSUS = {"step": 91, "interaction": 49, "boundary": 31, "imaged_exit": 40, "oth
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock at the 2.4 GHz peak engine clock.
 PEAK_SLOTS_PER_S = 256 * 64 * 2.4e9
 
+# HBM traffic of one walk_kernel launch on this workload, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters
+# read for a 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); valid
+# only for the kernel sources it was measured on (profiles/walk_tau4_counters.md).
+TRAFFIC = {"sources_sha256": "30ae587a4d24252b90ecb126b9cc21c638dab5575a47ddeba7bbc0e1b4d73053",
+           "fetch_kib": 326.5, "write_kib": 2103600.0, "fetch_factor": 2.0, "write_factor": 1.0}
+WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
+
+
+def measured_traffic():
+    """Bytes per launch if the walk kernel is the one the counters were taken on, else None."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in WALK_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != TRAFFIC["sources_sha256"]:
+        return None
+    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] + TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -73,10 +92,11 @@ def cpu_baseline(w, target_s: float):
     from oracle import walk as owalk
     threads = max(1, min(os.cpu_count() or 1, 16))
     wk = owalk.Walk(w)
-    pilot = wk.run(n_photons=20000, threads=threads)
-    rate = 20000 / max(pilot.seconds, 1e-6)
-    n = int(min(w.n_photons, max(20000, rate * target_s)))
+    n = 1_000_000
     res = wk.run(n_photons=n, threads=threads)
+    if res.seconds < 0.5 * target_s:           # scale the sample to about target_s
+        n = int(min(w.n_photons, n * target_s / max(res.seconds, 1e-3)))
+        res = wk.run(n_photons=n, threads=threads)
     ev = res.scalars[9]
     try:
         cpu = open("/proc/cpuinfo").read().split("model name")[1].split("\n")[0].strip(" :\t")
@@ -126,9 +146,19 @@ def main():
     walk_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.warmup + args.steps)]
 
+    # One step = the table build (device) followed by the walk on the same
+    # stream.  With the Mie phase the table is enqueued without a host wait, so
+    # steps pipeline; the HG step needs g on the host and waits for the table.
+    inv_cdf = torch.empty(w.n_cdf, dtype=torch.float32, device=dev)
+    result = torch.empty(4, dtype=torch.float64, device=dev)
+    g_hg = mc.mie_table_build(spec, dev).g if phase == W.PHASE_HG else None
+
     def step(i):
-        table = mc.mie_table_build(spec, dev)                    # device kernel; returns after sync
-        _, med, src, geo, det, run = mc.args_from_workload(w, table, block_size=args.block_size,
+        if phase == W.PHASE_MIE:
+            table = mc.mie_table_enqueue(spec, dev, inv_cdf=inv_cdf, result=result)
+        else:
+            table = mc.mie_table_build(spec, dev)
+        _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g_hg, block_size=args.block_size,
                                                            grid_blocks=args.grid_blocks)
         e0, e1 = walk_ev[i]
         e0.record(stream)
@@ -177,8 +207,10 @@ def main():
                    "cuboid_mm": list(w.size_mm), "n_cdf": w.n_cdf, "images": [w.side_px, w.trans_px],
                    "seed": w.seed, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
-                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S, "traffic": None,
-                     "kernel": "walk_kernel<MIE>" if phase == W.PHASE_MIE else "walk_kernel<HG>",
+                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S,
+                     "traffic": measured_traffic() if (args.tau == 4.0 and args.photons == 100_000_000
+                                                       and phase == W.PHASE_MIE) else None,
+                     "kernel": "mc_simulate (init, walk_kernel, finalize)",
                      "kernel_ms": walk_avg_s * 1e3, "slots_per_launch": slots},
         "photons_per_s": photons / elapsed,
         "events_per_photon": s_last[9] / s_last[10],

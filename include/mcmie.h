@@ -111,6 +111,8 @@ typedef struct {
     double *cdf;           /* device, n_angles doubles: F(theta_j), trapezoid rule, F = 1 at pi, optional */
     double *coef;          /* device, 4 * coef_capacity doubles: Re a_n, Im a_n, Re b_n, Im b_n per n (Eqs. 7-8), optional */
     int32_t coef_capacity; /* terms coef can hold; must be >= n_terms when coef is set */
+    double *result;        /* device, 4 doubles: Q_ext, Q_sca, g, n_terms as computed by the kernel
+                              (optional for mie_table_build, required for mie_table_enqueue) */
 } mie_table_t;
 
 /*
@@ -125,6 +127,15 @@ typedef struct {
  * missing buffer, MC_EDEVICE / MC_ENOMEM on runtime failure.
  */
 int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void *stream);
+
+/*
+ * The same table build, enqueued on `stream` without waiting: the device
+ * arrays and table->result are written when the stream reaches the kernel.
+ * On return the host fields x, m_rel_re, m_rel_im, n_terms and n_cdf are
+ * set; the efficiencies, g and cross-sections are NaN (read them from
+ * table->result).  For pipelines that need the table only on the device.
+ */
+int mie_table_enqueue(const mie_spec_t *spec, mie_table_t *table, void *stream);
 
 /* -------------------------------------------------------------- the walk */
 

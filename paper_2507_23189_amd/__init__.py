@@ -8,7 +8,8 @@ not been built.
 from ._capi import (MC_ACCUMULATE, MC_EDEVICE, MC_EINVAL, MC_ENOMEM, MC_EUNSUPPORTED, MC_FIX64, MC_MAX_N_ANGLES,
                     MC_MAX_N_CDF, MC_MAX_TERMS, MC_N_SCALARS, MC_OK, MC_PHASE_HG, MC_PHASE_MIE, MC_RECORD,
                     MC_SIGMA, Detector, Geometry, McError, Medium, MieSpec, MieTable, Run, Source, Tally, lib,
-                    mc_grad, mc_philox_blocks, mc_simulate, mc_version, mc_workspace_bytes, mie_table_build)
+                    mc_grad, mc_philox_blocks, mc_simulate, mc_version, mc_workspace_bytes, mie_table_build,
+                    mie_table_enqueue)
 from .args import args_from_workload
 
 __all__ = [n for n in dir() if not n.startswith("_")]

@@ -33,7 +33,7 @@ class _MieTableC(C.Structure):
                 ("sigma_ext_mm2", C.c_double), ("sigma_sca_mm2", C.c_double), ("sigma_abs_mm2", C.c_double),
                 ("n_terms", C.c_int32), ("n_cdf", C.c_int32),
                 ("inv_cdf", C.c_void_p), ("phase", C.c_void_p), ("cdf", C.c_void_p), ("coef", C.c_void_p),
-                ("coef_capacity", C.c_int32)]
+                ("coef_capacity", C.c_int32), ("result", C.c_void_p)]
 
 
 class Medium(C.Structure):
@@ -87,6 +87,7 @@ def lib():
                               "(there is no CPU fallback)")
         L = C.CDLL(LIB_PATH)
         L.mie_table_build.argtypes = [C.POINTER(MieSpec), C.POINTER(_MieTableC), C.c_void_p]
+        L.mie_table_enqueue.argtypes = [C.POINTER(MieSpec), C.POINTER(_MieTableC), C.c_void_p]
         L.mc_simulate.argtypes = [C.POINTER(Medium), C.POINTER(Source), C.POINTER(Geometry),
                                   C.POINTER(Detector), C.POINTER(Run), C.POINTER(_TallyC), C.c_void_p]
         L.mc_grad.argtypes = [C.POINTER(Medium), C.POINTER(Source), C.POINTER(Geometry), C.POINTER(Detector),
@@ -97,7 +98,7 @@ def lib():
         L.mc_workspace_bytes.restype = C.c_uint64
         L.mc_last_error.restype = C.c_char_p
         L.mc_version.restype = C.c_int
-        for f in ("mie_table_build", "mc_simulate", "mc_grad", "mc_philox_blocks"):
+        for f in ("mie_table_build", "mie_table_enqueue", "mc_simulate", "mc_grad", "mc_philox_blocks"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -135,6 +136,7 @@ class MieTable:
     phase: "object" = None         # torch float64 (n_angles,)
     cdf: "object" = None           # torch float64 (n_angles,)
     coef: "object" = None          # torch float64 (n_terms, 4): Re a, Im a, Re b, Im b
+    result: "object" = None        # torch float64 (4,): Q_ext, Q_sca, g, n_terms (device)
 
 
 def mie_table_build(spec: MieSpec, device="cuda", *, phase=False, cdf=False, coef=False,
@@ -154,6 +156,21 @@ def mie_table_build(spec: MieSpec, device="cuda", *, phase=False, cdf=False, coe
     return MieTable(t.x, complex(t.m_rel_re, t.m_rel_im), t.q_ext, t.q_sca, t.q_abs, t.g, t.sigma_ext_mm2,
                     t.sigma_sca_mm2, t.sigma_abs_mm2, t.n_terms, inv, ph, cd,
                     co[: t.n_terms] if co is not None else None)
+
+
+def mie_table_enqueue(spec: MieSpec, device="cuda", *, inv_cdf=None, result=None, stream=None) -> MieTable:
+    """Enqueue the table build without waiting (efficiencies and g stay on
+    the device in `result`).  Reuses the given buffers when passed."""
+    import torch
+    dev = torch.device(device)
+    inv = inv_cdf if inv_cdf is not None else torch.empty(max(int(spec.n_cdf), 1), dtype=torch.float32, device=dev)
+    res = result if result is not None else torch.empty(4, dtype=torch.float64, device=dev)
+    t = _MieTableC()
+    t.inv_cdf, t.result = _ptr(inv), _ptr(res)
+    with torch.cuda.device(dev):
+        _check(lib().mie_table_enqueue(C.byref(spec), C.byref(t), _stream(stream)))
+    return MieTable(t.x, complex(t.m_rel_re, t.m_rel_im), t.q_ext, t.q_sca, t.q_abs, t.g, t.sigma_ext_mm2,
+                    t.sigma_sca_mm2, t.sigma_abs_mm2, t.n_terms, inv, result=res)
 
 
 def mc_workspace_bytes(det: Detector) -> int:

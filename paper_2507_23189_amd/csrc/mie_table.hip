@@ -231,67 +231,59 @@ __global__ __launch_bounds__(kBlock) void mie_table_kernel(MieArgs a)
 std::mutex g_scratch_mu;
 double *g_scratch[64] = {nullptr};
 
-}  // namespace
-}  // namespace mcmie
-
-extern "C" int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void *stream)
+// Validate the spec and derive x, m and the series length (no device work).
+int prepare_table(const mie_spec_t *spec, const mie_table_t *table, MieArgs *args, const char *who)
 {
-    using namespace mcmie;
-    clear_error();
-    if (!spec || !table) return fail(MC_EINVAL, "mie_table_build: null spec or table");
+    if (!spec || !table) return fail(MC_EINVAL, "%s: null spec or table", who);
     const mie_spec_t s = *spec;
     if (!(s.n_medium > 0) || !(s.m_re > 0) || !(s.m_im >= 0) || !(s.diameter_um > 0) ||
         !(s.wavelength_nm > 0) || !std::isfinite(s.n_medium * s.m_re * s.m_im * s.diameter_um *
                                                    s.wavelength_nm))
-        return fail(MC_EINVAL, "mie_table_build: indices, diameter and wavelength must be finite, "
-                               "positive (m_im >= 0)");
+        return fail(MC_EINVAL, "%s: indices, diameter and wavelength must be finite, positive (m_im >= 0)", who);
     if (s.n_angles < 3 || s.n_angles > MC_MAX_N_ANGLES)
-        return fail(MC_EINVAL, "mie_table_build: n_angles %d outside 3..%d", s.n_angles, MC_MAX_N_ANGLES);
+        return fail(MC_EINVAL, "%s: n_angles %d outside 3..%d", who, s.n_angles, MC_MAX_N_ANGLES);
     if (s.n_cdf < 2 || s.n_cdf > MC_MAX_N_CDF)
-        return fail(MC_EINVAL, "mie_table_build: n_cdf %d outside 2..%d", s.n_cdf, MC_MAX_N_CDF);
-    if (!table->inv_cdf) return fail(MC_EINVAL, "mie_table_build: inv_cdf buffer is required");
+        return fail(MC_EINVAL, "%s: n_cdf %d outside 2..%d", who, s.n_cdf, MC_MAX_N_CDF);
+    if (!table->inv_cdf) return fail(MC_EINVAL, "%s: inv_cdf buffer is required", who);
 
     // Parameter processing (Sec. 3.1.1): x = pi d n_med / lambda0 (Eq. 3 with
     // the wavelength in the medium), m relative to the medium (Eq. 4).
     const double x = M_PI * s.diameter_um * 1e3 * s.n_medium / s.wavelength_nm;
     const double m_re = s.m_re / s.n_medium, m_im = s.m_im / s.n_medium;
     const double mx_abs = x * std::hypot(m_re, m_im);
-    if (!(x >= 1e-6)) return fail(MC_EINVAL, "mie_table_build: size parameter %g below 1e-6", x);
+    if (!(x >= 1e-6)) return fail(MC_EINVAL, "%s: size parameter %g below 1e-6", who, x);
     const int n_terms = (int)std::lround(x + 4.0 * std::cbrt(x) + 2.0);   // Wiscombe 1980
     if (n_terms > MC_MAX_TERMS)
-        return fail(MC_EINVAL, "mie_table_build: %d series terms exceed %d (x = %g)", n_terms,
-                    MC_MAX_TERMS, x);
+        return fail(MC_EINVAL, "%s: %d series terms exceed %d (x = %g)", who, n_terms, MC_MAX_TERMS, x);
     if (table->coef && table->coef_capacity < n_terms)
-        return fail(MC_EINVAL, "mie_table_build: coef holds %d terms, %d needed", table->coef_capacity,
-                    n_terms);
+        return fail(MC_EINVAL, "%s: coef holds %d terms, %d needed", who, table->coef_capacity, n_terms);
     // Downward start: the start error decays slowly across the turning point
     // n ~ |mx|, whose width grows like |mx|^(1/3).
     const int n_start = (int)std::ceil(std::max((double)n_terms, mx_abs)) + 16 +
                         (int)std::ceil(8.0 * std::cbrt(mx_abs));
 
-    int dev = 0;
-    MC_HIP_CHECK(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return fail(MC_EDEVICE, "device index %d out of range", dev);
-    std::lock_guard<std::mutex> lock(g_scratch_mu);
-    if (!g_scratch[dev]) {
-        void *p = nullptr;
-        if (hipMalloc(&p, 8 * sizeof(double)) != hipSuccess)
-            return fail(MC_ENOMEM, "mie_table_build: scratch allocation failed");
-        g_scratch[dev] = (double *)p;
-    }
-    hipStream_t st = (hipStream_t)stream;
-    MieArgs args{x, m_re, m_im, n_terms, n_start, s.n_angles, s.n_cdf,
-                 table->inv_cdf, table->phase, table->cdf, table->coef, g_scratch[dev]};
+    *args = MieArgs{x, m_re, m_im, n_terms, n_start, s.n_angles, s.n_cdf,
+                    table->inv_cdf, table->phase, table->cdf, table->coef, nullptr};
+    return MC_OK;
+}
+
+// Launch the prepared table kernel on `st`, results to `result` (device).
+int launch_table(MieArgs args, mie_table_t *table, hipStream_t st, double *result)
+{
+    args.result = result;
     hipLaunchKernelGGL(mie_table_kernel, dim3(1), dim3(kBlock), 0, st, args);
     MC_HIP_CHECK(hipGetLastError());
-    double res[4];
-    MC_HIP_CHECK(hipMemcpyAsync(res, g_scratch[dev], sizeof res, hipMemcpyDeviceToHost, st));
-    MC_HIP_CHECK(hipStreamSynchronize(st));
+    table->x = args.x;
+    table->m_rel_re = args.m_re;
+    table->m_rel_im = args.m_im;
+    table->n_terms = args.n_terms;
+    table->n_cdf = args.n_cdf;
+    return MC_OK;
+}
 
+void set_scalars(mie_table_t *table, const mie_spec_t &s, const double res[3])
+{
     const double geo_mm2 = M_PI * (s.diameter_um * 1e-3) * (s.diameter_um * 1e-3) / 4.0;   // Eq. 14
-    table->x = x;
-    table->m_rel_re = m_re;
-    table->m_rel_im = m_im;
     table->q_ext = res[0];
     table->q_sca = res[1];
     table->q_abs = res[0] - res[1];
@@ -299,7 +291,52 @@ extern "C" int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void 
     table->sigma_ext_mm2 = res[0] * geo_mm2;
     table->sigma_sca_mm2 = res[1] * geo_mm2;
     table->sigma_abs_mm2 = (res[0] - res[1]) * geo_mm2;
-    table->n_terms = n_terms;
-    table->n_cdf = s.n_cdf;
+}
+
+}  // namespace
+}  // namespace mcmie
+
+extern "C" int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void *stream)
+{
+    using namespace mcmie;
+    clear_error();
+    hipStream_t st = (hipStream_t)stream;
+    MieArgs args;
+    if (int rc = prepare_table(spec, table, &args, "mie_table_build")) return rc;
+    double *result = table->result;
+    std::unique_lock<std::mutex> lock(g_scratch_mu, std::defer_lock);
+    if (!result) {
+        // No caller buffer: the library's per-device scratch, held until the
+        // results are back on the host.
+        int dev = 0;
+        MC_HIP_CHECK(hipGetDevice(&dev));
+        if (dev < 0 || dev >= 64) return fail(MC_EDEVICE, "device index %d out of range", dev);
+        lock.lock();
+        if (!g_scratch[dev]) {
+            void *p = nullptr;
+            if (hipMalloc(&p, 8 * sizeof(double)) != hipSuccess)
+                return fail(MC_ENOMEM, "mie_table_build: scratch allocation failed");
+            g_scratch[dev] = (double *)p;
+        }
+        result = g_scratch[dev];
+    }
+    if (int rc = launch_table(args, table, st, result)) return rc;
+    double res[4];
+    MC_HIP_CHECK(hipMemcpyAsync(res, result, sizeof res, hipMemcpyDeviceToHost, st));
+    MC_HIP_CHECK(hipStreamSynchronize(st));
+    set_scalars(table, *spec, res);
+    return MC_OK;
+}
+
+extern "C" int mie_table_enqueue(const mie_spec_t *spec, mie_table_t *table, void *stream)
+{
+    using namespace mcmie;
+    clear_error();
+    MieArgs args;
+    if (int rc = prepare_table(spec, table, &args, "mie_table_enqueue")) return rc;
+    if (!table->result) return fail(MC_EINVAL, "mie_table_enqueue: result buffer is required");
+    if (int rc = launch_table(args, table, (hipStream_t)stream, table->result)) return rc;
+    const double nan3[3] = {NAN, NAN, NAN};
+    set_scalars(table, *spec, nan3);
     return MC_OK;
 }

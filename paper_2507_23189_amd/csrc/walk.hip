@@ -500,11 +500,21 @@ __global__ __launch_bounds__(256) void finalize_images(const unsigned long long 
         if (is_side) sum_side += v; else sum_trans += v;
     }
     if (face_side) {
+        // One atomic per block and face: same-address global atomics serialise.
+        __shared__ unsigned long long s_part[2][4];
         sum_side = wave_sum(sum_side);
         sum_trans = wave_sum(sum_trans);
+        const int wave = threadIdx.x >> 6;
         if (__lane_id() == 0) {
-            if (sum_side) atomicAdd(face_side, sum_side);
-            if (sum_trans) atomicAdd(face_trans, sum_trans);
+            s_part[0][wave] = sum_side;
+            s_part[1][wave] = sum_trans;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long a0 = s_part[0][0] + s_part[0][1] + s_part[0][2] + s_part[0][3];
+            const unsigned long long a1 = s_part[1][0] + s_part[1][1] + s_part[1][2] + s_part[1][3];
+            if (a0) atomicAdd(face_side, a0);
+            if (a1) atomicAdd(face_trans, a1);
         }
     }
 }
@@ -730,7 +740,7 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     }
     // ---- finalize: per-XCD copies to the caller's images, scalars to doubles ----
     const bool fix64 = (det.flags & MC_FIX64) != 0;
-    const unsigned fin_grid = (unsigned)std::min<uint64_t>(2048, (n_pix_all + 255) / 256);
+    const unsigned fin_grid = (unsigned)std::min<uint64_t>(512, (n_pix_all + 255) / 256);
     auto fin = fix64 ? finalize_images<true> : finalize_images<false>;
     hipLaunchKernelGGL(fin, dim3(fin_grid), dim3(256), 0, st, a.ws_img, n_pix_all, a.n_side, t.side, t.trans,
                        ws + MC_S_FACE + 1, ws + MC_S_FACE + 5);

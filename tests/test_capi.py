@@ -29,7 +29,7 @@ def _declared_functions():
 def test_header_declares_the_entry_points():
     names = set(_declared_functions())
     assert {"mie_table_build", "mc_simulate", "mc_grad", "mc_last_error", "mc_philox_blocks",
-            "mc_version", "mc_workspace_bytes"} <= names
+            "mc_version", "mc_workspace_bytes", "mie_table_enqueue"} <= names
 
 
 def test_library_exports_every_declared_symbol():
@@ -160,6 +160,16 @@ def test_mie_table_build_rejects_invalid_spec(field, value):
     rc = mc.lib().mie_table_build(C.byref(spec), C.byref(t), None)
     assert rc == mc.MC_EINVAL
     assert mc.lib().mc_last_error().startswith(b"mie_table_build")
+
+
+def test_mie_table_enqueue_requires_result_buffer():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, *_ = _valid_args()
+    t = mc._capi._MieTableC()
+    t.inv_cdf = 0x1000
+    assert mc.lib().mie_table_enqueue(C.byref(spec), C.byref(t), None) == mc.MC_EINVAL
+    assert b"result" in mc.lib().mc_last_error()
 
 
 def test_mc_grad_reports_unsupported():

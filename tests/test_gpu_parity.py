@@ -93,6 +93,19 @@ def test_mie_table_parity(mc, cuda_device, case):
     assert np.all(np.abs(inv.astype(np.float64) - ref32.astype(np.float64)) <= ulp + 1e-30)
 
 
+def test_mie_table_enqueue_matches_build(mc, cuda_device):
+    torch = _torch()
+    w = W.HEADLINE
+    spec, *_ = mc.args_from_workload(w)
+    t = mc.mie_table_build(spec, cuda_device)
+    e = mc.mie_table_enqueue(spec, cuda_device)
+    torch.cuda.synchronize()
+    assert math.isnan(e.q_ext) and e.n_terms == t.n_terms and e.x == t.x
+    torch.testing.assert_close(e.inv_cdf, t.inv_cdf, rtol=0, atol=0)
+    r = e.result.cpu().numpy()
+    assert (r[0], r[1], r[2], r[3]) == (t.q_ext, t.q_sca, t.g, t.n_terms)
+
+
 # ------------------------------------------------------- trajectories, images
 
 def _oracle(w, records=True, ids=None, g=None):

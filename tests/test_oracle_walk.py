@@ -256,3 +256,20 @@ def test_photon_ranges_compose(c1_table):
     ids = np.array([17, 3999, 0, 2048], dtype=np.uint64)
     c = wk.run(ids=ids, records=True)
     np.testing.assert_array_equal(c.frec, full.frec[:, ids.astype(int)])
+
+
+def test_exit_refraction_restores_the_incident_direction(c1_table):
+    # tau = 0: the beam refracts in at z = 0 and out at the parallel face
+    # z = L (Snell twice), so photons leaving +z on their first wall hit carry
+    # the incident direction again; those reflected first leave -z mirrored.
+    d = np.array([0.3, -0.2, 0.9])
+    d /= np.linalg.norm(d)
+    w = W.TINY.replace(tau=0.0, src_pos_mm=(2.0, 8.0, 0.0), src_dir=tuple(d), size_mm=(50.0, 50.0, 10.0),
+                       n_photons=2000)
+    r = owalk.Walk(w, c1_table).run(records=True)
+    out = np.stack([r.rec("dx"), r.rec("dy"), r.rec("dz")], 1)
+    first = (r.rec("face") == 5) & (r.rec("steps") == 1)
+    assert first.sum() > 1500
+    np.testing.assert_allclose(out[first], np.broadcast_to(d, out[first].shape), atol=1e-14)
+    back = r.rec("face") == 4
+    np.testing.assert_allclose(out[back], np.broadcast_to(d * [1, 1, -1], out[back].shape), atol=1e-14)
