@@ -52,6 +52,8 @@ extern "C" {
 #define MC_RECORD 4u          /* write per-photon end records (mc_tally_t.rec_*) */
 #define MC_FIX64 8u           /* images (and squared-weight images) are int64 fixed point,
                                  value = weight * 2^32; otherwise they are double */
+#define MC_MOMENTS 16u        /* also tally, per side-image pixel, the path moments
+                                 sum(w k), sum(w L), sum(w^2 k), sum(w^2 L) used by mc_grad (double) */
 
 /* Scalar tallies: mc_tally_t.scalars holds MC_N_SCALARS doubles. */
 #define MC_S_FACE 0           /* 0..5: weight leaving faces -x, +x, -y, +y, -z, +z */
@@ -147,6 +149,8 @@ typedef struct {
     int32_t n_cdf;         /* MIE: entries of inv_cdf, 2..MC_MAX_N_CDF */
     const float *inv_cdf;  /* MIE: device inverse table as written by mie_table_build */
     double g;              /* HG: asymmetry in (-1, 1) */
+    double sigma_sca_mm2;  /* particle cross-sections (Eq. 14), used only by mc_grad for the */
+    double sigma_abs_mm2;  /* concentration derivative; 0 and 0 make that derivative NaN */
 } mc_medium_t;
 
 /* Collimated pencil beam entering the z = 0 face (Sec. 3.1.3: parallel beam,
@@ -198,9 +202,13 @@ typedef struct {
     int32_t *rec_i;        /* MC_RECORD: MC_REC_I_N * rec_rows int32 */
     float *rec_f;          /* MC_RECORD: MC_REC_F_N * rec_rows float */
     uint64_t rec_rows;     /* MC_RECORD: rows available (0: record nothing, buffers may be NULL) */
-    void *workspace;       /* device scratch of at least mc_workspace_bytes(detector) bytes, 256-byte
+    void *workspace;       /* device scratch of at least mc_workspace_bytes(detector) bytes, 8-byte
                               aligned (required); its contents on entry do not matter */
     uint64_t workspace_bytes;
+    double *side_wk;       /* MC_MOMENTS: side-image shape, sum over detected photons of w k */
+    double *side_wl;       /* MC_MOMENTS: side-image shape, sum over detected photons of w L (mm) */
+    double *side_w2k;      /* MC_MOMENTS: side-image shape, sum of w^2 k */
+    double *side_w2l;      /* MC_MOMENTS: side-image shape, sum of w^2 L */
 } mc_tally_t;
 
 /*
@@ -229,14 +237,33 @@ int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_g
                 void *stream);
 
 /*
- * Reserved for the perturbation Monte Carlo adjoint (derivatives of a loss
- * on the side image with respect to mu_sca, mu_abs and concentration, Eq. 15
- * to Eq. 17).  Not implemented in this build: validates nothing and returns
- * MC_EUNSUPPORTED.
+ * Perturbation Monte Carlo adjoint of a loss on the side image.  A detected
+ * photon's weight, for a path with k interactions and length L sampled with
+ * free paths from Eq. 15 and weighted by Eq. 16, is proportional to
+ * mu_sca^k exp(-(mu_sca + mu_abs) L); its score is s = k / mu_sca - L for
+ * mu_sca and s = -L for mu_abs, and dI_p = D_p = sum over the photons in pixel
+ * p of w s (from the moment images M_k = sum w k, M_L = sum w L).
+ *
+ * Given g = dLoss/dI (device, side-image shape) and a tally filled by
+ * mc_simulate with MC_MOMENTS for the same medium and geometry:
+ *     G = sum_p g_p D_p                      (d2loss_dside2 NULL)
+ *     G = sum_p (g_p D_p - h_p Q_p)          (h = d2loss_dside2, device)
+ * with Q_p = sum w^2 s over the photons in pixel p.  The first is the exact
+ * derivative of the loss of this sample with the paths held fixed; when g is
+ * computed from the same sample (g = 2 (I - T) for an L2 loss, h = 2) it is
+ * biased by the sample's self-correlation, and the second form removes that
+ * bias to first order, estimating the gradient of Loss(E[I]).
+ * Writes on the host out_grad[0] = G for mu_sca, out_grad[1] = G for mu_abs,
+ * out_grad[2] = sigma_sca out_grad[0] + sigma_abs out_grad[1], the derivative
+ * with respect to the particle concentration c in 1/mm^3 (Eq. 17, with
+ * mu_sca = c sigma_sca and mu_abs = mu_abs,medium + c sigma_abs; NaN when both
+ * sigmas are 0).  The dot products run in one device workgroup (fixed order,
+ * deterministic); the call waits for the stream.  Roulette's dependence on
+ * the weight threshold is not differentiated.
  */
-int mc_grad(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
-            const mc_detector_t *detector, const mc_run_t *run, const double *dloss_dside,
-            double out_grad[3], void *stream);
+int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry, const mc_detector_t *detector,
+            const mc_tally_t *tally, const double *dloss_dside, const double *d2loss_dside2, double out_grad[3],
+            void *stream);
 
 /*
  * The random numbers the walk draws: for each of n_ids photon ids (device

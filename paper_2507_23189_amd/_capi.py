@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libmcmie.so")
 
 MC_OK, MC_EINVAL, MC_EDEVICE, MC_ENOMEM, MC_EUNSUPPORTED = 0, -1, -2, -3, -4
 MC_PHASE_MIE, MC_PHASE_HG = 0, 1
-MC_ACCUMULATE, MC_SIGMA, MC_RECORD, MC_FIX64 = 1, 2, 4, 8
+MC_ACCUMULATE, MC_SIGMA, MC_RECORD, MC_FIX64, MC_MOMENTS = 1, 2, 4, 8, 16
 MC_N_SCALARS = 16
 MC_S_FACE, MC_S_ABSORBED, MC_S_ROULETTE_NET, MC_S_CAPPED_W, MC_S_EVENTS = 0, 6, 7, 8, 9
 MC_S_PHOTONS, MC_S_ROULETTE_KILLS, MC_S_CAPPED, MC_S_REFLECTIONS, MC_S_STEPS, MC_S_RESERVED = 10, 11, 12, 13, 14, 15
@@ -38,7 +38,8 @@ class _MieTableC(C.Structure):
 
 class Medium(C.Structure):
     _fields_ = [("tau", C.c_double), ("albedo", C.c_double), ("phase", C.c_int32), ("n_cdf", C.c_int32),
-                ("inv_cdf", C.c_void_p), ("g", C.c_double)]
+                ("inv_cdf", C.c_void_p), ("g", C.c_double), ("sigma_sca_mm2", C.c_double),
+                ("sigma_abs_mm2", C.c_double)]
 
 
 class Source(C.Structure):
@@ -65,7 +66,8 @@ class _TallyC(C.Structure):
     _fields_ = [("side", C.c_void_p), ("trans", C.c_void_p), ("side_w2", C.c_void_p),
                 ("trans_w2", C.c_void_p), ("scalars", C.c_void_p), ("rec_i", C.c_void_p),
                 ("rec_f", C.c_void_p), ("rec_rows", C.c_uint64), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_uint64)]
+                ("workspace_bytes", C.c_uint64), ("side_wk", C.c_void_p), ("side_wl", C.c_void_p),
+                ("side_w2k", C.c_void_p), ("side_w2l", C.c_void_p)]
 
 
 class McError(RuntimeError):
@@ -90,8 +92,8 @@ def lib():
         L.mie_table_enqueue.argtypes = [C.POINTER(MieSpec), C.POINTER(_MieTableC), C.c_void_p]
         L.mc_simulate.argtypes = [C.POINTER(Medium), C.POINTER(Source), C.POINTER(Geometry),
                                   C.POINTER(Detector), C.POINTER(Run), C.POINTER(_TallyC), C.c_void_p]
-        L.mc_grad.argtypes = [C.POINTER(Medium), C.POINTER(Source), C.POINTER(Geometry), C.POINTER(Detector),
-                              C.POINTER(Run), C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
+        L.mc_grad.argtypes = [C.POINTER(Medium), C.POINTER(Geometry), C.POINTER(Detector), C.POINTER(_TallyC),
+                              C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
         L.mc_philox_blocks.argtypes = [C.c_uint64, C.c_uint32, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
                                        C.c_void_p, C.c_void_p]
         L.mc_workspace_bytes.argtypes = [C.POINTER(Detector)]
@@ -189,9 +191,14 @@ class Tally:
     trans_w2: "object" = None
     rec_i: "object" = None          # (MC_REC_I_N, rows) int32
     rec_f: "object" = None          # (MC_REC_F_N, rows) float32
+    side_wk: "object" = None        # MC_MOMENTS: float64, side-image shape
+    side_wl: "object" = None
+    side_w2k: "object" = None
+    side_w2l: "object" = None
 
     @staticmethod
-    def alloc(det: Detector, device="cuda", *, sigma=False, record_rows=0, fix64=False) -> "Tally":
+    def alloc(det: Detector, device="cuda", *, sigma=False, record_rows=0, fix64=False,
+              moments=False) -> "Tally":
         import torch
         dev = torch.device(device)
         img = dict(dtype=torch.int64 if fix64 else torch.float64, device=dev)
@@ -204,6 +211,11 @@ class Tally:
         if sigma:
             t.side_w2 = torch.empty_like(t.side)
             t.trans_w2 = torch.empty_like(t.trans)
+        if moments:
+            t.side_wk = torch.empty((det.side_ny, det.side_nx), dtype=torch.float64, device=dev)
+            t.side_wl = torch.empty_like(t.side_wk)
+            t.side_w2k = torch.empty_like(t.side_wk)
+            t.side_w2l = torch.empty_like(t.side_wk)
         if record_rows:
             t.rec_i = torch.empty((MC_REC_I_N, record_rows), dtype=torch.int32, device=dev)
             t.rec_f = torch.empty((MC_REC_F_N, record_rows), dtype=torch.float32, device=dev)
@@ -217,6 +229,8 @@ class Tally:
         c.rec_rows = 0 if self.rec_i is None else int(self.rec_i.shape[1])
         c.workspace = _ptr(self.workspace)
         c.workspace_bytes = 0 if self.workspace is None else self.workspace.numel() * 8
+        c.side_wk, c.side_wl = _ptr(self.side_wk), _ptr(self.side_wl)
+        c.side_w2k, c.side_w2l = _ptr(self.side_w2k), _ptr(self.side_w2l)
         return c
 
 
@@ -228,11 +242,16 @@ def mc_simulate(medium: Medium, source: Source, geometry: Geometry, detector: De
                              C.byref(run), C.byref(tc), _stream(stream)))
 
 
-def mc_grad(medium: Medium, source: Source, geometry: Geometry, detector: Detector, run: Run,
-            dloss_dside, stream=None):
+def mc_grad(medium: Medium, geometry: Geometry, detector: Detector, tally: Tally, dloss_dside,
+            d2loss_dside2=None, stream=None):
+    """(dLoss/dmu_sca, dLoss/dmu_abs, dLoss/dconcentration) from the moment
+    images of `tally` (filled by mc_simulate with MC_MOMENTS), dLoss/dI of the
+    side image and, optionally, the loss's diagonal second derivative for the
+    self-correlation correction (float64 device tensors).  Waits for the stream."""
     out = (C.c_double * 3)()
-    _check(lib().mc_grad(C.byref(medium), C.byref(source), C.byref(geometry), C.byref(detector), C.byref(run),
-                         _ptr(dloss_dside), out, _stream(stream)))
+    tc = tally._c()
+    _check(lib().mc_grad(C.byref(medium), C.byref(geometry), C.byref(detector), C.byref(tc),
+                         _ptr(dloss_dside), _ptr(d2loss_dside2), out, _stream(stream)))
     return tuple(out)
 
 

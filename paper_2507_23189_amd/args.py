@@ -15,7 +15,9 @@ def args_from_workload(w, table=None, *, g=None, flags=0, record_stride=1, block
                    wavelength_nm=p.wavelength_nm, n_angles=w.n_angles, n_cdf=w.n_cdf)
     med = Medium(tau=w.tau, albedo=w.albedo, phase=w.phase, n_cdf=w.n_cdf if w.phase == MC_PHASE_MIE else 0,
                  inv_cdf=(table.inv_cdf.data_ptr() if (table is not None and w.phase == MC_PHASE_MIE) else None),
-                 g=(g if g is not None else (table.g if table is not None else 0.0)))
+                 g=(g if g is not None else (table.g if table is not None else 0.0)),
+                 sigma_sca_mm2=(table.sigma_sca_mm2 if table is not None else 0.0) or 0.0,
+                 sigma_abs_mm2=(table.sigma_abs_mm2 if table is not None else 0.0) or 0.0)
     src = Source()
     for i in range(3):
         src.pos_mm[i] = w.src_pos_mm[i]

@@ -73,6 +73,8 @@ struct WalkArgs {
     uint64_t n_pix;
     int32_t *rec_i;
     float *rec_f;
+    double *side_wk, *side_wl;     // MC_MOMENTS: per side pixel, sum w k and sum w L
+    double *side_w2k, *side_w2l;   //             and sum w^2 k, sum w^2 L
     uint64_t rec_rows, record_stride;
 };
 
@@ -129,9 +131,12 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 constexpr int kQueue = 64;                 // queued image exits per wave
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;   // free tally-cache slot
 
-template <int PHASE, bool SIGMA, bool RECORD>
+constexpr int kOptSigma = 1, kOptRecord = 2, kOptMoments = 4;
+
+template <int PHASE, int OPT>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void walk_kernel(WalkArgs a)
 {
+    constexpr bool SIGMA = OPT & kOptSigma, RECORD = OPT & kOptRecord, MOMENTS = OPT & kOptMoments;
     // LDS layout: inverse table (n_cdf floats, padded to 4), 16 scalar doubles,
     // tally cache (slots doubles of weight, [SIGMA] slots doubles of squared
     // weight, slots uint32 keys), per-wave exit queues (3 x kQueue floats).
@@ -368,6 +373,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             if (ended) {
                 // Faces +x and +z are totalled from their images when finalizing.
                 if (cause == 0 && face != 1 && face != 5) atomicAdd(&s_scal[MC_S_FACE + face], fix(w));
+                if (MOMENTS && cause == 0 && face == 1) {
+                    // Path moments of the side image (perturbation Monte Carlo).
+                    const uint32_t key = (uint32_t)(pixel(py, a.size[1], a.side_ny) * a.side_nx +
+                                                    pixel(pz, a.size[2], a.side_nx));
+                    const double wd = (double)w, wk = wd * (double)k, wl = wd * (double)L;
+                    atomicAdd(a.side_wk + key, wk);
+                    atomicAdd(a.side_wl + key, wl);
+                    atomicAdd(a.side_w2k + key, wd * wk);
+                    atomicAdd(a.side_w2l + key, wd * wl);
+                }
                 acc_abs += fix(A);
                 acc_events += k;
                 acc_steps += step;
@@ -454,7 +469,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 // not memset, so the sequence stays valid under stream capture.)
 __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long long *side, unsigned long long *trans,
                             unsigned long long *side_w2, unsigned long long *trans_w2, size_t n_side, size_t n_trans,
-                            double *scalars, int32_t *rec_i, float *rec_f, size_t n_rec, int zero_all)
+                            double *scalars, int32_t *rec_i, float *rec_f, size_t n_rec, double *side_wk,
+                            double *side_wl, double *side_w2k, double *side_w2l, int zero_all)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -463,6 +479,12 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
     for (size_t i = t0; i < n_side; i += stride) {
         side[i] = 0ull;                 // +0.0 and int64 0 share the bit pattern
         if (side_w2) side_w2[i] = 0ull;
+        if (side_wk) {
+            side_wk[i] = 0.0;
+            side_wl[i] = 0.0;
+            side_w2k[i] = 0.0;
+            side_w2l[i] = 0.0;
+        }
     }
     for (size_t i = t0; i < n_trans; i += stride) {
         trans[i] = 0ull;
@@ -545,6 +567,32 @@ __global__ void philox_blocks_kernel(uint32_t k0, uint32_t k1, uint32_t instance
     out[4 * t + 3] = r.r3;
 }
 
+// sum_p g_p M_k[p], sum_p g_p M_L[p] and, with h, sum_p h_p M2_k[p] and
+// sum_p h_p M2_L[p], in one workgroup (fixed order, deterministic).
+__global__ __launch_bounds__(1024) void grad_dot(const double *g, const double *h, const double *wk,
+                                                 const double *wl, const double *w2k, const double *w2l,
+                                                 uint64_t n, double *out)
+{
+    __shared__ double s_red[4][1024];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        acc[0] = fma(g[i], wk[i], acc[0]);
+        acc[1] = fma(g[i], wl[i], acc[1]);
+        if (h) {
+            acc[2] = fma(h[i], w2k[i], acc[2]);
+            acc[3] = fma(h[i], w2l[i], acc[3]);
+        }
+    }
+    for (int c = 0; c < 4; ++c) s_red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int c = 0; c < 4; ++c) s_red[c][threadIdx.x] += s_red[c][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = s_red[threadIdx.x][0];
+}
+
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 // Workspace layout: 32 uint64 scalar words, then kCopies fixed-point copies of
@@ -612,8 +660,10 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     if (rn.block_size != 0 && (rn.block_size < 64 || rn.block_size > 1024 || rn.block_size % 64))
         return fail(MC_EINVAL, "mc_simulate: block_size must be a multiple of 64 in 64..1024");
     if (rn.grid_blocks < 0) return fail(MC_EINVAL, "mc_simulate: grid_blocks must be >= 0");
-    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64))
+    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64 | MC_MOMENTS))
         return fail(MC_EINVAL, "mc_simulate: unknown detector flags 0x%x", det.flags);
+    if ((det.flags & MC_MOMENTS) && (!t.side_wk || !t.side_wl || !t.side_w2k || !t.side_w2l))
+        return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS needs side_wk, side_wl, side_w2k and side_w2l");
     if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < workspace_words(det) * 8)
         return fail(MC_EINVAL, "mc_simulate: workspace needs %llu bytes, 8-byte aligned",
                     (unsigned long long)(workspace_words(det) * 8));
@@ -689,6 +739,10 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     a.ws_img2 = (det.flags & MC_SIGMA) ? a.ws_img + (uint64_t)kCopies * n_pix_all : nullptr;
     a.n_pix = n_pix_all;
     a.rec_i = t.rec_i; a.rec_f = t.rec_f;
+    a.side_wk = (det.flags & MC_MOMENTS) ? t.side_wk : nullptr;
+    a.side_wl = (det.flags & MC_MOMENTS) ? t.side_wl : nullptr;
+    a.side_w2k = (det.flags & MC_MOMENTS) ? t.side_w2k : nullptr;
+    a.side_w2l = (det.flags & MC_MOMENTS) ? t.side_w2l : nullptr;
     a.rec_rows = (det.flags & MC_RECORD) ? t.rec_rows : 0;
     a.record_stride = rn.record_stride >= 1 ? rn.record_stride : 1;
 
@@ -723,16 +777,20 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     hipLaunchKernelGGL(init_kernel, dim3(1024), dim3(256), 0, st, ws, (size_t)workspace_words(det),
                        (unsigned long long *)t.side, (unsigned long long *)t.trans,
                        sig ? (unsigned long long *)t.side_w2 : nullptr, sig ? (unsigned long long *)t.trans_w2 : nullptr,
-                       n_side, n_trans, t.scalars, a.rec_i, a.rec_f, (size_t)a.rec_rows, zero_all);
+                       n_side, n_trans, t.scalars, a.rec_i, a.rec_f, (size_t)a.rec_rows, a.side_wk, a.side_wl,
+                       a.side_w2k, a.side_w2l, zero_all);
     MC_HIP_CHECK(hipGetLastError());
-    void (*kern)(WalkArgs) = nullptr;
-#define MC_PICK(P, S, R) \
-    if (m.phase == P && sig == S && rec == R) kern = walk_kernel<P, S, R>;
-    MC_PICK(MC_PHASE_MIE, false, false) MC_PICK(MC_PHASE_MIE, false, true)
-    MC_PICK(MC_PHASE_MIE, true, false) MC_PICK(MC_PHASE_MIE, true, true)
-    MC_PICK(MC_PHASE_HG, false, false) MC_PICK(MC_PHASE_HG, false, true)
-    MC_PICK(MC_PHASE_HG, true, false) MC_PICK(MC_PHASE_HG, true, true)
-#undef MC_PICK
+    const int opt = (sig ? kOptSigma : 0) | (rec ? kOptRecord : 0) | ((det.flags & MC_MOMENTS) ? kOptMoments : 0);
+    using Kern = void (*)(WalkArgs);
+    static const Kern mie_kernels[8] = {walk_kernel<MC_PHASE_MIE, 0>, walk_kernel<MC_PHASE_MIE, 1>,
+                                        walk_kernel<MC_PHASE_MIE, 2>, walk_kernel<MC_PHASE_MIE, 3>,
+                                        walk_kernel<MC_PHASE_MIE, 4>, walk_kernel<MC_PHASE_MIE, 5>,
+                                        walk_kernel<MC_PHASE_MIE, 6>, walk_kernel<MC_PHASE_MIE, 7>};
+    static const Kern hg_kernels[8] = {walk_kernel<MC_PHASE_HG, 0>, walk_kernel<MC_PHASE_HG, 1>,
+                                       walk_kernel<MC_PHASE_HG, 2>, walk_kernel<MC_PHASE_HG, 3>,
+                                       walk_kernel<MC_PHASE_HG, 4>, walk_kernel<MC_PHASE_HG, 5>,
+                                       walk_kernel<MC_PHASE_HG, 6>, walk_kernel<MC_PHASE_HG, 7>};
+    const Kern kern = m.phase == MC_PHASE_MIE ? mie_kernels[opt] : hg_kernels[opt];
     if (rn.n_photons > 0) {
         MC_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, a);
@@ -760,11 +818,44 @@ extern "C" uint64_t mc_workspace_bytes(const mc_detector_t *detector)
     return mcmie::workspace_words(*detector) * 8;
 }
 
-extern "C" int mc_grad(const mc_medium_t *, const mc_source_t *, const mc_geometry_t *, const mc_detector_t *,
-                       const mc_run_t *, const double *, double *, void *)
+extern "C" int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry, const mc_detector_t *detector,
+                       const mc_tally_t *tally, const double *dloss_dside, const double *d2loss_dside2,
+                       double out_grad[3], void *stream)
 {
-    mcmie::clear_error();
-    return mcmie::fail(MC_EUNSUPPORTED, "mc_grad: the adjoint walk is not implemented in this build");
+    using namespace mcmie;
+    clear_error();
+    if (!medium || !geometry || !detector || !tally || !dloss_dside || !out_grad)
+        return fail(MC_EINVAL, "mc_grad: null argument");
+    const mc_medium_t m = *medium;
+    const mc_geometry_t geo = *geometry;
+    const mc_detector_t det = *detector;
+    const mc_tally_t t = *tally;
+    if (!finite_pos(geo.size_mm[2]) || !(m.tau > 0.0) || !std::isfinite(m.tau) || !(m.albedo > 0.0 && m.albedo <= 1.0))
+        return fail(MC_EINVAL, "mc_grad: needs tau > 0, albedo in (0, 1] and size_mm[2] > 0");
+    if (det.side_nx < 1 || det.side_ny < 1) return fail(MC_EINVAL, "mc_grad: side image dimensions must be >= 1");
+    if (!t.side_wk || !t.side_wl || !t.side_w2k || !t.side_w2l)
+        return fail(MC_EINVAL, "mc_grad: the tally has no moment images (MC_MOMENTS)");
+    if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < kWsScalarWords * 8)
+        return fail(MC_EINVAL, "mc_grad: workspace of at least %llu bytes required",
+                    (unsigned long long)(kWsScalarWords * 8));
+    const double mu_t = m.tau / geo.size_mm[2];
+    const double mu_s = m.albedo * mu_t;
+    hipStream_t st = (hipStream_t)stream;
+    double *dots = (double *)t.workspace + 16;    // scalar words 16..19
+    const uint64_t n = (uint64_t)det.side_nx * det.side_ny;
+    hipLaunchKernelGGL(grad_dot, dim3(1), dim3(1024), 0, st, dloss_dside, d2loss_dside2, (const double *)t.side_wk,
+                       (const double *)t.side_wl, (const double *)t.side_w2k, (const double *)t.side_w2l, n, dots);
+    MC_HIP_CHECK(hipGetLastError());
+    double d[4];
+    MC_HIP_CHECK(hipMemcpyAsync(d, dots, sizeof d, hipMemcpyDeviceToHost, st));
+    MC_HIP_CHECK(hipStreamSynchronize(st));
+    // D = M_k / mu_s - M_L (mu_sca), -M_L (mu_abs); Q likewise from the w^2 moments.
+    const double gq_s = d2loss_dside2 ? d[2] / mu_s - d[3] : 0.0, gq_a = d2loss_dside2 ? -d[3] : 0.0;
+    out_grad[0] = (d[0] / mu_s - d[1]) - gq_s;
+    out_grad[1] = -d[1] - gq_a;
+    const bool have_sigma = m.sigma_sca_mm2 != 0.0 || m.sigma_abs_mm2 != 0.0;
+    out_grad[2] = have_sigma ? m.sigma_sca_mm2 * out_grad[0] + m.sigma_abs_mm2 * out_grad[1] : NAN;
+    return MC_OK;
 }
 
 extern "C" int mc_philox_blocks(uint64_t seed, uint32_t instance, const uint64_t *ids, uint64_t n_ids,

@@ -172,8 +172,27 @@ def test_mie_table_enqueue_requires_result_buffer():
     assert b"result" in mc.lib().mc_last_error()
 
 
-def test_mc_grad_reports_unsupported():
+def test_mc_grad_validates():
     import paper_2507_23189_amd as mc
     _lib_path()
+    spec, med, src, geo, det, run = _valid_args()
     out = (C.c_double * 3)()
-    assert mc.lib().mc_grad(None, None, None, None, None, None, out, None) == mc.MC_EUNSUPPORTED
+    tal = _tally_stub(det)
+    assert mc.lib().mc_grad(None, None, None, None, None, None, out, None) == mc.MC_EINVAL
+    # no moment images in the tally
+    rc = mc.lib().mc_grad(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, None, out, None)
+    assert rc == mc.MC_EINVAL and b"MC_MOMENTS" in mc.lib().mc_last_error()
+    tal.side_wk = tal.side_wl = tal.side_w2k = tal.side_w2l = 0x1000
+    med.tau = 0.0
+    rc = mc.lib().mc_grad(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, None, out, None)
+    assert rc == mc.MC_EINVAL
+
+
+def test_mc_simulate_moments_need_buffers():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, med, src, geo, det, run = _valid_args()
+    det.flags = mc.MC_MOMENTS
+    rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                              C.byref(_tally_stub(det)), None)
+    assert rc == mc.MC_EINVAL and b"MC_MOMENTS" in mc.lib().mc_last_error()
