@@ -15,7 +15,12 @@ The JSON line also carries
                 measured average duration (HIP events on the launch stream),
                 against the chip's FP32 VALU issue peak;
   cpu_baseline  the FP64 oracle timed on this host on a bounded sample of the
-                same workload.
+                same workload;
+  adjoint       after the timed steps, the same walk run forward only
+                (mc_simulate, then a stream wait) and forward + adjoint
+                (mc_simulate with the path-moment tallies, then mc_grad for
+                an L2 loss, which waits), each over --steps launches on the
+                same seed: the wall-clock ratio t(fwd + adjoint) / t(fwd).
 
     python bench.py [--steps K] [--warmup W]
 """
@@ -107,6 +112,55 @@ def cpu_baseline(w, target_s: float):
                       f"{threads} host threads, {res.seconds:.1f} s, {ev:.3e} events; host CPU: {cpu}"}
 
 
+def adjoint_timing(mc, w, dev, args):
+    """Wall-clock of forward-only and forward + adjoint walks of `w` (table
+    built once), each launch followed by a wait, as an optimiser step would."""
+    import torch
+    spec = mc.args_from_workload(w)[0]
+    table = mc.mie_table_build(spec, dev)
+    g_hg = table.g if w.phase == mc.MC_PHASE_HG else None
+    kw = dict(g=g_hg, block_size=args.block_size, grid_blocks=args.grid_blocks)
+    _, med, src, geo, det, run = mc.args_from_workload(w, table, **kw)
+    _, med_a, _, _, det_a, _ = mc.args_from_workload(w, table, flags=mc.MC_MOMENTS, **kw)
+    _, med_p, _, _, det_p, _ = mc.args_from_workload(w, table, flags=mc.MC_MOMENTS | mc.MC_MOMENTS_PIXEL2, **kw)
+    t_fwd = mc.Tally.alloc(det, dev)
+    t_adj = mc.Tally.alloc(det_a, dev, moments=True)
+    t_pix = mc.Tally.alloc(det_p, dev, moments=True, pixel2=True)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    dloss = torch.randn(w.side_px, w.side_px, generator=gen, dtype=torch.float64).to(dev)
+    d2loss = torch.full_like(dloss, 2.0)
+
+    def fwd():
+        mc.mc_simulate(med, src, geo, det, run, t_fwd)
+        torch.cuda.synchronize()
+
+    def adj():
+        mc.mc_simulate(med_a, src, geo, det_a, run, t_adj)
+        return mc.mc_grad(med_a, geo, det_a, t_adj, dloss, d2loss_uniform=2.0)
+
+    def adj_pixel():
+        mc.mc_simulate(med_p, src, geo, det_p, run, t_pix)
+        return mc.mc_grad(med_p, geo, det_p, t_pix, dloss, d2loss)
+
+    def clock(fn):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = fn()
+        return (time.perf_counter() - t0) / args.steps * 1e3, out
+
+    fwd_ms, _ = clock(fwd)
+    adj_ms, grad = clock(adj)
+    pix_ms, _ = clock(adj_pixel)
+    return {"ratio": adj_ms / fwd_ms, "fwd_ms": fwd_ms, "fwd_adjoint_ms": adj_ms,
+            "ratio_pixel_hessian": pix_ms / fwd_ms, "fwd_adjoint_pixel_hessian_ms": pix_ms,
+            "grad_mu_sca_mu_abs_c": list(grad),
+            "what": "fwd = mc_simulate (images, scalars); fwd+adjoint = mc_simulate with MC_MOMENTS "
+                    "(side images of sum w k and sum w L, image-wide sums of w^2, w^2 k, w^2 L), then "
+                    "mc_grad with dLoss/dI and a uniform d2Loss/dI2 = 2 (L2 loss); the pixel-Hessian "
+                    "variant adds the per-pixel w^2 k and w^2 L images (MC_MOMENTS_PIXEL2)"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +232,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log("bench: timed steps done")
+    adjoint = adjoint_timing(mc, w, dev, args)
+    log("bench: adjoint timing done")
 
     scal = [t.scalars.cpu().numpy() for t in tallies[args.warmup:]]
     events = float(sum(s[9] for s in scal))
@@ -215,7 +271,8 @@ def main():
         "photons_per_s": photons / elapsed,
         "events_per_photon": s_last[9] / s_last[10],
         "steps_per_photon": s_last[14] / s_last[10],
-        "adjoint_ratio": None,
+        "adjoint_ratio": adjoint["ratio"],
+        "adjoint": adjoint,
     }
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")

@@ -52,8 +52,13 @@ extern "C" {
 #define MC_RECORD 4u          /* write per-photon end records (mc_tally_t.rec_*) */
 #define MC_FIX64 8u           /* images (and squared-weight images) are int64 fixed point,
                                  value = weight * 2^32; otherwise they are double */
-#define MC_MOMENTS 16u        /* also tally, per side-image pixel, the path moments
-                                 sum(w k), sum(w L), sum(w^2 k), sum(w^2 L) used by mc_grad (double) */
+#define MC_MOMENTS 16u        /* also tally the path moments of the side image used by mc_grad:
+                                 per pixel sum(w k) and sum(w L) (side_wk, side_wl, double), and
+                                 over all side-image exits sum(w^2), sum(w^2 k), sum(w^2 L)
+                                 (scalars MC_S_SIDE_W2, MC_S_SIDE_W2K, MC_S_SIDE_W2L) */
+#define MC_MOMENTS_PIXEL2 32u /* with MC_MOMENTS: also per pixel sum(w^2 k) and sum(w^2 L)
+                                 (side_w2k, side_w2l), for losses whose second derivative
+                                 varies from pixel to pixel */
 
 /* Scalar tallies: mc_tally_t.scalars holds MC_N_SCALARS doubles. */
 #define MC_S_FACE 0           /* 0..5: weight leaving faces -x, +x, -y, +y, -z, +z */
@@ -67,7 +72,11 @@ extern "C" {
 #define MC_S_REFLECTIONS 13   /* Fresnel / total internal reflections at walls */
 #define MC_S_STEPS 14         /* random-number blocks drawn (walk steps) */
 #define MC_S_RESERVED 15      /* reserved (written as 0) */
-#define MC_N_SCALARS 16
+#define MC_S_SIDE_W2 16       /* MC_MOMENTS: sum of w^2 over photons leaving through the side image */
+#define MC_S_SIDE_W2K 17      /* MC_MOMENTS: sum of w^2 k over the same photons */
+#define MC_S_SIDE_W2L 18      /* MC_MOMENTS: sum of w^2 L (mm) over the same photons */
+#define MC_S_RESERVED2 19     /* reserved (written as 0) */
+#define MC_N_SCALARS 20
 
 /* Per-photon record fields (structure of arrays, rec_rows rows per field). */
 #define MC_REC_I_FACE 0       /* exit face 0..5, or -1 */
@@ -207,8 +216,8 @@ typedef struct {
     uint64_t workspace_bytes;
     double *side_wk;       /* MC_MOMENTS: side-image shape, sum over detected photons of w k */
     double *side_wl;       /* MC_MOMENTS: side-image shape, sum over detected photons of w L (mm) */
-    double *side_w2k;      /* MC_MOMENTS: side-image shape, sum of w^2 k */
-    double *side_w2l;      /* MC_MOMENTS: side-image shape, sum of w^2 L */
+    double *side_w2k;      /* MC_MOMENTS_PIXEL2: side-image shape, sum of w^2 k */
+    double *side_w2l;      /* MC_MOMENTS_PIXEL2: side-image shape, sum of w^2 L */
 } mc_tally_t;
 
 /*
@@ -246,13 +255,16 @@ int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_g
  *
  * Given g = dLoss/dI (device, side-image shape) and a tally filled by
  * mc_simulate with MC_MOMENTS for the same medium and geometry:
- *     G = sum_p g_p D_p                      (d2loss_dside2 NULL)
- *     G = sum_p (g_p D_p - h_p Q_p)          (h = d2loss_dside2, device)
- * with Q_p = sum w^2 s over the photons in pixel p.  The first is the exact
- * derivative of the loss of this sample with the paths held fixed; when g is
- * computed from the same sample (g = 2 (I - T) for an L2 loss, h = 2) it is
- * biased by the sample's self-correlation, and the second form removes that
- * bias to first order, estimating the gradient of Loss(E[I]).
+ *     G = sum_p g_p D_p                      (no second derivative)
+ *     G = sum_p (g_p D_p - h_p Q_p)          (h_p = d2loss_dside2[p], device, needs MC_MOMENTS_PIXEL2)
+ *     G = sum_p g_p D_p - h sum_p Q_p        (h = d2loss_uniform, d2loss_dside2 NULL)
+ * with Q_p = sum w^2 s over the photons in pixel p (sum_p Q_p from the
+ * MC_S_SIDE_W2K / MC_S_SIDE_W2L scalars).  The first is the exact derivative
+ * of the loss of this sample with the paths held fixed; when g is computed
+ * from the same sample (g = 2 (I - T) for an L2 loss, h = 2) it is biased by
+ * the sample's self-correlation, and the other two remove that bias to first
+ * order, estimating the gradient of Loss(E[I]).  Passing both a
+ * d2loss_dside2 array and a nonzero d2loss_uniform is MC_EINVAL.
  * Writes on the host out_grad[0] = G for mu_sca, out_grad[1] = G for mu_abs,
  * out_grad[2] = sigma_sca out_grad[0] + sigma_abs out_grad[1], the derivative
  * with respect to the particle concentration c in 1/mm^3 (Eq. 17, with
@@ -262,8 +274,8 @@ int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_g
  * the weight threshold is not differentiated.
  */
 int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry, const mc_detector_t *detector,
-            const mc_tally_t *tally, const double *dloss_dside, const double *d2loss_dside2, double out_grad[3],
-            void *stream);
+            const mc_tally_t *tally, const double *dloss_dside, const double *d2loss_dside2,
+            double d2loss_uniform, double out_grad[3], void *stream);
 
 /*
  * The random numbers the walk draws: for each of n_ids photon ids (device

@@ -6,6 +6,7 @@ package does not load the library; the first call does, and raises if it has
 not been built.
 """
 from ._capi import (MC_ACCUMULATE, MC_EDEVICE, MC_EINVAL, MC_ENOMEM, MC_EUNSUPPORTED, MC_FIX64, MC_MAX_N_ANGLES, MC_MOMENTS,
+                    MC_MOMENTS_PIXEL2, MC_S_SIDE_W2, MC_S_SIDE_W2K, MC_S_SIDE_W2L,
                     MC_MAX_N_CDF, MC_MAX_TERMS, MC_N_SCALARS, MC_OK, MC_PHASE_HG, MC_PHASE_MIE, MC_RECORD,
                     MC_SIGMA, Detector, Geometry, McError, Medium, MieSpec, MieTable, Run, Source, Tally, lib,
                     mc_grad, mc_philox_blocks, mc_simulate, mc_version, mc_workspace_bytes, mie_table_build,

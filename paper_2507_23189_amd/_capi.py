@@ -13,10 +13,11 @@ LIB_PATH = os.path.join(_HERE, "libmcmie.so")
 
 MC_OK, MC_EINVAL, MC_EDEVICE, MC_ENOMEM, MC_EUNSUPPORTED = 0, -1, -2, -3, -4
 MC_PHASE_MIE, MC_PHASE_HG = 0, 1
-MC_ACCUMULATE, MC_SIGMA, MC_RECORD, MC_FIX64, MC_MOMENTS = 1, 2, 4, 8, 16
-MC_N_SCALARS = 16
+MC_ACCUMULATE, MC_SIGMA, MC_RECORD, MC_FIX64, MC_MOMENTS, MC_MOMENTS_PIXEL2 = 1, 2, 4, 8, 16, 32
+MC_N_SCALARS = 20
 MC_S_FACE, MC_S_ABSORBED, MC_S_ROULETTE_NET, MC_S_CAPPED_W, MC_S_EVENTS = 0, 6, 7, 8, 9
 MC_S_PHOTONS, MC_S_ROULETTE_KILLS, MC_S_CAPPED, MC_S_REFLECTIONS, MC_S_STEPS, MC_S_RESERVED = 10, 11, 12, 13, 14, 15
+MC_S_SIDE_W2, MC_S_SIDE_W2K, MC_S_SIDE_W2L = 16, 17, 18
 MC_REC_I_N, MC_REC_F_N = 4, 9
 MC_MAX_N_CDF, MC_MAX_N_ANGLES, MC_MAX_TERMS = 16384, 3001, 1024
 
@@ -93,7 +94,7 @@ def lib():
         L.mc_simulate.argtypes = [C.POINTER(Medium), C.POINTER(Source), C.POINTER(Geometry),
                                   C.POINTER(Detector), C.POINTER(Run), C.POINTER(_TallyC), C.c_void_p]
         L.mc_grad.argtypes = [C.POINTER(Medium), C.POINTER(Geometry), C.POINTER(Detector), C.POINTER(_TallyC),
-                              C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
+                              C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]
         L.mc_philox_blocks.argtypes = [C.c_uint64, C.c_uint32, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
                                        C.c_void_p, C.c_void_p]
         L.mc_workspace_bytes.argtypes = [C.POINTER(Detector)]
@@ -193,12 +194,12 @@ class Tally:
     rec_f: "object" = None          # (MC_REC_F_N, rows) float32
     side_wk: "object" = None        # MC_MOMENTS: float64, side-image shape
     side_wl: "object" = None
-    side_w2k: "object" = None
+    side_w2k: "object" = None       # MC_MOMENTS_PIXEL2
     side_w2l: "object" = None
 
     @staticmethod
     def alloc(det: Detector, device="cuda", *, sigma=False, record_rows=0, fix64=False,
-              moments=False) -> "Tally":
+              moments=False, pixel2=False) -> "Tally":
         import torch
         dev = torch.device(device)
         img = dict(dtype=torch.int64 if fix64 else torch.float64, device=dev)
@@ -214,6 +215,7 @@ class Tally:
         if moments:
             t.side_wk = torch.empty((det.side_ny, det.side_nx), dtype=torch.float64, device=dev)
             t.side_wl = torch.empty_like(t.side_wk)
+        if moments and pixel2:
             t.side_w2k = torch.empty_like(t.side_wk)
             t.side_w2l = torch.empty_like(t.side_wk)
         if record_rows:
@@ -243,15 +245,17 @@ def mc_simulate(medium: Medium, source: Source, geometry: Geometry, detector: De
 
 
 def mc_grad(medium: Medium, geometry: Geometry, detector: Detector, tally: Tally, dloss_dside,
-            d2loss_dside2=None, stream=None):
-    """(dLoss/dmu_sca, dLoss/dmu_abs, dLoss/dconcentration) from the moment
-    images of `tally` (filled by mc_simulate with MC_MOMENTS), dLoss/dI of the
-    side image and, optionally, the loss's diagonal second derivative for the
-    self-correlation correction (float64 device tensors).  Waits for the stream."""
+            d2loss_dside2=None, d2loss_uniform: float = 0.0, stream=None):
+    """(dLoss/dmu_sca, dLoss/dmu_abs, dLoss/dconcentration) from the moments
+    of `tally` (filled by mc_simulate with MC_MOMENTS), dLoss/dI of the side
+    image (float64 device tensor) and, optionally, the loss's diagonal second
+    derivative for the self-correlation correction: per pixel
+    (`d2loss_dside2`, device tensor, needs MC_MOMENTS_PIXEL2) or one value for
+    every pixel (`d2loss_uniform`).  Waits for the stream."""
     out = (C.c_double * 3)()
     tc = tally._c()
     _check(lib().mc_grad(C.byref(medium), C.byref(geometry), C.byref(detector), C.byref(tc),
-                         _ptr(dloss_dside), _ptr(d2loss_dside2), out, _stream(stream)))
+                         _ptr(dloss_dside), _ptr(d2loss_dside2), float(d2loss_uniform), out, _stream(stream)))
     return tuple(out)
 
 

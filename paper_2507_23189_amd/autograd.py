@@ -8,16 +8,17 @@ side_image(mu_sca, mu_abs, sim)
     The side image; backward is the exact derivative of this sample with the
     paths held fixed (right for losses linear in the image).
 side_l2_loss(mu_sca, mu_abs, target, sim)
-    sum_p [(I_p - T_p)^2 - sum w^2], an unbiased estimate of
-    sum_p (E[I_p] - T_p)^2 (plus the target's own variance, independent of the
-    coefficients); backward subtracts the sample's self-correlation
-    (second-derivative 2) so the gradient estimates that of the clean loss.
+    sum_p (I_p - T_p)^2 - sum w^2 (the last sum over every photon leaving
+    through the side image), an unbiased estimate of sum_p (E[I_p] - T_p)^2
+    (plus the target's own variance, independent of the coefficients);
+    backward subtracts the sample's self-correlation (uniform second
+    derivative 2) so the gradient estimates that of the clean loss.
 """
 from __future__ import annotations
 
 import math
 
-from ._capi import MC_MOMENTS, MC_SIGMA, Detector, Geometry, Medium, Run, Source, Tally, mc_grad, mc_simulate
+from ._capi import MC_MOMENTS, MC_S_SIDE_W2, Detector, Geometry, Medium, Run, Source, Tally, mc_grad, mc_simulate
 
 
 class SideImage:
@@ -28,7 +29,7 @@ class SideImage:
                  device="cuda"):
         self.medium, self.source, self.geometry, self.run = medium, source, geometry, run
         self.detector = Detector(detector.side_nx, detector.side_ny, detector.trans_nx, detector.trans_ny,
-                                 detector.flags | MC_MOMENTS | MC_SIGMA)
+                                 detector.flags | MC_MOMENTS)
         self.device = device
 
     def medium_for(self, mu_sca: float, mu_abs: float) -> Medium:
@@ -45,7 +46,7 @@ class SideImage:
 
     def run_walk(self, mu_sca: float, mu_abs: float):
         med = self.medium_for(mu_sca, mu_abs)
-        tally = Tally.alloc(self.detector, self.device, sigma=True, moments=True)
+        tally = Tally.alloc(self.detector, self.device, moments=True)
         mc_simulate(med, self.source, self.geometry, self.detector, self.run, tally)
         return med, tally
 
@@ -82,7 +83,7 @@ def _functions():
         def forward(ctx, mu_sca, mu_abs, target, sim):
             med, tally = sim.run_walk(float(mu_sca), float(mu_abs))
             diff = tally.side - target
-            loss = (diff * diff).sum() - tally.side_w2.sum()
+            loss = (diff * diff).sum() - tally.scalars[MC_S_SIDE_W2]
             ctx.sim, ctx.med, ctx.tally = sim, med, tally
             ctx.g = (2.0 * diff).contiguous()
             ctx.dtypes = (mu_sca.dtype, mu_sca.device, mu_abs.dtype, mu_abs.device)
@@ -90,8 +91,8 @@ def _functions():
 
         @staticmethod
         def backward(ctx, grad_loss):
-            h = torch.full_like(ctx.g, 2.0)
-            d_ms, d_ma, _ = mc_grad(ctx.med, ctx.sim.geometry, ctx.sim.detector, ctx.tally, ctx.g, h)
+            d_ms, d_ma, _ = mc_grad(ctx.med, ctx.sim.geometry, ctx.sim.detector, ctx.tally, ctx.g,
+                                    d2loss_uniform=2.0)
             return (*_grads(ctx, d_ms, d_ma, float(grad_loss)), None, None)
 
     _fns["image"] = _SideImageFn

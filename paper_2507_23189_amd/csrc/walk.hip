@@ -74,16 +74,23 @@ struct WalkArgs {
     int32_t *rec_i;
     float *rec_f;
     double *side_wk, *side_wl;     // MC_MOMENTS: per side pixel, sum w k and sum w L
-    double *side_w2k, *side_w2l;   //             and sum w^2 k, sum w^2 L
+    double *side_w2k, *side_w2l;   // MC_MOMENTS_PIXEL2: per side pixel, sum w^2 k and sum w^2 L
     uint64_t rec_rows, record_stride;
 };
 
 constexpr int kCopies = 8;                 // per-XCD image copies in the workspace
 constexpr double kFix = 4294967296.0;      // fixed-point scale 2^32 per unit weight
 
+// w * 2^32 rounded to nearest, ties to even, for 0 <= w < 2^32.  The integer
+// part of w and its fraction are exact in FP32, and the fraction times 2^32
+// is an exact FP32 value below 2^32, so two FP32 conversions give the same
+// integer as llrint((double)w * 2^32) with no FP64 arithmetic (an even
+// multiple of 2^32 does not change the tie-breaking parity).
 __device__ __forceinline__ unsigned long long fix(float w)
 {
-    return (unsigned long long)llrint((double)w * kFix);
+    const float hi = truncf(w);
+    const float lo = rintf((w - hi) * 4294967296.f);
+    return ((unsigned long long)(uint32_t)hi << 32) + (unsigned long long)(uint32_t)lo;
 }
 
 // Pixel = floor(coord / size * n), clamped to the image (IEEE division, so a
@@ -295,11 +302,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             L += t;
             if (hit) {
                 // Boundary: snap onto the wall, then reflect (u3 < R) or leave.
-                const float da = axis == 0 ? dx : (axis == 1 ? dy : dz);
+                // Written as selects so the wave runs it without branches.
+                const bool on_x = axis == 0, on_y = axis == 1, on_z = axis == 2;
+                const float da = on_x ? dx : (on_y ? dy : dz);
                 const bool pos_side = da > 0.f;
-                if (axis == 0) px = pos_side ? a.size[0] : 0.f;
-                else if (axis == 1) py = pos_side ? a.size[1] : 0.f;
-                else pz = pos_side ? a.size[2] : 0.f;
+                const float wall = pos_side ? (on_x ? a.size[0] : (on_y ? a.size[1] : a.size[2])) : 0.f;
+                px = on_x ? wall : px;
+                py = on_y ? wall : py;
+                pz = on_z ? wall : pz;
                 float R = 0.f;
                 if (!a.matched) {
                     const float ci = fabsf(da);
@@ -309,13 +319,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                     const float rp = (a.n21 * ci - ct) * __builtin_amdgcn_rcpf(a.n21 * ci + ct);
                     R = st2 >= 1.f ? 1.f : 0.5f * fmaf(rs, rs, rp * rp);
                 }
-                if (u3 < R) {
-                    if (axis == 0) dx = -dx; else if (axis == 1) dy = -dy; else dz = -dz;
-                    ++acc_refl;
-                } else {
-                    ended = true;
-                    face = 2 * axis + (pos_side ? 1 : 0);
-                }
+                const bool refl = u3 < R;
+                dx = refl && on_x ? -dx : dx;
+                dy = refl && on_y ? -dy : dy;
+                dz = refl && on_z ? -dz : dz;
+                acc_refl += refl ? 1u : 0u;
+                ended = !refl;
+                face = refl ? -1 : 2 * axis + (pos_side ? 1 : 0);
             } else {
                 // Interaction: count, absorb (Eq. 16), roulette, scatter.
                 ++k;
@@ -374,14 +384,22 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 // Faces +x and +z are totalled from their images when finalizing.
                 if (cause == 0 && face != 1 && face != 5) atomicAdd(&s_scal[MC_S_FACE + face], fix(w));
                 if (MOMENTS && cause == 0 && face == 1) {
-                    // Path moments of the side image (perturbation Monte Carlo).
+                    // Path moments of the side image (perturbation Monte Carlo):
+                    // first order per pixel, second order summed over the image
+                    // in the block's LDS (per pixel as well when asked for).
                     const uint32_t key = (uint32_t)(pixel(py, a.size[1], a.side_ny) * a.side_nx +
                                                     pixel(pz, a.size[2], a.side_nx));
                     const double wd = (double)w, wk = wd * (double)k, wl = wd * (double)L;
                     atomicAdd(a.side_wk + key, wk);
                     atomicAdd(a.side_wl + key, wl);
-                    atomicAdd(a.side_w2k + key, wd * wk);
-                    atomicAdd(a.side_w2l + key, wd * wl);
+                    double *s_m2 = (double *)(s_scal + MC_S_SIDE_W2);
+                    atomicAdd(s_m2 + 0, wd * wd);
+                    atomicAdd(s_m2 + 1, wd * wk);
+                    atomicAdd(s_m2 + 2, wd * wl);
+                    if (a.side_w2k) {
+                        atomicAdd(a.side_w2k + key, wd * wk);
+                        atomicAdd(a.side_w2l + key, wd * wl);
+                    }
                 }
                 acc_abs += fix(A);
                 acc_events += k;
@@ -456,6 +474,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     if (threadIdx.x < MC_S_RESERVED) {
         const unsigned long long v = s_scal[threadIdx.x];
         if (v != 0ull) atomicAdd(&a.ws_scal[threadIdx.x], v);
+    } else if (MOMENTS && threadIdx.x >= MC_S_SIDE_W2 && threadIdx.x <= MC_S_SIDE_W2L) {
+        const double v = __longlong_as_double((long long)s_scal[threadIdx.x]);
+        if (v != 0.0) atomicAdd((double *)&a.ws_scal[threadIdx.x], v);
     }
     for (int i = threadIdx.x; i < slots; i += blockDim.x) {
         const uint32_t key = s_key[i];
@@ -482,6 +503,8 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
         if (side_wk) {
             side_wk[i] = 0.0;
             side_wl[i] = 0.0;
+        }
+        if (side_w2k) {
             side_w2k[i] = 0.0;
             side_w2l[i] = 0.0;
         }
@@ -542,14 +565,17 @@ __global__ __launch_bounds__(256) void finalize_images(const unsigned long long 
 }
 
 // Fixed-point scalar sums to the caller's doubles (weights scaled back by
-// 2^-32, counts as they are).
+// 2^-32, counts as they are); the second-order side moments are FP64 sums.
 __global__ void finalize_scalars(const unsigned long long *ws_scal, double *scalars)
 {
     const int t = threadIdx.x;
-    if (t >= MC_S_RESERVED) return;
-    const bool weight = t <= MC_S_CAPPED_W;
-    const long long v = (long long)ws_scal[t];
-    scalars[t] += weight ? (double)v * (1.0 / kFix) : (double)v;
+    if (t < MC_S_RESERVED) {
+        const bool weight = t <= MC_S_CAPPED_W;
+        const long long v = (long long)ws_scal[t];
+        scalars[t] += weight ? (double)v * (1.0 / kFix) : (double)v;
+    } else if (t >= MC_S_SIDE_W2 && t <= MC_S_SIDE_W2L) {
+        scalars[t] += __longlong_as_double((long long)ws_scal[t]);
+    }
 }
 
 __global__ void philox_blocks_kernel(uint32_t k0, uint32_t k1, uint32_t instance, const uint64_t *ids,
@@ -567,11 +593,12 @@ __global__ void philox_blocks_kernel(uint32_t k0, uint32_t k1, uint32_t instance
     out[4 * t + 3] = r.r3;
 }
 
-// sum_p g_p M_k[p], sum_p g_p M_L[p] and, with h, sum_p h_p M2_k[p] and
-// sum_p h_p M2_L[p], in one workgroup (fixed order, deterministic).
+// sum_p g_p M_k[p], sum_p g_p M_L[p] and, with per-pixel h, sum_p h_p M2_k[p]
+// and sum_p h_p M2_L[p], in one workgroup (fixed order, deterministic); with a
+// uniform h instead, h times the image-wide second moments.
 __global__ __launch_bounds__(1024) void grad_dot(const double *g, const double *h, const double *wk,
                                                  const double *wl, const double *w2k, const double *w2l,
-                                                 uint64_t n, double *out)
+                                                 uint64_t n, double h_uniform, const double *scalars, double *out)
 {
     __shared__ double s_red[4][1024];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -590,13 +617,20 @@ __global__ __launch_bounds__(1024) void grad_dot(const double *g, const double *
             for (int c = 0; c < 4; ++c) s_red[c][threadIdx.x] += s_red[c][threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x < 4) out[threadIdx.x] = s_red[threadIdx.x][0];
+    if (threadIdx.x < 4) {
+        double v = s_red[threadIdx.x][0];
+        if (!h && threadIdx.x >= 2)
+            v = h_uniform != 0.0 ? h_uniform * scalars[threadIdx.x == 2 ? MC_S_SIDE_W2K : MC_S_SIDE_W2L] : 0.0;
+        out[threadIdx.x] = v;
+    }
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// Workspace layout: 32 uint64 scalar words, then kCopies fixed-point copies of
-// the images (and of the squared-weight images with MC_SIGMA).
+// Workspace layout: 32 uint64 scalar words (0..14 fixed-point scalar sums,
+// 15 the photon work counter, 16..18 FP64 second-order side moments, 24..27
+// mc_grad's dot products), then kCopies fixed-point copies of the images (and
+// of the squared-weight images with MC_SIGMA).
 constexpr uint64_t kWsScalarWords = 32;
 
 uint64_t workspace_words(const mc_detector_t &d)
@@ -660,10 +694,12 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     if (rn.block_size != 0 && (rn.block_size < 64 || rn.block_size > 1024 || rn.block_size % 64))
         return fail(MC_EINVAL, "mc_simulate: block_size must be a multiple of 64 in 64..1024");
     if (rn.grid_blocks < 0) return fail(MC_EINVAL, "mc_simulate: grid_blocks must be >= 0");
-    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64 | MC_MOMENTS))
+    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64 | MC_MOMENTS | MC_MOMENTS_PIXEL2))
         return fail(MC_EINVAL, "mc_simulate: unknown detector flags 0x%x", det.flags);
-    if ((det.flags & MC_MOMENTS) && (!t.side_wk || !t.side_wl || !t.side_w2k || !t.side_w2l))
-        return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS needs side_wk, side_wl, side_w2k and side_w2l");
+    if ((det.flags & MC_MOMENTS) && (!t.side_wk || !t.side_wl))
+        return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS needs side_wk and side_wl");
+    if ((det.flags & MC_MOMENTS_PIXEL2) && (!(det.flags & MC_MOMENTS) || !t.side_w2k || !t.side_w2l))
+        return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS_PIXEL2 needs MC_MOMENTS, side_w2k and side_w2l");
     if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < workspace_words(det) * 8)
         return fail(MC_EINVAL, "mc_simulate: workspace needs %llu bytes, 8-byte aligned",
                     (unsigned long long)(workspace_words(det) * 8));
@@ -741,8 +777,8 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     a.rec_i = t.rec_i; a.rec_f = t.rec_f;
     a.side_wk = (det.flags & MC_MOMENTS) ? t.side_wk : nullptr;
     a.side_wl = (det.flags & MC_MOMENTS) ? t.side_wl : nullptr;
-    a.side_w2k = (det.flags & MC_MOMENTS) ? t.side_w2k : nullptr;
-    a.side_w2l = (det.flags & MC_MOMENTS) ? t.side_w2l : nullptr;
+    a.side_w2k = (det.flags & MC_MOMENTS_PIXEL2) ? t.side_w2k : nullptr;
+    a.side_w2l = (det.flags & MC_MOMENTS_PIXEL2) ? t.side_w2l : nullptr;
     a.rec_rows = (det.flags & MC_RECORD) ? t.rec_rows : 0;
     a.record_stride = rn.record_stride >= 1 ? rn.record_stride : 1;
 
@@ -820,7 +856,7 @@ extern "C" uint64_t mc_workspace_bytes(const mc_detector_t *detector)
 
 extern "C" int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry, const mc_detector_t *detector,
                        const mc_tally_t *tally, const double *dloss_dside, const double *d2loss_dside2,
-                       double out_grad[3], void *stream)
+                       double d2loss_uniform, double out_grad[3], void *stream)
 {
     using namespace mcmie;
     clear_error();
@@ -833,24 +869,31 @@ extern "C" int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry,
     if (!finite_pos(geo.size_mm[2]) || !(m.tau > 0.0) || !std::isfinite(m.tau) || !(m.albedo > 0.0 && m.albedo <= 1.0))
         return fail(MC_EINVAL, "mc_grad: needs tau > 0, albedo in (0, 1] and size_mm[2] > 0");
     if (det.side_nx < 1 || det.side_ny < 1) return fail(MC_EINVAL, "mc_grad: side image dimensions must be >= 1");
-    if (!t.side_wk || !t.side_wl || !t.side_w2k || !t.side_w2l)
+    if (!t.side_wk || !t.side_wl || !t.scalars)
         return fail(MC_EINVAL, "mc_grad: the tally has no moment images (MC_MOMENTS)");
+    if (d2loss_dside2 && (!t.side_w2k || !t.side_w2l))
+        return fail(MC_EINVAL, "mc_grad: a per-pixel second derivative needs the MC_MOMENTS_PIXEL2 images");
+    if (!std::isfinite(d2loss_uniform))
+        return fail(MC_EINVAL, "mc_grad: d2loss_uniform must be finite");
+    if (d2loss_dside2 && d2loss_uniform != 0.0)
+        return fail(MC_EINVAL, "mc_grad: give either d2loss_dside2 or d2loss_uniform, not both");
     if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < kWsScalarWords * 8)
         return fail(MC_EINVAL, "mc_grad: workspace of at least %llu bytes required",
                     (unsigned long long)(kWsScalarWords * 8));
     const double mu_t = m.tau / geo.size_mm[2];
     const double mu_s = m.albedo * mu_t;
     hipStream_t st = (hipStream_t)stream;
-    double *dots = (double *)t.workspace + 16;    // scalar words 16..19
+    double *dots = (double *)t.workspace + 24;    // scalar words 24..27
     const uint64_t n = (uint64_t)det.side_nx * det.side_ny;
     hipLaunchKernelGGL(grad_dot, dim3(1), dim3(1024), 0, st, dloss_dside, d2loss_dside2, (const double *)t.side_wk,
-                       (const double *)t.side_wl, (const double *)t.side_w2k, (const double *)t.side_w2l, n, dots);
+                       (const double *)t.side_wl, (const double *)t.side_w2k, (const double *)t.side_w2l, n,
+                       d2loss_uniform, (const double *)t.scalars, dots);
     MC_HIP_CHECK(hipGetLastError());
     double d[4];
     MC_HIP_CHECK(hipMemcpyAsync(d, dots, sizeof d, hipMemcpyDeviceToHost, st));
     MC_HIP_CHECK(hipStreamSynchronize(st));
     // D = M_k / mu_s - M_L (mu_sca), -M_L (mu_abs); Q likewise from the w^2 moments.
-    const double gq_s = d2loss_dside2 ? d[2] / mu_s - d[3] : 0.0, gq_a = d2loss_dside2 ? -d[3] : 0.0;
+    const double gq_s = d[2] / mu_s - d[3], gq_a = -d[3];
     out_grad[0] = (d[0] / mu_s - d[1]) - gq_s;
     out_grad[1] = -d[1] - gq_a;
     const bool have_sigma = m.sigma_sca_mm2 != 0.0 || m.sigma_abs_mm2 != 0.0;

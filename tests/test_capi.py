@@ -45,7 +45,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_empty_error():
     import paper_2507_23189_amd as mc
     _lib_path()
-    assert mc.mc_version() == 100
+    assert mc.mc_version() == 200
     assert mc.lib().mc_last_error() == b""
 
 
@@ -178,13 +178,23 @@ def test_mc_grad_validates():
     spec, med, src, geo, det, run = _valid_args()
     out = (C.c_double * 3)()
     tal = _tally_stub(det)
-    assert mc.lib().mc_grad(None, None, None, None, None, None, out, None) == mc.MC_EINVAL
+    g = mc.lib().mc_grad
+    assert g(None, None, None, None, None, None, 0.0, out, None) == mc.MC_EINVAL
     # no moment images in the tally
-    rc = mc.lib().mc_grad(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, None, out, None)
+    rc = g(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, None, 0.0, out, None)
     assert rc == mc.MC_EINVAL and b"MC_MOMENTS" in mc.lib().mc_last_error()
-    tal.side_wk = tal.side_wl = tal.side_w2k = tal.side_w2l = 0x1000
+    tal.side_wk = tal.side_wl = 0x1000
+    # a per-pixel second derivative needs the per-pixel second moments
+    rc = g(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, 0x1000, 0.0, out, None)
+    assert rc == mc.MC_EINVAL and b"PIXEL2" in mc.lib().mc_last_error()
+    tal.side_w2k = tal.side_w2l = 0x1000
+    # per-pixel and uniform second derivatives together, or a non-finite one
+    rc = g(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, 0x1000, 2.0, out, None)
+    assert rc == mc.MC_EINVAL and b"not both" in mc.lib().mc_last_error()
+    rc = g(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, None, float("inf"), out, None)
+    assert rc == mc.MC_EINVAL
     med.tau = 0.0
-    rc = mc.lib().mc_grad(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, None, out, None)
+    rc = g(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, None, 0.0, out, None)
     assert rc == mc.MC_EINVAL
 
 
@@ -193,6 +203,17 @@ def test_mc_simulate_moments_need_buffers():
     _lib_path()
     spec, med, src, geo, det, run = _valid_args()
     det.flags = mc.MC_MOMENTS
-    rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
-                              C.byref(_tally_stub(det)), None)
+    sim = mc.lib().mc_simulate
+    rc = sim(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run), C.byref(_tally_stub(det)), None)
     assert rc == mc.MC_EINVAL and b"MC_MOMENTS" in mc.lib().mc_last_error()
+    # per-pixel second moments: only with MC_MOMENTS and their two buffers
+    det.flags = mc.MC_MOMENTS_PIXEL2
+    tal = _tally_stub(det)
+    tal.side_wk = tal.side_wl = tal.side_w2k = tal.side_w2l = 0x1000
+    rc = sim(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run), C.byref(tal), None)
+    assert rc == mc.MC_EINVAL and b"PIXEL2" in mc.lib().mc_last_error()
+    det.flags = mc.MC_MOMENTS | mc.MC_MOMENTS_PIXEL2
+    tal = _tally_stub(det)
+    tal.side_wk = tal.side_wl = 0x1000
+    rc = sim(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run), C.byref(tal), None)
+    assert rc == mc.MC_EINVAL and b"PIXEL2" in mc.lib().mc_last_error()

@@ -42,8 +42,9 @@ def test_moments_and_gradient_match_oracle(mc, cuda_device):
     # Moments need their buffers: allocate the tally with moments=True.
     spec, *_ = mc.args_from_workload(w)
     table = mc.mie_table_build(spec, cuda_device)
-    _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=mc.MC_MOMENTS | mc.MC_RECORD)
-    tal = mc.Tally.alloc(det, cuda_device, moments=True, record_rows=w.n_photons)
+    _, med, src, geo, det, run = mc.args_from_workload(
+        w, table, flags=mc.MC_MOMENTS | mc.MC_MOMENTS_PIXEL2 | mc.MC_RECORD)
+    tal = mc.Tally.alloc(det, cuda_device, moments=True, pixel2=True, record_rows=w.n_photons)
     mc.mc_simulate(med, src, geo, det, run, tal)
     torch.cuda.synchronize()
     r = owalk.Walk(w).run(records=True)
@@ -70,18 +71,30 @@ def test_moments_and_gradient_match_oracle(mc, cuda_device):
     assert abs(d_ms - o_ms) <= 0.05 * scale_s
     assert abs(d_ma - o_ma) <= 0.05 * scale_a
     assert d_c == pytest.approx(table.sigma_sca_mm2 * d_ms + table.sigma_abs_mm2 * d_ma, rel=1e-12)
-    # Second-order moments and the self-correlation correction (h = 2).
+    # Second-order moments, per pixel (MC_MOMENTS_PIXEL2) and summed over the
+    # image (scalars), and the self-correlation correction (h = 2).
+    w_s, k_s, l_s = r.rec("w")[sel], r.rec("k")[sel], r.rec("L")[sel]
     w2k = np.zeros_like(wk); w2l = np.zeros_like(wl)
-    np.add.at(w2k, (rows, cols), r.rec("w")[sel] ** 2 * r.rec("k")[sel])
-    np.add.at(w2l, (rows, cols), r.rec("w")[sel] ** 2 * r.rec("L")[sel])
-    assert tal.side_w2k.cpu().numpy().sum() == pytest.approx(w2k.sum(), rel=2e-3)
-    assert tal.side_w2l.cpu().numpy().sum() == pytest.approx(w2l.sum(), rel=2e-3)
+    np.add.at(w2k, (rows, cols), w_s ** 2 * k_s)
+    np.add.at(w2l, (rows, cols), w_s ** 2 * l_s)
+    g2k, g2l = tal.side_w2k.cpu().numpy(), tal.side_w2l.cpu().numpy()
+    assert g2k.sum() == pytest.approx(w2k.sum(), rel=2e-3)
+    assert g2l.sum() == pytest.approx(w2l.sum(), rel=2e-3)
+    sc = tal.scalars.cpu().numpy()
+    assert sc[mc.MC_S_SIDE_W2] == pytest.approx(np.sum(w_s ** 2), rel=2e-3)
+    assert sc[mc.MC_S_SIDE_W2K] == pytest.approx(g2k.sum(), rel=1e-12)
+    assert sc[mc.MC_S_SIDE_W2L] == pytest.approx(g2l.sum(), rel=1e-12)
+    gdev = torch.tensor(gimg, device=cuda_device)
     h2 = torch.full((w.side_px, w.side_px), 2.0, dtype=torch.float64, device=cuda_device)
-    c_ms, c_ma, _ = mc.mc_grad(med, geo, det, tal, torch.tensor(gimg, device=cuda_device), h2)
-    q_s = 2 * np.sum(r.rec("w")[sel] ** 2 * (r.rec("k")[sel] / mu_s - r.rec("L")[sel]))
-    q_a = -2 * np.sum(r.rec("w")[sel] ** 2 * r.rec("L")[sel])
+    c_ms, c_ma, _ = mc.mc_grad(med, geo, det, tal, gdev, h2)
+    q_s = 2 * np.sum(w_s ** 2 * (k_s / mu_s - l_s))
+    q_a = -2 * np.sum(w_s ** 2 * l_s)
     assert c_ms == pytest.approx(d_ms - q_s, abs=0.05 * scale_s + 1e-3 * abs(q_s))
     assert c_ma == pytest.approx(d_ma - q_a, abs=0.05 * scale_a + 1e-3 * abs(q_a))
+    # A uniform second derivative through the image-wide sums gives the same.
+    u_ms, u_ma, _ = mc.mc_grad(med, geo, det, tal, gdev, d2loss_uniform=2.0)
+    assert u_ms == pytest.approx(c_ms, rel=1e-9, abs=1e-9 * abs(q_s))
+    assert u_ma == pytest.approx(c_ma, rel=1e-9, abs=1e-9 * abs(q_a))
 
 
 def _walk(mc, dev, w, table, mu_s, mu_a, moments, tau_albedo=None):
@@ -130,7 +143,8 @@ def test_corrected_l2_gradient_matches_crn_differences(mc, cuda_device):
     (seed 99).  At these pixel counts the plain loss is dominated by Monte
     Carlo variance, so the comparison uses the variance-corrected loss
     sum[(I - T)^2 - sum w^2] and the self-correlation-corrected pMC gradient
-    (mc_grad with d2loss = 2); both estimate the gradient of |E[I] - T|^2.
+    (mc_grad with a uniform second derivative 2); both estimate the gradient
+    of |E[I] - T|^2.
     Relative step 1e-2 and 4e8 photons per evaluation keep the differences'
     noise below 1 % (at step 1e-3 the pixel crossings of a 512^2 image need
     ~1e10 photons)."""
@@ -142,7 +156,9 @@ def test_corrected_l2_gradient_matches_crn_differences(mc, cuda_device):
     mu_s, mu_a = _coefficients(w)
     med, geo, det, tal = _walk(mc, cuda_device, w, table, mu_s, mu_a, True)
     diff = tal.side - T
-    d_ms, d_ma, _ = mc.mc_grad(med, geo, det, tal, (2 * diff).contiguous(), (2 + 0 * diff).contiguous())
+    d_ms, d_ma, _ = mc.mc_grad(med, geo, det, tal, (2 * diff).contiguous(), d2loss_uniform=2.0)
+    # The image-wide sum of w^2 in the scalars is the squared-weight image's sum.
+    assert float(tal.scalars[mc.MC_S_SIDE_W2]) == pytest.approx(float(tal.side_w2.sum()), rel=1e-6)
 
     def clean(tt):
         return float(((tt.side - T) ** 2).sum() - tt.side_w2.sum())
@@ -169,9 +185,11 @@ def test_corrected_l2_gradient_matches_crn_differences(mc, cuda_device):
 
 
 def test_autograd_fits_optical_depth_to_a_lateral_image(mc, cuda_device):
-    """40 Adam steps on tau through torch.autograd (side_l2_loss), 1e7 photons
+    """20 Adam steps on tau through torch.autograd (side_l2_loss), 1e7 photons
     per evaluation, 128 x 128 lateral image, from tau = 4 towards the target
-    made at tau = 4.5 with seed 99 (learning rate halved after 20 steps)."""
+    made at tau = 4.5 with seed 99.  Adam's step is nearly independent of the
+    gradient's scale; betas (0.5, 0.9) and rate 0.1 settle within 1e-3 of
+    the optimum of a quadratic 0.5 away in 20 steps."""
     import torch
     w = W.DIFF.replace(side_px=128, trans_px=128)
     spec, *_ = mc.args_from_workload(w)
@@ -181,14 +199,12 @@ def test_autograd_fits_optical_depth_to_a_lateral_image(mc, cuda_device):
     sim = mc.SideImage(med, src, geo, det, run, cuda_device)
     L = w.size_mm[2]
     tau = torch.tensor(4.0, dtype=torch.float64, requires_grad=True)
-    opt = torch.optim.Adam([tau], lr=0.05)
-    sched = torch.optim.lr_scheduler.StepLR(opt, step_size=20, gamma=0.5)
-    for it in range(40):
+    opt = torch.optim.Adam([tau], lr=0.1, betas=(0.5, 0.9))
+    for it in range(20):
         opt.zero_grad()
         mu_t = tau / L
         loss = mc.side_l2_loss(mu_t * w.albedo, mu_t * (1 - w.albedo), target, sim)
         loss.backward()
         opt.step()
-        sched.step()
     print(f"fitted tau {tau.item():.4f} (target 4.5)")
-    assert abs(tau.item() - 4.5) < 0.1
+    assert abs(tau.item() - 4.5) < 0.05

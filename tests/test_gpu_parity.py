@@ -202,6 +202,36 @@ def test_launch_shape_and_photon_ranges_are_invariant(mc, cuda_device):
     assert f["trans"].sum() * 2.0**-32 == f["scalars"][5]
 
 
+def test_fixed_point_tallies_are_exact_sums_of_record_weights(mc, cuda_device):
+    """MC_FIX64 tallies hold, per pixel and per face, the sum of each exit
+    weight rounded to nearest (ties to even) at 2^32 per unit, bit for bit:
+    recomputed here from the per-photon records, with the pixel of each exit
+    from its recorded position by the same FP32 floor(coord / size * n)."""
+    w = W.TINY.replace(tau=3.0, n_photons=30000, side_px=97, trans_px=131)
+    f = gpu_run(w, records=True, fix64=True)
+    r = f["rec"]
+    f32 = np.float32
+
+    def q(x):
+        return np.rint(np.asarray(x, dtype=np.float64) * 2.0**32).astype(np.int64)
+
+    wf = r["w"].astype(f32)
+    out = r["cause"] == 0
+    for face, img, row_c, col_c, col_size, n in ((1, "side", "py", "pz", w.size_mm[2], w.side_px),
+                                                 (5, "trans", "py", "px", w.size_mm[0], w.trans_px)):
+        sel = out & (r["face"] == face)
+        row = np.floor(r[row_c][sel].astype(f32) / f32(w.size_mm[1]) * f32(n)).astype(np.int64).clip(0, n - 1)
+        col = np.floor(r[col_c][sel].astype(f32) / f32(col_size) * f32(n)).astype(np.int64).clip(0, n - 1)
+        for name, vals in ((img, q(wf[sel])), (img + "_w2", q(wf[sel] * wf[sel]))):
+            expect = np.zeros(n * n, dtype=np.int64)
+            np.add.at(expect, row * n + col, vals)
+            np.testing.assert_array_equal(f[name].reshape(-1), expect, err_msg=name)
+    s = f["scalars"]
+    for face in range(6):
+        assert s[face] == q(wf[out & (r["face"] == face)]).sum() * 2.0**-32, face
+    assert s[6] == q(r["A"].astype(f32)).sum() * 2.0**-32
+
+
 def test_zero_and_single_photon(mc, cuda_device):
     w = W.TINY
     z = gpu_run(w, n_photons=0, records=True)
