@@ -20,7 +20,13 @@ The JSON line also carries
                 (mc_simulate, then a stream wait) and forward + adjoint
                 (mc_simulate with the path-moment tallies, then mc_grad for
                 an L2 loss, which waits), each over --steps launches on the
-                same seed: the wall-clock ratio t(fwd + adjoint) / t(fwd).
+                same seed: the wall-clock ratio t(fwd + adjoint) / t(fwd);
+  batch         the 256-medium batched launch (particle diameters, depths,
+                albedos and photon counts from the seeded batch sampler,
+                5.75e8 photons): launch shape from mc_autotune_batch on a
+                1/16 photon sample, then scatter events/s of the batched
+                launch against the best rate any of its media reaches when
+                run alone with mc_simulate (--no-batch skips it).
 
     python bench.py [--steps K] [--warmup W]
 """
@@ -161,6 +167,52 @@ def adjoint_timing(mc, w, dev, args):
                     "variant adds the per-pixel w^2 k and w^2 L images (MC_MOMENTS_PIXEL2)"}
 
 
+def batch_timing(mc, W, dev, args):
+    """Batched launch of the 256 sampled media against each medium run alone."""
+    import torch
+    ws = W.batch_workloads(256)
+    tables = [mc.mie_table_build(mc.args_from_workload(w)[0], dev) for w in ws]
+    _, _, src, geo, det, run = mc.args_from_workload(ws[0])
+    items = [mc.batch_item(w, t) for w, t in zip(ws, tables)]
+    tal = mc.Tally.alloc_batch(det, len(ws), dev)
+    t0 = time.perf_counter()
+    blk, chk, best, table = mc.mc_autotune_batch(items, ws[0].n_cdf, src, geo, det, run, tal, 1.0 / 16)
+    tune_s = time.perf_counter() - t0
+    run.block_size, run.chunk = blk, chk
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    mc.mc_simulate_batch(items, ws[0].n_cdf, src, geo, det, run, tal)
+    ms = []
+    for _ in range(max(1, args.steps)):
+        ev[0].record()
+        mc.mc_simulate_batch(items, ws[0].n_cdf, src, geo, det, run, tal)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    scal = tal.scalars.cpu().numpy()
+    events = float(scal[:, 9].sum())
+    batch_ms = sorted(ms)[len(ms) // 2]
+    # Every medium alone (default launch shape), timed the same way.
+    single = []
+    for w, t in zip(ws, tables):
+        _, med, s1, g1, d1, r1 = mc.args_from_workload(w, t)
+        one = mc.Tally.alloc(d1, dev)
+        mc.mc_simulate(med, s1, g1, d1, r1, one)
+        ev[0].record()
+        mc.mc_simulate(med, s1, g1, d1, r1, one)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_ms = ev[0].elapsed_time(ev[1])
+        single.append((float(one.scalars[9]) / (t_ms * 1e-3), t_ms))
+    best_single = max(r for r, _ in single)
+    return {"media": len(ws), "photons": int(sum(w.n_photons for w in ws)), "events": events,
+            "batch_ms": batch_ms, "events_per_s": events / (batch_ms * 1e-3),
+            "best_single_events_per_s": best_single,
+            "ratio_to_best_single": events / (batch_ms * 1e-3) / best_single,
+            "sum_of_single_ms": float(sum(m for _, m in single)),
+            "autotune": {"block_size": blk, "chunk": chk, "sample_ms": best, "seconds": tune_s,
+                         "candidates_ms": {f"{b}x{c}": v for (b, c), v in table.items()}}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +225,7 @@ def main():
     ap.add_argument("--grid-blocks", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -234,6 +287,8 @@ def main():
     log("bench: timed steps done")
     adjoint = adjoint_timing(mc, w, dev, args)
     log("bench: adjoint timing done")
+    batch = None if args.no_batch else batch_timing(mc, W, dev, args)
+    log("bench: batch timing done")
 
     scal = [t.scalars.cpu().numpy() for t in tallies[args.warmup:]]
     events = float(sum(s[9] for s in scal))
@@ -273,6 +328,7 @@ def main():
         "steps_per_photon": s_last[14] / s_last[10],
         "adjoint_ratio": adjoint["ratio"],
         "adjoint": adjoint,
+        "batch": batch,
     }
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")

@@ -199,6 +199,8 @@ typedef struct {
     uint64_t record_stride;/* MC_RECORD: photon offset + r * stride goes to row r (>= 1) */
     int32_t block_size;    /* threads per block, multiple of 64 in 64..1024; 0 = library choice */
     int32_t grid_blocks;   /* blocks; 0 = library choice (enough to fill every CU) */
+    uint32_t chunk;        /* photons a wave claims at a time, 1..65536; 0 = library choice */
+    uint32_t reserved;     /* set to 0 */
 } mc_run_t;
 
 /* Caller-owned DEVICE outputs and workspace. */
@@ -244,6 +246,58 @@ uint64_t mc_workspace_bytes(const mc_detector_t *detector);
 int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
                 const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,
                 void *stream);
+
+/*
+ * Batched launch: many media in one persistent kernel.  Every item is a
+ * medium in the same cuvette, with the same source, detector and run
+ * settings, the Mie phase function (its own device inverse table of n_cdf
+ * entries, from mie_table_build) and its own optical depth, albedo, photon
+ * count and Philox counter word.  Photon i of an item follows exactly the
+ * walk mc_simulate gives it for that medium with run->instance = item.instance
+ * and photon id i, so each item's tallies equal a separate mc_simulate of the
+ * item (bit for bit with MC_FIX64; up to FP64 summation order otherwise).
+ *
+ * Work is handed out in units of run->chunk photons of one item (0: library
+ * choice), items ordered by decreasing estimated cost (photons x (1 + tau))
+ * so the long ones start first; each lane carries its own photon's medium, so
+ * waves move from one item to the next without waiting for each other.
+ * Outputs are item-major: side is n_items x side_ny x side_nx, trans and the
+ * MC_SIGMA images likewise, scalars n_items x MC_N_SCALARS.  run->n_photons,
+ * photon_offset, instance and record_stride are ignored.  Supported flags:
+ * MC_ACCUMULATE, MC_SIGMA, MC_FIX64 (MC_RECORD and MC_MOMENTS give
+ * MC_EUNSUPPORTED).  n_items is 1..MC_MAX_BATCH.  Asynchronous.
+ */
+#define MC_MAX_BATCH 512
+typedef struct {
+    double tau;            /* optical depth along z (Eq. 1), >= 0 */
+    double albedo;         /* mu_sca / mu_ext, in [0, 1] */
+    const float *inv_cdf;  /* DEVICE inverse table of v = 1 - cos(theta), n_cdf floats (Sec. 2.6) */
+    uint64_t n_photons;    /* photons of this medium, ids 0 .. n_photons - 1 (0 allowed) */
+    uint32_t instance;     /* Philox counter word 1 of its photons */
+    uint32_t reserved;     /* set to 0 */
+} mc_batch_item_t;
+
+int mc_simulate_batch(const mc_batch_item_t *items, uint32_t n_items, int32_t n_cdf, const mc_source_t *source,
+                      const mc_geometry_t *geometry, const mc_detector_t *detector, const mc_run_t *run,
+                      const mc_tally_t *tally, void *stream);
+
+/* Workspace bytes mc_simulate_batch needs for n_items media (0 if invalid). */
+uint64_t mc_workspace_bytes_batch(const mc_detector_t *detector, uint32_t n_items);
+
+/*
+ * Launch-shape autotuner for mc_simulate_batch.  Runs the batch with every
+ * item's photon count scaled by sample_fraction (in (0, 1], at least one
+ * photon for a nonzero count) once for each candidate block size
+ * {256, 512, 1024} and chunk {256, 512, 1024, 2048, 4096} (block-major order),
+ * timing each candidate's second launch with HIP events on `stream`, and
+ * writes the fastest pair to *block_size and *chunk and its time to *best_ms.
+ * candidate_ms, if not NULL, receives all 15 times.  The tally buffers are
+ * overwritten by the trial runs.  Waits for the stream.
+ */
+int mc_autotune_batch(const mc_batch_item_t *items, uint32_t n_items, int32_t n_cdf, const mc_source_t *source,
+                      const mc_geometry_t *geometry, const mc_detector_t *detector, const mc_run_t *run,
+                      const mc_tally_t *tally, double sample_fraction, int32_t *block_size, uint32_t *chunk,
+                      double *best_ms, double *candidate_ms, void *stream);
 
 /*
  * Perturbation Monte Carlo adjoint of a loss on the side image.  A detected

@@ -20,6 +20,9 @@ MC_S_PHOTONS, MC_S_ROULETTE_KILLS, MC_S_CAPPED, MC_S_REFLECTIONS, MC_S_STEPS, MC
 MC_S_SIDE_W2, MC_S_SIDE_W2K, MC_S_SIDE_W2L = 16, 17, 18
 MC_REC_I_N, MC_REC_F_N = 4, 9
 MC_MAX_N_CDF, MC_MAX_N_ANGLES, MC_MAX_TERMS = 16384, 3001, 1024
+MC_MAX_BATCH = 512
+# Candidates mc_autotune_batch times, in its block-major order.
+AUTOTUNE_BLOCKS, AUTOTUNE_CHUNKS = (256, 512, 1024), (256, 512, 1024, 2048, 4096)
 
 
 class MieSpec(C.Structure):
@@ -60,7 +63,13 @@ class Run(C.Structure):
     _fields_ = [("n_photons", C.c_uint64), ("photon_offset", C.c_uint64), ("seed", C.c_uint64),
                 ("instance", C.c_uint32), ("max_steps", C.c_uint32), ("roulette_w", C.c_double),
                 ("roulette_p", C.c_double), ("record_stride", C.c_uint64), ("block_size", C.c_int32),
-                ("grid_blocks", C.c_int32)]
+                ("grid_blocks", C.c_int32), ("chunk", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class BatchItem(C.Structure):
+    """One medium of mc_simulate_batch (mc_batch_item_t)."""
+    _fields_ = [("tau", C.c_double), ("albedo", C.c_double), ("inv_cdf", C.c_void_p), ("n_photons", C.c_uint64),
+                ("instance", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class _TallyC(C.Structure):
@@ -99,9 +108,17 @@ def lib():
                                        C.c_void_p, C.c_void_p]
         L.mc_workspace_bytes.argtypes = [C.POINTER(Detector)]
         L.mc_workspace_bytes.restype = C.c_uint64
+        L.mc_workspace_bytes_batch.argtypes = [C.POINTER(Detector), C.c_uint32]
+        L.mc_workspace_bytes_batch.restype = C.c_uint64
+        _batch_args = [C.POINTER(BatchItem), C.c_uint32, C.c_int32, C.POINTER(Source), C.POINTER(Geometry),
+                       C.POINTER(Detector), C.POINTER(Run), C.POINTER(_TallyC)]
+        L.mc_simulate_batch.argtypes = _batch_args + [C.c_void_p]
+        L.mc_autotune_batch.argtypes = _batch_args + [C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_uint32),
+                                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]
         L.mc_last_error.restype = C.c_char_p
         L.mc_version.restype = C.c_int
-        for f in ("mie_table_build", "mie_table_enqueue", "mc_simulate", "mc_grad", "mc_philox_blocks"):
+        for f in ("mie_table_build", "mie_table_enqueue", "mc_simulate", "mc_grad", "mc_philox_blocks",
+                  "mc_simulate_batch", "mc_autotune_batch"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -180,6 +197,10 @@ def mc_workspace_bytes(det: Detector) -> int:
     return int(lib().mc_workspace_bytes(C.byref(det)))
 
 
+def mc_workspace_bytes_batch(det: Detector, n_items: int) -> int:
+    return int(lib().mc_workspace_bytes_batch(C.byref(det), int(n_items)))
+
+
 @dataclass
 class Tally:
     """Caller-owned device outputs and workspace of mc_simulate.  Images are
@@ -223,6 +244,26 @@ class Tally:
             t.rec_f = torch.empty((MC_REC_F_N, record_rows), dtype=torch.float32, device=dev)
         return t
 
+    @staticmethod
+    def alloc_batch(det: Detector, n_items: int, device="cuda", *, sigma=False, fix64=False) -> "Tally":
+        """Item-major outputs of mc_simulate_batch for n_items media."""
+        import torch
+        dev = torch.device(device)
+        img = dict(dtype=torch.int64 if fix64 else torch.float64, device=dev)
+        probe = Detector(det.side_nx, det.side_ny, det.trans_nx, det.trans_ny,
+                         det.flags | (MC_SIGMA if sigma else 0))
+        ws_bytes = mc_workspace_bytes_batch(probe, n_items)
+        if ws_bytes == 0:
+            raise ValueError(f"invalid detector or n_items {n_items} (1..{MC_MAX_BATCH})")
+        t = Tally(torch.empty((n_items, det.side_ny, det.side_nx), **img),
+                  torch.empty((n_items, det.trans_ny, det.trans_nx), **img),
+                  torch.empty((n_items, MC_N_SCALARS), dtype=torch.float64, device=dev),
+                  torch.empty((ws_bytes + 7) // 8, dtype=torch.int64, device=dev))
+        if sigma:
+            t.side_w2 = torch.empty_like(t.side)
+            t.trans_w2 = torch.empty_like(t.trans)
+        return t
+
     def _c(self) -> _TallyC:
         c = _TallyC()
         c.side, c.trans, c.scalars = _ptr(self.side), _ptr(self.trans), _ptr(self.scalars)
@@ -257,6 +298,40 @@ def mc_grad(medium: Medium, geometry: Geometry, detector: Detector, tally: Tally
     _check(lib().mc_grad(C.byref(medium), C.byref(geometry), C.byref(detector), C.byref(tc),
                          _ptr(dloss_dside), _ptr(d2loss_dside2), float(d2loss_uniform), out, _stream(stream)))
     return tuple(out)
+
+
+def _batch_items(items) -> "C.Array":
+    arr = (BatchItem * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it
+    return arr
+
+
+def mc_simulate_batch(items, n_cdf: int, source: Source, geometry: Geometry, detector: Detector, run: Run,
+                      tally: Tally, stream=None) -> None:
+    """Enqueue the batched walk of `items` (a sequence of BatchItem, one per
+    medium; outputs item-major in `tally`, see Tally.alloc_batch)."""
+    arr = _batch_items(items)
+    tc = tally._c()
+    _check(lib().mc_simulate_batch(arr, len(items), int(n_cdf), C.byref(source), C.byref(geometry),
+                                   C.byref(detector), C.byref(run), C.byref(tc), _stream(stream)))
+
+
+def mc_autotune_batch(items, n_cdf: int, source: Source, geometry: Geometry, detector: Detector, run: Run,
+                      tally: Tally, sample_fraction: float = 0.0625, stream=None):
+    """Time every (block size, chunk) candidate on a photon sample of the
+    batch; returns (block_size, chunk, best_ms, {(block, chunk): ms}).  The
+    tally is overwritten.  Waits for the stream."""
+    arr = _batch_items(items)
+    tc = tally._c()
+    blk, chk, best = C.c_int32(), C.c_uint32(), C.c_double()
+    cand = (C.c_double * (len(AUTOTUNE_BLOCKS) * len(AUTOTUNE_CHUNKS)))()
+    _check(lib().mc_autotune_batch(arr, len(items), int(n_cdf), C.byref(source), C.byref(geometry),
+                                   C.byref(detector), C.byref(run), C.byref(tc), float(sample_fraction),
+                                   C.byref(blk), C.byref(chk), C.byref(best), cand, _stream(stream)))
+    table = {(b, c): cand[i * len(AUTOTUNE_CHUNKS) + j]
+             for i, b in enumerate(AUTOTUNE_BLOCKS) for j, c in enumerate(AUTOTUNE_CHUNKS)}
+    return blk.value, chk.value, best.value, table
 
 
 def mc_philox_blocks(seed: int, instance: int, ids, step0: int, n_steps: int, out, stream=None) -> None:

@@ -2,7 +2,7 @@
 the C-ABI argument structs.  Pure marshalling: no arithmetic of the method."""
 from __future__ import annotations
 
-from ._capi import MC_PHASE_MIE, Detector, Geometry, Medium, MieSpec, Run, Source
+from ._capi import MC_PHASE_MIE, BatchItem, Detector, Geometry, Medium, MieSpec, Run, Source
 
 
 def args_from_workload(w, table=None, *, g=None, flags=0, record_stride=1, block_size=0, grid_blocks=0,
@@ -33,3 +33,9 @@ def args_from_workload(w, table=None, *, g=None, flags=0, record_stride=1, block
               roulette_p=w.roulette_p, record_stride=record_stride, block_size=block_size,
               grid_blocks=grid_blocks)
     return spec, med, src, geo, det, run
+
+
+def batch_item(w, table) -> BatchItem:
+    """BatchItem for workload `w` with its Mie table (from mie_table_build)."""
+    return BatchItem(tau=w.tau, albedo=w.albedo, inv_cdf=table.inv_cdf.data_ptr(), n_photons=w.n_photons,
+                     instance=w.instance)

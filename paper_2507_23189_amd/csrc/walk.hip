@@ -41,12 +41,24 @@
 
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
+#include <vector>
 
 #include "common.hpp"
 #include "philox.hpp"
 
 namespace mcmie {
 namespace {
+
+// One medium of a batched launch, in the order its work units are handed out.
+struct BatchInst {
+    float neg_ln2_over_mu, albedo, absorb, pad;   // as WalkArgs, for this medium
+    const float *inv_cdf;     // device inverse table of this medium (n_cdf entries)
+    uint64_t n_photons;
+    uint64_t unit_begin;      // first work unit of this medium
+    uint32_t counter;         // Philox counter word 1 of its photons
+    uint32_t slot;            // index of its images and scalars in the caller's arrays
+};
 
 struct WalkArgs {
     float size[3];
@@ -76,6 +88,11 @@ struct WalkArgs {
     double *side_wk, *side_wl;     // MC_MOMENTS: per side pixel, sum w k and sum w L
     double *side_w2k, *side_w2l;   // MC_MOMENTS_PIXEL2: per side pixel, sum w^2 k and sum w^2 L
     uint64_t rec_rows, record_stride;
+    // Batched launch: media in schedule order, work units over all of them.
+    const BatchInst *insts;
+    uint32_t n_inst;          // media (slots) in the launch
+    uint32_t n_pix_inst;      // side + transmitted pixels of one medium (key stride)
+    uint64_t n_units;
 };
 
 constexpr int kCopies = 8;                 // per-XCD image copies in the workspace
@@ -138,58 +155,78 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 constexpr int kQueue = 64;                 // queued image exits per wave
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;   // free tally-cache slot
 
-constexpr int kOptSigma = 1, kOptRecord = 2, kOptMoments = 4;
+constexpr int kOptSigma = 1, kOptRecord = 2, kOptMoments = 4, kOptBatch = 8;
+constexpr int kBatchScal = 16;             // LDS scalar words per medium in a batched launch
+constexpr uint64_t kWsScalarWords = 32;    // workspace scalar words per medium
+constexpr int kLdsBallistic = 15;          // LDS scalar word (per medium) counting first-step exits
+constexpr int kWsBallistic = 19;           // workspace word (per medium) of that count
+constexpr int kWsBeamKey = 20;             // workspace word (first medium): beam exit key + 1, or 0
 
 template <int PHASE, int OPT>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void walk_kernel(WalkArgs a)
 {
     constexpr bool SIGMA = OPT & kOptSigma, RECORD = OPT & kOptRecord, MOMENTS = OPT & kOptMoments;
-    // LDS layout: inverse table (n_cdf floats, padded to 4), 16 scalar doubles,
-    // tally cache (slots doubles of weight, [SIGMA] slots doubles of squared
-    // weight, slots uint32 keys), per-wave exit queues (3 x kQueue floats).
-    extern __shared__ float s_table[];
-    unsigned long long *s_scal = (unsigned long long *)(s_table + ((a.n_cdf + 3) & ~3));
+    constexpr bool BATCH = OPT & kOptBatch;
+    // LDS layout: inverse table (n_cdf floats, padded to 4; batched launches
+    // read each medium's table from global memory instead), scalar words
+    // (MC_N_SCALARS, or kBatchScal per medium), tally cache (slots words of
+    // weight, [SIGMA] slots words of squared weight, slots uint32 keys),
+    // per-wave exit queues (3 x kQueue floats, a fourth for the medium's slot).
+    // (The kernel declares no static LDS: the dynamic array starts at offset 0,
+    // and its 16-byte alignment keeps the 64-bit words below aligned.)
+    extern __shared__ __attribute__((aligned(16))) float s_table[];
+    constexpr int kQueueArrays = BATCH ? 4 : 3;
+    unsigned long long *s_scal = (unsigned long long *)(s_table + (BATCH ? 0 : ((a.n_cdf + 3) & ~3)));
+    const int n_scal = BATCH ? (int)a.n_inst * kBatchScal : MC_N_SCALARS;
     const int slots = a.cache_bits ? 1 << a.cache_bits : 0;
-    unsigned long long *s_cw = s_scal + MC_N_SCALARS;
+    unsigned long long *s_cw = s_scal + n_scal;
     unsigned long long *s_cw2 = s_cw + (SIGMA ? slots : 0);
     uint32_t *s_key = (uint32_t *)(s_cw2 + slots);
     float *s_queue = (float *)(s_key + slots);
 
-    if (PHASE == MC_PHASE_MIE)
+    if (PHASE == MC_PHASE_MIE && !BATCH)
         for (int i = threadIdx.x; i < a.n_cdf; i += blockDim.x) s_table[i] = a.inv_cdf[i];
-    if (threadIdx.x < MC_N_SCALARS) s_scal[threadIdx.x] = 0ull;
+    for (int i = threadIdx.x; i < n_scal; i += blockDim.x) s_scal[i] = 0ull;
     for (int i = threadIdx.x; i < slots; i += blockDim.x) {
         s_cw[i] = 0ull;
         if (SIGMA) s_cw2[i] = 0ull;
         s_key[i] = kEmpty;
     }
-    __syncthreads();
-    // Seed the cache with the pixel where unscattered photons leave (the
-    // hottest pixel of a pencil beam), so no other pixel can take its slot.
-    if (slots && threadIdx.x == 0) {
+    // Unscattered photons that leave on their first step all take the same
+    // path from the source to the same pixel with the same weight w0, so the
+    // walk only counts them (per medium) and the finalize pass adds count x w0
+    // to that pixel.  The pixel (its key within a medium's key range) and face
+    // are found here, by every thread, with the walk's own arithmetic; face -1
+    // when the beam leaves through a face without an image (or through the
+    // side image while its path moments are tallied).
+    int beam_face = -1;
+    {
         int ax;
         const float db = wall_distance(a.pos0[0], a.pos0[1], a.pos0[2], a.dir0[0], a.dir0[1], a.dir0[2],
                                        a.size[0], a.size[1], a.size[2], ax);
         const float bx = fmaf(db, a.dir0[0], a.pos0[0]), by = fmaf(db, a.dir0[1], a.pos0[1]);
         const float bz = fmaf(db, a.dir0[2], a.pos0[2]);
         const float da = ax == 0 ? a.dir0[0] : (ax == 1 ? a.dir0[1] : a.dir0[2]);
-        if (da > 0.f && (ax == 0 || ax == 2)) {
-            const uint32_t key =
-                ax == 0 ? (uint32_t)(pixel(by, a.size[1], a.side_ny) * a.side_nx + pixel(bz, a.size[2], a.side_nx))
-                        : a.n_side + (uint32_t)(pixel(by, a.size[1], a.trans_ny) * a.trans_nx +
-                                                pixel(bx, a.size[0], a.trans_nx));
-            s_key[(key * 2654435761u) >> (32 - a.cache_bits)] = key;
+        int face = -1;
+        uint32_t key = 0;
+        if (da > 0.f && (ax == 0 || ax == 2) && !(MOMENTS && ax == 0)) {
+            face = 2 * ax + 1;
+            key = ax == 0 ? (uint32_t)(pixel(by, a.size[1], a.side_ny) * a.side_nx + pixel(bz, a.size[2], a.side_nx))
+                          : a.n_side + (uint32_t)(pixel(by, a.size[1], a.trans_ny) * a.trans_nx +
+                                                  pixel(bx, a.size[0], a.trans_nx));
+            if (blockIdx.x == 0 && threadIdx.x == 0) a.ws_scal[kWsBeamKey] = (unsigned long long)key + 1ull;
         }
+        beam_face = face;
     }
-    __syncthreads();
 
     const int lane = __lane_id();
     const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) % kCopies;   // hwreg(HW_REG_XCC_ID, 0, 4)
     unsigned long long *my_img = a.ws_img + (uint64_t)xcc * a.n_pix;
     unsigned long long *my_img2 = SIGMA ? a.ws_img2 + (uint64_t)xcc * a.n_pix : nullptr;
-    float *q_y = s_queue + (threadIdx.x >> 6) * (3 * kQueue);
+    float *q_y = s_queue + (threadIdx.x >> 6) * (kQueueArrays * kQueue);
     float *q_b = q_y + kQueue;
     float *q_w = q_b + kQueue;                 // weight bits, bit 31 set for the side image
+    float *q_s = q_w + kQueue;                 // batched: the medium's slot (uint32 bits)
     uint32_t q_n = 0;                          // wave-uniform queue fill
 
     // Tally the first n queued exits, one per lane: pixel key, then the LDS
@@ -203,10 +240,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             const bool side = wb >> 31;
             const float wf = __uint_as_float(wb & 0x7FFFFFFFu);
             const unsigned long long wq = fix(wf), wq2 = SIGMA ? fix(wf * wf) : 0ull;
+            const uint32_t key_base = BATCH ? __float_as_uint(q_s[lane]) * a.n_pix_inst : 0u;
             const uint32_t key =
-                side ? (uint32_t)(pixel(y, a.size[1], a.side_ny) * a.side_nx + pixel(b, a.size[2], a.side_nx))
-                     : a.n_side + (uint32_t)(pixel(y, a.size[1], a.trans_ny) * a.trans_nx +
-                                             pixel(b, a.size[0], a.trans_nx));
+                key_base +
+                (side ? (uint32_t)(pixel(y, a.size[1], a.side_ny) * a.side_nx + pixel(b, a.size[2], a.side_nx))
+                      : a.n_side + (uint32_t)(pixel(y, a.size[1], a.trans_ny) * a.trans_nx +
+                                              pixel(b, a.size[0], a.trans_nx)));
             bool cached = false;
             if (slots) {
                 uint32_t slot = (key * 2654435761u) >> (32 - a.cache_bits);
@@ -245,19 +284,54 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     uint32_t k = 0, step = 0;
     // Lane accumulators.
     unsigned long long acc_abs = 0ull;
-    uint32_t acc_events = 0, acc_steps = 0, acc_refl = 0, acc_photons = 0;
+    uint32_t acc_events = 0, acc_steps = 0, acc_refl = 0, acc_photons = 0, acc_ball = 0;
+    // The medium of the lane's photon (batched launches change it per photon;
+    // otherwise these stay the launch's values).
+    uint32_t l_slot = kEmpty, q_p = 0;
+    float l_mu = a.neg_ln2_over_mu, l_alb = a.albedo, l_abs = a.absorb;
+    const float *l_tab = a.inv_cdf;
+    uint32_t l_ctr = a.instance;
+    // Batched: move the lane accumulators into the LDS scalars of its medium.
+    auto flush_lane = [&]() {
+        unsigned long long *sc = s_scal + l_slot * kBatchScal;
+        atomicAdd(&sc[MC_S_ABSORBED], acc_abs);
+        atomicAdd(&sc[MC_S_EVENTS], (unsigned long long)acc_events);
+        atomicAdd(&sc[MC_S_STEPS], (unsigned long long)acc_steps);
+        atomicAdd(&sc[MC_S_REFLECTIONS], (unsigned long long)acc_refl);
+        atomicAdd(&sc[MC_S_PHOTONS], (unsigned long long)acc_photons);
+        if (acc_ball) atomicAdd(&sc[kLdsBallistic], (unsigned long long)acc_ball);
+        acc_abs = 0ull;
+        acc_events = acc_steps = acc_refl = acc_photons = acc_ball = 0;
+    };
 
     for (;;) {
         // ---- refill lanes whose photon has ended -------------------------
         const uint64_t need = __ballot(!alive);
         if (need) {
             if (q_rem == 0 && !exhausted) {
+                // Single medium: claim the next `chunk` photon ids.  Batched:
+                // claim the next work unit, `chunk` photons of one medium.
                 unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd(work, (unsigned long long)a.chunk);
+                if (lane == 0) base = atomicAdd(work, BATCH ? 1ull : (unsigned long long)a.chunk);
                 const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
                 const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
                 const uint64_t b = ((uint64_t)hi << 32) | lo;
-                if (b >= a.n_photons) {
+                if (BATCH) {
+                    if (b >= a.n_units) {
+                        exhausted = true;
+                    } else {
+                        // The unit's medium: the last one whose first unit is <= b
+                        // (media without photons own no units and are never found).
+                        uint32_t l = 0, h = a.n_inst;
+                        while (h - l > 1) {
+                            const uint32_t mid = (l + h) >> 1;
+                            if (a.insts[mid].unit_begin <= b) l = mid; else h = mid;
+                        }
+                        q_p = l;
+                        q_next = (b - a.insts[l].unit_begin) * a.chunk;
+                        q_rem = (uint32_t)min((uint64_t)a.chunk, a.insts[l].n_photons - q_next);
+                    }
+                } else if (b >= a.n_photons) {
                     exhausted = true;
                 } else {
                     q_next = b;
@@ -267,7 +341,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
             if (!alive && rank < q_rem) {
-                id = a.photon_offset + q_next + rank;
+                id = (BATCH ? 0ull : a.photon_offset) + q_next + rank;
+                if (BATCH) {
+                    const BatchInst &bi = a.insts[q_p];
+                    if (bi.slot != l_slot) {
+                        if (l_slot != kEmpty) flush_lane();
+                        l_slot = bi.slot;
+                        l_mu = bi.neg_ln2_over_mu;
+                        l_alb = bi.albedo;
+                        l_abs = bi.absorb;
+                        l_tab = bi.inv_cdf;
+                        l_ctr = bi.counter;
+                    }
+                }
                 alive = true;
                 px = a.pos0[0]; py = a.pos0[1]; pz = a.pos0[2];
                 dx = a.dir0[0]; dy = a.dir0[1]; dz = a.dir0[2];
@@ -281,16 +367,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 
         bool ended = false;
         int cause = 0, face = -1, axis = 0;
+        const uint32_t scal_at = BATCH ? l_slot * kBatchScal : 0u;   // the medium's LDS scalars
         if (alive) {
             // ---- one step ---------------------------------------------------
             // The round keys derive from the seed inside the loop (scalar adds)
             // rather than living in 20 scalar registers across it.
             uint32_t k0 = a.key0, k1 = a.key1;
             asm volatile("" : "+s"(k0), "+s"(k1));
-            const Block4 r = philox4x32_10(step, a.instance, (uint32_t)id, (uint32_t)(id >> 32), k0, k1);
+            const Block4 r = philox4x32_10(step, l_ctr, (uint32_t)id, (uint32_t)(id >> 32), k0, k1);
             const float u0 = uniform01(r.r0), u1 = uniform01(r.r1);
             const float u2 = uniform01(r.r2), u3 = uniform01(r.r3);
-            const float s = __builtin_amdgcn_logf(u0) * a.neg_ln2_over_mu;     // Eq. 15
+            const float s = __builtin_amdgcn_logf(u0) * l_mu;     // Eq. 15
             ++step;
 
             // Nearest wall along the direction.
@@ -329,16 +416,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             } else {
                 // Interaction: count, absorb (Eq. 16), roulette, scatter.
                 ++k;
-                A = fmaf(w, a.absorb, A);
-                w *= a.albedo;
+                A = fmaf(w, l_abs, A);
+                w *= l_alb;
                 if (w < a.roulette_w) {
                     if (u3 < a.roulette_p) {
                         const float wn = w * a.inv_roulette_p;
-                        atomicAdd(&s_scal[MC_S_ROULETTE_NET], fix(wn) - fix(w));
+                        atomicAdd(&s_scal[scal_at + MC_S_ROULETTE_NET], fix(wn) - fix(w));
                         w = wn;
                     } else {
-                        atomicAdd(&s_scal[MC_S_ROULETTE_NET], 0ull - fix(w));
-                        atomicAdd(&s_scal[MC_S_ROULETTE_KILLS], 1ull);
+                        atomicAdd(&s_scal[scal_at + MC_S_ROULETTE_NET], 0ull - fix(w));
+                        atomicAdd(&s_scal[scal_at + MC_S_ROULETTE_KILLS], 1ull);
                         w = 0.f;
                         ended = true;
                         cause = 1;
@@ -350,7 +437,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                         const float tt = u1 * tab_scale;
                         const int i = min((int)tt, tab_last);
                         const float f = tt - (float)i;
-                        const float t0 = s_table[i], t1 = s_table[i + 1];
+                        const float t0 = BATCH ? l_tab[i] : s_table[i], t1 = BATCH ? l_tab[i + 1] : s_table[i + 1];
                         v = fmaf(f, t1 - t0, t0);
                     } else {
                         const float D = fmaf(-a.hg_b, u1, a.hg_a);
@@ -377,12 +464,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             if (!ended && step >= a.max_steps) {
                 ended = true;
                 cause = 2;
-                atomicAdd(&s_scal[MC_S_CAPPED_W], fix(w));
-                atomicAdd(&s_scal[MC_S_CAPPED], 1ull);
+                atomicAdd(&s_scal[scal_at + MC_S_CAPPED_W], fix(w));
+                atomicAdd(&s_scal[scal_at + MC_S_CAPPED], 1ull);
             }
             if (ended) {
                 // Faces +x and +z are totalled from their images when finalizing.
-                if (cause == 0 && face != 1 && face != 5) atomicAdd(&s_scal[MC_S_FACE + face], fix(w));
+                if (cause == 0 && face != 1 && face != 5) atomicAdd(&s_scal[scal_at + MC_S_FACE + face], fix(w));
                 if (MOMENTS && cause == 0 && face == 1) {
                     // Path moments of the side image (perturbation Monte Carlo):
                     // first order per pixel, second order summed over the image
@@ -439,7 +526,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         }
 
         // ---- queue exits through the imaged faces (+x side, +z transmitted) ----
-        const bool to_img = ended && cause == 0 && (face == 1 || face == 5);
+        const bool ballistic = ended && cause == 0 && k == 0 && step == 1 && face == beam_face;
+        acc_ball += ballistic ? 1u : 0u;
+        const bool to_img = ended && cause == 0 && (face == 1 || face == 5) && !ballistic;
         const uint64_t m = __ballot(to_img);
         if (m) {
             const uint32_t n_push = __popcll(m);
@@ -453,6 +542,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 q_y[at] = py;
                 q_b[at] = face == 1 ? pz : px;
                 q_w[at] = __uint_as_float(__float_as_uint(w) | (face == 1 ? 0x80000000u : 0u));
+                if (BATCH) q_s[at] = __uint_as_float(l_slot);
             }
             q_n += n_push;
         }
@@ -460,23 +550,39 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     flush(q_n);
 
     // ---- block-level flush of the scalar tallies and the cache ---------------
-    const unsigned long long wabs = wave_sum(acc_abs);
-    const uint32_t wev = wave_sum(acc_events), wst = wave_sum(acc_steps), wrf = wave_sum(acc_refl),
-                   wph = wave_sum(acc_photons);
-    if (lane == 0) {
-        atomicAdd(&s_scal[MC_S_ABSORBED], wabs);
-        atomicAdd(&s_scal[MC_S_EVENTS], (unsigned long long)wev);
-        atomicAdd(&s_scal[MC_S_STEPS], (unsigned long long)wst);
-        atomicAdd(&s_scal[MC_S_REFLECTIONS], (unsigned long long)wrf);
-        atomicAdd(&s_scal[MC_S_PHOTONS], (unsigned long long)wph);
-    }
-    __syncthreads();
-    if (threadIdx.x < MC_S_RESERVED) {
-        const unsigned long long v = s_scal[threadIdx.x];
-        if (v != 0ull) atomicAdd(&a.ws_scal[threadIdx.x], v);
-    } else if (MOMENTS && threadIdx.x >= MC_S_SIDE_W2 && threadIdx.x <= MC_S_SIDE_W2L) {
-        const double v = __longlong_as_double((long long)s_scal[threadIdx.x]);
-        if (v != 0.0) atomicAdd((double *)&a.ws_scal[threadIdx.x], v);
+    if (BATCH) {
+        if (l_slot != kEmpty) flush_lane();
+        __syncthreads();
+        for (int i = threadIdx.x; i < n_scal; i += blockDim.x) {
+            const int j = i % kBatchScal;
+            const unsigned long long v = s_scal[i];
+            if (v != 0ull && (j < MC_S_RESERVED || j == kLdsBallistic))
+                atomicAdd(&a.ws_scal[(uint64_t)(i / kBatchScal) * kWsScalarWords +
+                                     (j == kLdsBallistic ? kWsBallistic : j)], v);
+        }
+    } else {
+        const unsigned long long wabs = wave_sum(acc_abs);
+        const uint32_t wev = wave_sum(acc_events), wst = wave_sum(acc_steps), wrf = wave_sum(acc_refl),
+                       wph = wave_sum(acc_photons), wbl = wave_sum(acc_ball);
+        if (lane == 0) {
+            if (wbl) atomicAdd(&s_scal[kLdsBallistic], (unsigned long long)wbl);
+            atomicAdd(&s_scal[MC_S_ABSORBED], wabs);
+            atomicAdd(&s_scal[MC_S_EVENTS], (unsigned long long)wev);
+            atomicAdd(&s_scal[MC_S_STEPS], (unsigned long long)wst);
+            atomicAdd(&s_scal[MC_S_REFLECTIONS], (unsigned long long)wrf);
+            atomicAdd(&s_scal[MC_S_PHOTONS], (unsigned long long)wph);
+        }
+        __syncthreads();
+        if (threadIdx.x < MC_S_RESERVED) {
+            const unsigned long long v = s_scal[threadIdx.x];
+            if (v != 0ull) atomicAdd(&a.ws_scal[threadIdx.x], v);
+        } else if (threadIdx.x == kLdsBallistic) {
+            const unsigned long long v = s_scal[kLdsBallistic];
+            if (v != 0ull) atomicAdd(&a.ws_scal[kWsBallistic], v);
+        } else if (MOMENTS && threadIdx.x >= MC_S_SIDE_W2 && threadIdx.x <= MC_S_SIDE_W2L) {
+            const double v = __longlong_as_double((long long)s_scal[threadIdx.x]);
+            if (v != 0.0) atomicAdd((double *)&a.ws_scal[threadIdx.x], v);
+        }
     }
     for (int i = threadIdx.x; i < slots; i += blockDim.x) {
         const uint32_t key = s_key[i];
@@ -490,7 +596,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 // not memset, so the sequence stays valid under stream capture.)
 __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long long *side, unsigned long long *trans,
                             unsigned long long *side_w2, unsigned long long *trans_w2, size_t n_side, size_t n_trans,
-                            double *scalars, int32_t *rec_i, float *rec_f, size_t n_rec, double *side_wk,
+                            double *scalars, size_t n_scalars, int32_t *rec_i, float *rec_f, size_t n_rec,
+                            double *side_wk,
                             double *side_wl, double *side_w2k, double *side_w2l, int zero_all)
 {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -513,7 +620,7 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
         trans[i] = 0ull;
         if (trans_w2) trans_w2[i] = 0ull;
     }
-    if (t0 < MC_N_SCALARS) scalars[t0] = 0.0;
+    for (size_t i = t0; i < n_scalars; i += stride) scalars[i] = 0.0;
     for (size_t i = t0; i < (size_t)MC_REC_I_N * n_rec; i += stride) rec_i[i] = (i / n_rec == MC_REC_I_FACE) ? -1 : 0;
     for (size_t i = t0; i < (size_t)MC_REC_F_N * n_rec; i += stride) rec_f[i] = 0.f;
 }
@@ -522,17 +629,36 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
 // order is immaterial) and add them to the caller's images, as int64 (FIX) or
 // converted to double.  Weight sums of the +x and +z images also give those
 // faces' totals.
+// One medium per blockIdx.y: its pixels are keys [y * n_pix, (y + 1) * n_pix)
+// of copies that hold n_total keys each; its images start at y * n_side and
+// y * (n_pix - n_side) in the outputs and its face totals are at
+// face_side / face_trans + y * face_stride.
+//
+// Unscattered first-step exits were only counted (workspace word kWsBallistic
+// of each medium); the beam pixel (word kWsBeamKey) gets count x ball_w.
 template <bool FIX>
-__global__ __launch_bounds__(256) void finalize_images(const unsigned long long *copies, uint64_t n_pix,
-                                                       uint32_t n_side, void *side, void *trans,
-                                                       unsigned long long *face_side, unsigned long long *face_trans)
+__global__ __launch_bounds__(256) void finalize_images(const unsigned long long *copies, uint64_t n_total,
+                                                       uint64_t n_pix, uint32_t n_side, void *side, void *trans,
+                                                       unsigned long long *face_side, unsigned long long *face_trans,
+                                                       uint64_t face_stride, const unsigned long long *ws_scal,
+                                                       unsigned long long ball_w)
 {
+    const uint64_t inst = blockIdx.y;
+    const uint64_t key0 = inst * n_pix;
+    side = FIX ? (void *)((long long *)side + inst * n_side) : (void *)((double *)side + inst * n_side);
+    trans = FIX ? (void *)((long long *)trans + inst * (n_pix - n_side))
+                : (void *)((double *)trans + inst * (n_pix - n_side));
+    if (face_side) {
+        face_side += inst * face_stride;
+        face_trans += inst * face_stride;
+    }
     unsigned long long sum_side = 0ull, sum_trans = 0ull;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pix;
          i += (uint64_t)gridDim.x * blockDim.x) {
         unsigned long long v = 0ull;
 #pragma unroll
-        for (int c = 0; c < kCopies; ++c) v += copies[(uint64_t)c * n_pix + i];
+        for (int c = 0; c < kCopies; ++c) v += copies[(uint64_t)c * n_total + key0 + i];
+        if (ws_scal[kWsBeamKey] == i + 1) v += ws_scal[inst * kWsScalarWords + kWsBallistic] * ball_w;
         const bool is_side = i < n_side;
         const uint64_t j = is_side ? i : i - n_side;
         if (FIX) {
@@ -566,8 +692,11 @@ __global__ __launch_bounds__(256) void finalize_images(const unsigned long long 
 
 // Fixed-point scalar sums to the caller's doubles (weights scaled back by
 // 2^-32, counts as they are); the second-order side moments are FP64 sums.
+// One medium per block.
 __global__ void finalize_scalars(const unsigned long long *ws_scal, double *scalars)
 {
+    ws_scal += (uint64_t)blockIdx.x * kWsScalarWords;
+    scalars += (uint64_t)blockIdx.x * MC_N_SCALARS;
     const int t = threadIdx.x;
     if (t < MC_S_RESERVED) {
         const bool weight = t <= MC_S_CAPPED_W;
@@ -627,106 +756,85 @@ __global__ __launch_bounds__(1024) void grad_dot(const double *g, const double *
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// Workspace layout: 32 uint64 scalar words (0..14 fixed-point scalar sums,
-// 15 the photon work counter, 16..18 FP64 second-order side moments, 24..27
-// mc_grad's dot products), then kCopies fixed-point copies of the images (and
-// of the squared-weight images with MC_SIGMA).
-constexpr uint64_t kWsScalarWords = 32;
-
-uint64_t workspace_words(const mc_detector_t &d)
+// Workspace layout: per medium kWsScalarWords uint64 scalar words (0..14
+// fixed-point scalar sums, 15 the photon work counter (first medium), 16..18
+// FP64 second-order side moments, 24..27 mc_grad's dot products), then
+// kCopies fixed-point copies of the images of every medium (and of the
+// squared-weight images with MC_SIGMA); a batched launch appends its schedule
+// (one BatchInst per medium).
+uint64_t workspace_words(const mc_detector_t &d, uint64_t n_inst = 1)
 {
     const uint64_t n_pix = (uint64_t)d.side_nx * d.side_ny + (uint64_t)d.trans_nx * d.trans_ny;
-    return kWsScalarWords + (uint64_t)kCopies * n_pix * ((d.flags & MC_SIGMA) ? 2 : 1);
+    return kWsScalarWords * n_inst + (uint64_t)kCopies * n_pix * n_inst * ((d.flags & MC_SIGMA) ? 2 : 1);
 }
 
-}  // namespace
-}  // namespace mcmie
-
-extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
-                           const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,
-                           void *stream)
+uint64_t batch_workspace_words(const mc_detector_t &d, uint64_t n_items)
 {
-    using namespace mcmie;
-    clear_error();
-    if (!medium || !source || !geometry || !detector || !run || !tally)
-        return fail(MC_EINVAL, "mc_simulate: null argument");
-    const mc_medium_t m = *medium;
-    const mc_source_t src = *source;
-    const mc_geometry_t geo = *geometry;
-    const mc_detector_t det = *detector;
-    const mc_run_t rn = *run;
-    const mc_tally_t t = *tally;
+    return workspace_words(d, n_items) + (n_items * sizeof(BatchInst) + 7) / 8;
+}
 
-    // ---- parameter checks (Sec. 3.1.1) ----
+bool dims_ok(const mc_detector_t &d) { return d.side_nx >= 1 && d.side_ny >= 1 && d.trans_nx >= 1 && d.trans_ny >= 1; }
+
+// Checks of the cuboid and its walls (Sec. 3.1.1: parameter validity).
+int check_geometry(const char *fn, const mc_geometry_t &geo)
+{
     for (int i = 0; i < 3; ++i)
-        if (!finite_pos(geo.size_mm[i])) return fail(MC_EINVAL, "mc_simulate: size_mm[%d] must be > 0", i);
+        if (!finite_pos(geo.size_mm[i])) return fail(MC_EINVAL, "%s: size_mm[%d] must be > 0", fn, i);
     if (!finite_pos(geo.n_medium) || !finite_pos(geo.n_outside))
-        return fail(MC_EINVAL, "mc_simulate: refractive indices must be > 0");
-    if (!(m.tau >= 0.0) || !std::isfinite(m.tau)) return fail(MC_EINVAL, "mc_simulate: tau must be >= 0");
-    if (!(m.albedo >= 0.0 && m.albedo <= 1.0)) return fail(MC_EINVAL, "mc_simulate: albedo must be in [0, 1]");
-    if (m.phase == MC_PHASE_MIE) {
-        if (m.n_cdf < 2 || m.n_cdf > MC_MAX_N_CDF)
-            return fail(MC_EINVAL, "mc_simulate: n_cdf %d outside 2..%d", m.n_cdf, MC_MAX_N_CDF);
-        if (!m.inv_cdf) return fail(MC_EINVAL, "mc_simulate: inv_cdf is required for MC_PHASE_MIE");
-    } else if (m.phase == MC_PHASE_HG) {
-        if (!(m.g > -1.0 && m.g < 1.0)) return fail(MC_EINVAL, "mc_simulate: HG g must be in (-1, 1)");
-    } else {
-        return fail(MC_EINVAL, "mc_simulate: unknown phase %d", m.phase);
-    }
+        return fail(MC_EINVAL, "%s: refractive indices must be > 0", fn);
+    return MC_OK;
+}
+
+// Checks of the source, detector, tally buffers and run settings shared by
+// single and batched walks.
+int check_setup(const char *fn, const mc_source_t &src, const mc_geometry_t &geo, const mc_detector_t &det,
+                const mc_run_t &rn, const mc_tally_t &t)
+{
     if (!(src.pos_mm[2] == 0.0) || !(src.pos_mm[0] >= 0.0 && src.pos_mm[0] <= geo.size_mm[0]) ||
         !(src.pos_mm[1] >= 0.0 && src.pos_mm[1] <= geo.size_mm[1]))
-        return fail(MC_EINVAL, "mc_simulate: the source must lie on the z = 0 face");
+        return fail(MC_EINVAL, "%s: the source must lie on the z = 0 face", fn);
     const double dl = std::sqrt(src.dir[0] * src.dir[0] + src.dir[1] * src.dir[1] + src.dir[2] * src.dir[2]);
     if (!(dl > 0.0) || !std::isfinite(dl) || !(src.dir[2] > 0.0))
-        return fail(MC_EINVAL, "mc_simulate: the source direction must point into the cuboid (dir[2] > 0)");
-    if (det.side_nx < 1 || det.side_ny < 1 || det.trans_nx < 1 || det.trans_ny < 1)
-        return fail(MC_EINVAL, "mc_simulate: image dimensions must be >= 1");
-    if (!t.side || !t.trans || !t.scalars) return fail(MC_EINVAL, "mc_simulate: side, trans and scalars are required");
+        return fail(MC_EINVAL, "%s: the source direction must point into the cuboid (dir[2] > 0)", fn);
+    if (!dims_ok(det)) return fail(MC_EINVAL, "%s: image dimensions must be >= 1", fn);
+    if (!t.side || !t.trans || !t.scalars) return fail(MC_EINVAL, "%s: side, trans and scalars are required", fn);
     if ((det.flags & MC_SIGMA) && (!t.side_w2 || !t.trans_w2))
-        return fail(MC_EINVAL, "mc_simulate: MC_SIGMA needs side_w2 and trans_w2");
-    if ((det.flags & MC_RECORD) && (rn.record_stride < 1 || (t.rec_rows > 0 && (!t.rec_i || !t.rec_f))))
-        return fail(MC_EINVAL, "mc_simulate: MC_RECORD needs record_stride >= 1 and, for rec_rows > 0, "
-                               "rec_i and rec_f");
-    if (rn.max_steps < 1) return fail(MC_EINVAL, "mc_simulate: max_steps must be >= 1");
+        return fail(MC_EINVAL, "%s: MC_SIGMA needs side_w2 and trans_w2", fn);
+    if (rn.max_steps < 1) return fail(MC_EINVAL, "%s: max_steps must be >= 1", fn);
     if (!(rn.roulette_w >= 0.0) || !(rn.roulette_p > 0.0 && rn.roulette_p <= 1.0))
-        return fail(MC_EINVAL, "mc_simulate: roulette_w >= 0 and roulette_p in (0, 1] required");
-    if (rn.photon_offset > UINT64_MAX - rn.n_photons) return fail(MC_EINVAL, "mc_simulate: photon ids overflow");
+        return fail(MC_EINVAL, "%s: roulette_w >= 0 and roulette_p in (0, 1] required", fn);
     if (rn.block_size != 0 && (rn.block_size < 64 || rn.block_size > 1024 || rn.block_size % 64))
-        return fail(MC_EINVAL, "mc_simulate: block_size must be a multiple of 64 in 64..1024");
-    if (rn.grid_blocks < 0) return fail(MC_EINVAL, "mc_simulate: grid_blocks must be >= 0");
-    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64 | MC_MOMENTS | MC_MOMENTS_PIXEL2))
-        return fail(MC_EINVAL, "mc_simulate: unknown detector flags 0x%x", det.flags);
-    if ((det.flags & MC_MOMENTS) && (!t.side_wk || !t.side_wl))
-        return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS needs side_wk and side_wl");
-    if ((det.flags & MC_MOMENTS_PIXEL2) && (!(det.flags & MC_MOMENTS) || !t.side_w2k || !t.side_w2l))
-        return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS_PIXEL2 needs MC_MOMENTS, side_w2k and side_w2l");
-    if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < workspace_words(det) * 8)
-        return fail(MC_EINVAL, "mc_simulate: workspace needs %llu bytes, 8-byte aligned",
-                    (unsigned long long)(workspace_words(det) * 8));
-    {
-        // Fixed-point sums stay below 2^63: every weight is at most
-        // max(1, roulette_w / roulette_p), so n_photons times that (squared
-        // for MC_SIGMA) must stay below 2^31.
-        const double wmax = std::max(1.0, rn.roulette_w / rn.roulette_p);
-        const double bound = (double)rn.n_photons * ((det.flags & MC_SIGMA) ? wmax * wmax : wmax);
-        if (!(bound < 2147483648.0))
-            return fail(MC_EINVAL, "mc_simulate: %llu photons with weights up to %g could overflow the "
-                        "fixed-point tallies; split the run into photon ranges",
-                        (unsigned long long)rn.n_photons, wmax);
-    }
+        return fail(MC_EINVAL, "%s: block_size must be a multiple of 64 in 64..1024", fn);
+    if (rn.grid_blocks < 0) return fail(MC_EINVAL, "%s: grid_blocks must be >= 0", fn);
+    if (rn.chunk > 65536) return fail(MC_EINVAL, "%s: chunk must be at most 65536", fn);
+    return MC_OK;
+}
 
-    // ---- derived coefficients (Eq. 1, Eq. 16) and the entry beam ----
-    WalkArgs a{};
+// Fixed-point sums stay below 2^63: every weight is at most
+// max(1, roulette_w / roulette_p), so n_photons times that (squared for
+// MC_SIGMA) must stay below 2^31.
+int check_overflow(const char *fn, uint64_t n_photons, const mc_detector_t &det, const mc_run_t &rn)
+{
+    const double wmax = std::max(1.0, rn.roulette_w / rn.roulette_p);
+    const double bound = (double)n_photons * ((det.flags & MC_SIGMA) ? wmax * wmax : wmax);
+    if (!(bound < 2147483648.0))
+        return fail(MC_EINVAL, "%s: %llu photons with weights up to %g could overflow the fixed-point tallies; "
+                    "split the run into photon ranges", fn, (unsigned long long)n_photons, wmax);
+    return MC_OK;
+}
+
+// Launch-independent kernel arguments: the cuboid and its walls, the entry
+// beam (refracted at the z = 0 face, keeping 1 - R of its weight), roulette,
+// the Philox key and the detector.
+void fill_common(WalkArgs &a, const mc_source_t &src, const mc_geometry_t &geo, const mc_detector_t &det,
+                 const mc_run_t &rn)
+{
     for (int i = 0; i < 3; ++i) a.size[i] = (float)geo.size_mm[i];
-    const double mu_t = m.tau / geo.size_mm[2];
-    a.neg_ln2_over_mu = mu_t > 0.0 ? (float)(-M_LN2 / mu_t) : -__builtin_huge_valf();
-    a.albedo = (float)m.albedo;
-    a.absorb = (float)(1.0 - m.albedo);
     a.matched = geo.n_outside == geo.n_medium;
     a.n21 = (float)(geo.n_outside / geo.n_medium);
     a.n12 = (float)(geo.n_medium / geo.n_outside);
     a.n12sq = (float)((geo.n_medium / geo.n_outside) * (geo.n_medium / geo.n_outside));
-    // The beam refracts into the medium at the z = 0 face and keeps 1 - R.
+    const double dl = std::sqrt(src.dir[0] * src.dir[0] + src.dir[1] * src.dir[1] + src.dir[2] * src.dir[2]);
     double din[3] = {src.dir[0] / dl, src.dir[1] / dl, src.dir[2] / dl};
     const double eta = geo.n_outside / geo.n_medium;
     double d0[3] = {eta * din[0], eta * din[1], 0.0};
@@ -752,6 +860,272 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     a.roulette_w = (float)rn.roulette_w;
     a.roulette_p = (float)rn.roulette_p;
     a.inv_roulette_p = (float)(1.0 / rn.roulette_p);
+    a.key0 = (uint32_t)rn.seed;
+    a.key1 = (uint32_t)(rn.seed >> 32);
+    a.max_steps = rn.max_steps;
+    a.flags = det.flags;
+    a.side_nx = det.side_nx; a.side_ny = det.side_ny;
+    a.trans_nx = det.trans_nx; a.trans_ny = det.trans_ny;
+    a.n_side = (uint32_t)((uint64_t)det.side_nx * det.side_ny);
+    a.n_pix_inst = (uint32_t)((uint64_t)det.side_nx * det.side_ny + (uint64_t)det.trans_nx * det.trans_ny);
+}
+
+// Per-medium coefficients (Eq. 1 and Eq. 16): s = log2(u0) * neg_ln2_over_mu.
+void fill_medium(float &neg_ln2_over_mu, float &albedo, float &absorb, double tau, double alb, double size_z)
+{
+    const double mu_t = tau / size_z;
+    neg_ln2_over_mu = mu_t > 0.0 ? (float)(-M_LN2 / mu_t) : -__builtin_huge_valf();
+    albedo = (float)alb;
+    absorb = (float)(1.0 - alb);
+}
+
+// A batched launch's schedule is written into the workspace by small kernels
+// whose arguments carry up to kInstPerCopy media each (no host buffer has to
+// outlive the call).
+constexpr int kInstPerCopy = 32;
+struct InstChunk {
+    BatchInst v[kInstPerCopy];
+    uint32_t n, first;
+};
+
+__global__ void set_schedule(BatchInst *dst, InstChunk c)
+{
+    if (threadIdx.x < c.n) dst[c.first + threadIdx.x] = c.v[threadIdx.x];
+}
+
+// Enqueue init, walk and finalize for n_inst media (a single medium, or a
+// batch whose schedule `sched` is given) on `st`.
+int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const mc_tally_t &t, int phase,
+                uint32_t n_inst, uint64_t total_photons, const std::vector<BatchInst> *sched, hipStream_t st)
+{
+    const bool batch = sched != nullptr;
+    int cus = 0;
+    if (int rc = device_cu_count(&cus)) return rc;
+    const uint64_t n_pix = a.n_pix_inst, n_side = a.n_side, n_trans = n_pix - n_side;
+    const uint64_t n_total = n_pix * n_inst;
+    unsigned long long *ws = (unsigned long long *)t.workspace;
+    a.ws_scal = ws;
+    a.ws_img = ws + kWsScalarWords * n_inst;
+    a.ws_img2 = (det.flags & MC_SIGMA) ? a.ws_img + (uint64_t)kCopies * n_total : nullptr;
+    a.n_pix = n_total;
+    a.n_inst = n_inst;
+
+    // ---- launch shape: 1024-lane blocks, two per CU (32 waves), each with
+    // the table (single medium), the scalar words, the per-wave exit queues and
+    // as large a tally cache as fits in half the CU's 160 KB LDS ----
+    const int block = rn.block_size ? rn.block_size : 1024;
+    const size_t table_bytes = batch ? 0 : (size_t)((a.n_cdf + 3) & ~3) * sizeof(float);
+    const size_t scal_bytes = (batch ? (size_t)n_inst * kBatchScal : MC_N_SCALARS) * sizeof(double);
+    const size_t lds_fixed = table_bytes + scal_bytes + (size_t)(block / 64) * (batch ? 4 : 3) * kQueue * sizeof(float);
+    const size_t slot_bytes = sizeof(uint32_t) + sizeof(double) * ((det.flags & MC_SIGMA) ? 2 : 1);
+    const size_t lds_half_cu = 80 * 1024;
+    a.cache_bits = 0;
+    for (int b = 10; b >= 4; --b)
+        if (lds_fixed + (slot_bytes << b) <= lds_half_cu) { a.cache_bits = b; break; }
+    const size_t lds = lds_fixed + (a.cache_bits ? (slot_bytes << a.cache_bits) : 0);
+    if (lds > 160 * 1024) return fail(MC_EINVAL, "mc_simulate: %zu bytes of LDS per block do not fit a CU", lds);
+    const int blocks_per_cu = std::max(1, std::min((int)(160 * 1024 / lds), 32 / (block / 64)));
+    const int grid = rn.grid_blocks > 0 ? rn.grid_blocks : cus * blocks_per_cu;
+    const uint64_t waves_total = (uint64_t)grid * (block / 64);
+    uint64_t chunk = rn.chunk;
+    if (chunk == 0) {
+        chunk = total_photons / std::max<uint64_t>(1, waves_total * 16);
+        chunk = std::max<uint64_t>(64, std::min<uint64_t>(1024, (chunk + 63) / 64 * 64));
+    }
+    a.chunk = (uint32_t)chunk;
+
+    const int zero_all = (det.flags & MC_ACCUMULATE) ? 0 : 1;
+    const bool sig = (det.flags & MC_SIGMA) != 0, rec = (det.flags & MC_RECORD) != 0;
+    const uint64_t ws_words = batch ? workspace_words(det, n_inst) : workspace_words(det);
+    hipLaunchKernelGGL(init_kernel, dim3(1024), dim3(256), 0, st, ws, (size_t)ws_words,
+                       (unsigned long long *)t.side, (unsigned long long *)t.trans,
+                       sig ? (unsigned long long *)t.side_w2 : nullptr, sig ? (unsigned long long *)t.trans_w2 : nullptr,
+                       (size_t)(n_side * n_inst), (size_t)(n_trans * n_inst), t.scalars,
+                       (size_t)MC_N_SCALARS * n_inst, a.rec_i, a.rec_f, (size_t)a.rec_rows, a.side_wk, a.side_wl,
+                       a.side_w2k, a.side_w2l, zero_all);
+    MC_HIP_CHECK(hipGetLastError());
+
+    using Kern = void (*)(WalkArgs);
+    Kern kern = nullptr;
+    uint64_t units = 0;
+    if (batch) {
+        // The schedule: unit ranges in schedule order, copied after the scalars
+        // and images of the workspace (after init has cleared it).
+        BatchInst *dst = (BatchInst *)(ws + ws_words);
+        std::vector<BatchInst> s = *sched;
+        for (auto &b : s) {
+            b.unit_begin = units;
+            units += (b.n_photons + chunk - 1) / chunk;
+        }
+        for (uint32_t i = 0; i < n_inst; i += kInstPerCopy) {
+            InstChunk c{};
+            c.first = i;
+            c.n = std::min<uint32_t>(kInstPerCopy, n_inst - i);
+            for (uint32_t j = 0; j < c.n; ++j) c.v[j] = s[i + j];
+            hipLaunchKernelGGL(set_schedule, dim3(1), dim3(kInstPerCopy), 0, st, dst, c);
+        }
+        MC_HIP_CHECK(hipGetLastError());
+        a.insts = dst;
+        a.n_units = units;
+        kern = sig ? walk_kernel<MC_PHASE_MIE, kOptBatch | kOptSigma> : walk_kernel<MC_PHASE_MIE, kOptBatch>;
+    } else {
+        const int opt = (sig ? kOptSigma : 0) | (rec ? kOptRecord : 0) | ((det.flags & MC_MOMENTS) ? kOptMoments : 0);
+        static const Kern mie_kernels[8] = {walk_kernel<MC_PHASE_MIE, 0>, walk_kernel<MC_PHASE_MIE, 1>,
+                                            walk_kernel<MC_PHASE_MIE, 2>, walk_kernel<MC_PHASE_MIE, 3>,
+                                            walk_kernel<MC_PHASE_MIE, 4>, walk_kernel<MC_PHASE_MIE, 5>,
+                                            walk_kernel<MC_PHASE_MIE, 6>, walk_kernel<MC_PHASE_MIE, 7>};
+        static const Kern hg_kernels[8] = {walk_kernel<MC_PHASE_HG, 0>, walk_kernel<MC_PHASE_HG, 1>,
+                                           walk_kernel<MC_PHASE_HG, 2>, walk_kernel<MC_PHASE_HG, 3>,
+                                           walk_kernel<MC_PHASE_HG, 4>, walk_kernel<MC_PHASE_HG, 5>,
+                                           walk_kernel<MC_PHASE_HG, 6>, walk_kernel<MC_PHASE_HG, 7>};
+        kern = phase == MC_PHASE_MIE ? mie_kernels[opt] : hg_kernels[opt];
+        units = total_photons;
+    }
+    if (units > 0) {
+        MC_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, a);
+        MC_HIP_CHECK(hipGetLastError());
+    }
+    // ---- finalize: per-XCD copies to the caller's images, scalars to doubles ----
+    const bool fix64 = (det.flags & MC_FIX64) != 0;
+    const unsigned fin_x = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(batch ? 64 : 512, (n_pix + 255) / 256));
+    auto fin = fix64 ? finalize_images<true> : finalize_images<false>;
+    // The fixed-point weight (and squared weight, an FP32 product as in the
+    // walk) of an unscattered first-step exit, as the walk's fix() rounds it.
+    const float w0sq = a.w0 * a.w0;
+    const unsigned long long ball_w = (unsigned long long)std::llrint((double)a.w0 * kFix);
+    const unsigned long long ball_w2 = (unsigned long long)std::llrint((double)w0sq * kFix);
+    hipLaunchKernelGGL(fin, dim3(fin_x, n_inst), dim3(256), 0, st, a.ws_img, n_total, n_pix, (uint32_t)n_side, t.side,
+                       t.trans, ws + MC_S_FACE + 1, ws + MC_S_FACE + 5, kWsScalarWords,
+                       (const unsigned long long *)ws, ball_w);
+    if (sig)
+        hipLaunchKernelGGL(fin, dim3(fin_x, n_inst), dim3(256), 0, st, a.ws_img2, n_total, n_pix, (uint32_t)n_side,
+                           t.side_w2, t.trans_w2, (unsigned long long *)nullptr, (unsigned long long *)nullptr,
+                           kWsScalarWords, (const unsigned long long *)ws, ball_w2);
+    hipLaunchKernelGGL(finalize_scalars, dim3(n_inst), dim3(64), 0, st, (const unsigned long long *)ws, t.scalars);
+    MC_HIP_CHECK(hipGetLastError());
+    return MC_OK;
+}
+
+// Checks and schedule of a batched launch (items in decreasing estimated
+// cost, photons x (1 + tau), so the longest start first).
+int prepare_batch(const char *fn, const mc_batch_item_t *items, uint32_t n_items, int32_t n_cdf,
+                  const mc_source_t *source, const mc_geometry_t *geometry, const mc_detector_t *detector,
+                  const mc_run_t *run, const mc_tally_t *tally, double photon_scale, WalkArgs &a,
+                  std::vector<BatchInst> &sched, uint64_t &total)
+{
+    if (!items || !source || !geometry || !detector || !run || !tally) return fail(MC_EINVAL, "%s: null argument", fn);
+    if (n_items < 1 || n_items > MC_MAX_BATCH) return fail(MC_EINVAL, "%s: n_items must be in 1..%d", fn, MC_MAX_BATCH);
+    if (n_cdf < 2 || n_cdf > MC_MAX_N_CDF) return fail(MC_EINVAL, "%s: n_cdf %d outside 2..%d", fn, n_cdf, MC_MAX_N_CDF);
+    const mc_geometry_t &geo = *geometry;
+    const mc_detector_t &det = *detector;
+    const mc_run_t &rn = *run;
+    const mc_tally_t &t = *tally;
+    if (int rc = check_geometry(fn, geo)) return rc;
+    if (int rc = check_setup(fn, *source, geo, det, rn, t)) return rc;
+    if (det.flags & (MC_RECORD | MC_MOMENTS | MC_MOMENTS_PIXEL2))
+        return fail(MC_EUNSUPPORTED, "%s: MC_RECORD and MC_MOMENTS are not available for batched launches", fn);
+    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_FIX64))
+        return fail(MC_EINVAL, "%s: unknown detector flags 0x%x", fn, det.flags);
+    const uint64_t n_pix = (uint64_t)det.side_nx * det.side_ny + (uint64_t)det.trans_nx * det.trans_ny;
+    if (n_pix * n_items >= 0xFFFFFFFFull)
+        return fail(MC_EINVAL, "%s: images exceed 2^32 - 2 pixels over all items", fn);
+    if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < batch_workspace_words(det, n_items) * 8)
+        return fail(MC_EINVAL, "%s: workspace needs %llu bytes, 8-byte aligned", fn,
+                    (unsigned long long)(batch_workspace_words(det, n_items) * 8));
+    sched.clear();
+    total = 0;
+    std::vector<double> cost;
+    for (uint32_t i = 0; i < n_items; ++i) {
+        const mc_batch_item_t &it = items[i];
+        if (!(it.tau >= 0.0) || !std::isfinite(it.tau)) return fail(MC_EINVAL, "%s: item %u: tau must be >= 0", fn, i);
+        if (!(it.albedo >= 0.0 && it.albedo <= 1.0))
+            return fail(MC_EINVAL, "%s: item %u: albedo must be in [0, 1]", fn, i);
+        if (!it.inv_cdf) return fail(MC_EINVAL, "%s: item %u: inv_cdf is required", fn, i);
+        uint64_t n = it.n_photons;
+        if (photon_scale < 1.0 && n > 0) n = std::max<uint64_t>(1, (uint64_t)std::llround((double)n * photon_scale));
+        if (int rc = check_overflow(fn, n, det, rn)) return rc;
+        BatchInst b{};
+        fill_medium(b.neg_ln2_over_mu, b.albedo, b.absorb, it.tau, it.albedo, geo.size_mm[2]);
+        b.inv_cdf = it.inv_cdf;
+        b.n_photons = n;
+        b.counter = it.instance;
+        b.slot = i;
+        sched.push_back(b);
+        cost.push_back((double)n * (1.0 + it.tau));
+        total += n;
+    }
+    std::vector<uint32_t> order(n_items);
+    for (uint32_t i = 0; i < n_items; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return cost[x] > cost[y]; });
+    std::vector<BatchInst> sorted;
+    for (uint32_t i : order) sorted.push_back(sched[i]);
+    sched.swap(sorted);
+
+    a = WalkArgs{};
+    fill_common(a, *source, geo, det, rn);
+    a.phase = MC_PHASE_MIE;
+    a.n_cdf = n_cdf;
+    a.inv_cdf = nullptr;
+    a.instance = 0;
+    a.n_photons = 0;
+    a.photon_offset = 0;
+    a.record_stride = 1;
+    return MC_OK;
+}
+
+}  // namespace
+}  // namespace mcmie
+
+extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
+                           const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,
+                           void *stream)
+{
+    using namespace mcmie;
+    clear_error();
+    if (!medium || !source || !geometry || !detector || !run || !tally)
+        return fail(MC_EINVAL, "mc_simulate: null argument");
+    const mc_medium_t m = *medium;
+    const mc_geometry_t geo = *geometry;
+    const mc_detector_t det = *detector;
+    const mc_run_t rn = *run;
+    const mc_tally_t t = *tally;
+    const char *fn = "mc_simulate";
+
+    // ---- parameter checks (Sec. 3.1.1) ----
+    if (int rc = check_geometry(fn, geo)) return rc;
+    if (!(m.tau >= 0.0) || !std::isfinite(m.tau)) return fail(MC_EINVAL, "mc_simulate: tau must be >= 0");
+    if (!(m.albedo >= 0.0 && m.albedo <= 1.0)) return fail(MC_EINVAL, "mc_simulate: albedo must be in [0, 1]");
+    if (m.phase == MC_PHASE_MIE) {
+        if (m.n_cdf < 2 || m.n_cdf > MC_MAX_N_CDF)
+            return fail(MC_EINVAL, "mc_simulate: n_cdf %d outside 2..%d", m.n_cdf, MC_MAX_N_CDF);
+        if (!m.inv_cdf) return fail(MC_EINVAL, "mc_simulate: inv_cdf is required for MC_PHASE_MIE");
+    } else if (m.phase == MC_PHASE_HG) {
+        if (!(m.g > -1.0 && m.g < 1.0)) return fail(MC_EINVAL, "mc_simulate: HG g must be in (-1, 1)");
+    } else {
+        return fail(MC_EINVAL, "mc_simulate: unknown phase %d", m.phase);
+    }
+    if (int rc = check_setup(fn, *source, geo, det, rn, t)) return rc;
+    if ((det.flags & MC_RECORD) && (rn.record_stride < 1 || (t.rec_rows > 0 && (!t.rec_i || !t.rec_f))))
+        return fail(MC_EINVAL, "mc_simulate: MC_RECORD needs record_stride >= 1 and, for rec_rows > 0, "
+                               "rec_i and rec_f");
+    if (rn.photon_offset > UINT64_MAX - rn.n_photons) return fail(MC_EINVAL, "mc_simulate: photon ids overflow");
+    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64 | MC_MOMENTS | MC_MOMENTS_PIXEL2))
+        return fail(MC_EINVAL, "mc_simulate: unknown detector flags 0x%x", det.flags);
+    if ((det.flags & MC_MOMENTS) && (!t.side_wk || !t.side_wl))
+        return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS needs side_wk and side_wl");
+    if ((det.flags & MC_MOMENTS_PIXEL2) && (!(det.flags & MC_MOMENTS) || !t.side_w2k || !t.side_w2l))
+        return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS_PIXEL2 needs MC_MOMENTS, side_w2k and side_w2l");
+    if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < workspace_words(det) * 8)
+        return fail(MC_EINVAL, "mc_simulate: workspace needs %llu bytes, 8-byte aligned",
+                    (unsigned long long)(workspace_words(det) * 8));
+    if (int rc = check_overflow(fn, rn.n_photons, det, rn)) return rc;
+    const uint64_t n_pix = (uint64_t)det.side_nx * det.side_ny + (uint64_t)det.trans_nx * det.trans_ny;
+    if (n_pix >= 0xFFFFFFFFull) return fail(MC_EINVAL, "mc_simulate: images exceed 2^32 - 2 pixels in total");
+
+    WalkArgs a{};
+    fill_common(a, *source, geo, det, rn);
+    fill_medium(a.neg_ln2_over_mu, a.albedo, a.absorb, m.tau, m.albedo, geo.size_mm[2]);
     a.phase = m.phase;
     a.n_cdf = m.phase == MC_PHASE_MIE ? m.n_cdf : 0;
     a.inv_cdf = m.inv_cdf;
@@ -759,21 +1133,9 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     a.hg_b = (float)(2.0 * m.g);
     a.hg_c = (float)(1.0 - m.g * m.g);
     a.hg_d = (float)(1.0 - m.g);
-    a.key0 = (uint32_t)rn.seed;
-    a.key1 = (uint32_t)(rn.seed >> 32);
     a.instance = rn.instance;
-    a.max_steps = rn.max_steps;
     a.n_photons = rn.n_photons;
     a.photon_offset = rn.photon_offset;
-    a.flags = det.flags;
-    a.side_nx = det.side_nx; a.side_ny = det.side_ny;
-    a.trans_nx = det.trans_nx; a.trans_ny = det.trans_ny;
-    const uint64_t n_pix_all = (uint64_t)det.side_nx * det.side_ny + (uint64_t)det.trans_nx * det.trans_ny;
-    unsigned long long *ws = (unsigned long long *)t.workspace;
-    a.ws_scal = ws;
-    a.ws_img = ws + kWsScalarWords;
-    a.ws_img2 = (det.flags & MC_SIGMA) ? a.ws_img + (uint64_t)kCopies * n_pix_all : nullptr;
-    a.n_pix = n_pix_all;
     a.rec_i = t.rec_i; a.rec_f = t.rec_f;
     a.side_wk = (det.flags & MC_MOMENTS) ? t.side_wk : nullptr;
     a.side_wl = (det.flags & MC_MOMENTS) ? t.side_wl : nullptr;
@@ -781,77 +1143,97 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     a.side_w2l = (det.flags & MC_MOMENTS_PIXEL2) ? t.side_w2l : nullptr;
     a.rec_rows = (det.flags & MC_RECORD) ? t.rec_rows : 0;
     a.record_stride = rn.record_stride >= 1 ? rn.record_stride : 1;
-
-    // ---- launch shape: 1024-lane blocks, two per CU (32 waves), each with
-    // the table, the per-wave exit queues and as large a tally cache as fits
-    // in half the CU's 160 KB LDS ----
-    int cus = 0;
-    if (int rc = device_cu_count(&cus)) return rc;
-    const size_t n_pix = (size_t)det.side_nx * det.side_ny + (size_t)det.trans_nx * det.trans_ny;
-    if (n_pix >= 0xFFFFFFFFull) return fail(MC_EINVAL, "mc_simulate: images exceed 2^32 - 2 pixels in total");
-    a.n_side = (uint32_t)((size_t)det.side_nx * det.side_ny);
-    const int block = rn.block_size ? rn.block_size : 1024;
-    const size_t lds_fixed = (size_t)((a.n_cdf + 3) & ~3) * sizeof(float) + MC_N_SCALARS * sizeof(double) +
-                             (size_t)(block / 64) * 3 * kQueue * sizeof(float);
-    const size_t slot_bytes = sizeof(uint32_t) + sizeof(double) * ((det.flags & MC_SIGMA) ? 2 : 1);
-    const size_t lds_half_cu = 80 * 1024;
-    a.cache_bits = 0;
-    for (int b = 10; b >= 4; --b)
-        if (lds_fixed + (slot_bytes << b) <= lds_half_cu) { a.cache_bits = b; break; }
-    const size_t lds = lds_fixed + (a.cache_bits ? (slot_bytes << a.cache_bits) : 0);
-    const int blocks_per_cu = std::max(1, std::min((int)(160 * 1024 / lds), 32 / (block / 64)));
-    const int grid = rn.grid_blocks > 0 ? rn.grid_blocks : cus * blocks_per_cu;
-    const uint64_t waves_total = (uint64_t)grid * (block / 64);
-    uint64_t chunk = rn.n_photons / std::max<uint64_t>(1, waves_total * 16);
-    chunk = std::max<uint64_t>(64, std::min<uint64_t>(1024, (chunk + 63) / 64 * 64));
-    a.chunk = (uint32_t)chunk;
-
-    hipStream_t st = (hipStream_t)stream;
-    const size_t n_side = (size_t)det.side_nx * det.side_ny, n_trans = (size_t)det.trans_nx * det.trans_ny;
-    const int zero_all = (det.flags & MC_ACCUMULATE) ? 0 : 1;
-    const bool sig = (det.flags & MC_SIGMA) != 0, rec = (det.flags & MC_RECORD) != 0;
-    hipLaunchKernelGGL(init_kernel, dim3(1024), dim3(256), 0, st, ws, (size_t)workspace_words(det),
-                       (unsigned long long *)t.side, (unsigned long long *)t.trans,
-                       sig ? (unsigned long long *)t.side_w2 : nullptr, sig ? (unsigned long long *)t.trans_w2 : nullptr,
-                       n_side, n_trans, t.scalars, a.rec_i, a.rec_f, (size_t)a.rec_rows, a.side_wk, a.side_wl,
-                       a.side_w2k, a.side_w2l, zero_all);
-    MC_HIP_CHECK(hipGetLastError());
-    const int opt = (sig ? kOptSigma : 0) | (rec ? kOptRecord : 0) | ((det.flags & MC_MOMENTS) ? kOptMoments : 0);
-    using Kern = void (*)(WalkArgs);
-    static const Kern mie_kernels[8] = {walk_kernel<MC_PHASE_MIE, 0>, walk_kernel<MC_PHASE_MIE, 1>,
-                                        walk_kernel<MC_PHASE_MIE, 2>, walk_kernel<MC_PHASE_MIE, 3>,
-                                        walk_kernel<MC_PHASE_MIE, 4>, walk_kernel<MC_PHASE_MIE, 5>,
-                                        walk_kernel<MC_PHASE_MIE, 6>, walk_kernel<MC_PHASE_MIE, 7>};
-    static const Kern hg_kernels[8] = {walk_kernel<MC_PHASE_HG, 0>, walk_kernel<MC_PHASE_HG, 1>,
-                                       walk_kernel<MC_PHASE_HG, 2>, walk_kernel<MC_PHASE_HG, 3>,
-                                       walk_kernel<MC_PHASE_HG, 4>, walk_kernel<MC_PHASE_HG, 5>,
-                                       walk_kernel<MC_PHASE_HG, 6>, walk_kernel<MC_PHASE_HG, 7>};
-    const Kern kern = m.phase == MC_PHASE_MIE ? mie_kernels[opt] : hg_kernels[opt];
-    if (rn.n_photons > 0) {
-        MC_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, a);
-        MC_HIP_CHECK(hipGetLastError());
-    }
-    // ---- finalize: per-XCD copies to the caller's images, scalars to doubles ----
-    const bool fix64 = (det.flags & MC_FIX64) != 0;
-    const unsigned fin_grid = (unsigned)std::min<uint64_t>(512, (n_pix_all + 255) / 256);
-    auto fin = fix64 ? finalize_images<true> : finalize_images<false>;
-    hipLaunchKernelGGL(fin, dim3(fin_grid), dim3(256), 0, st, a.ws_img, n_pix_all, a.n_side, t.side, t.trans,
-                       ws + MC_S_FACE + 1, ws + MC_S_FACE + 5);
-    if (sig)
-        hipLaunchKernelGGL(fin, dim3(fin_grid), dim3(256), 0, st, a.ws_img2, n_pix_all, a.n_side, t.side_w2,
-                           t.trans_w2, (unsigned long long *)nullptr, (unsigned long long *)nullptr);
-    hipLaunchKernelGGL(finalize_scalars, dim3(1), dim3(64), 0, st, (const unsigned long long *)ws, t.scalars);
-    MC_HIP_CHECK(hipGetLastError());
-    return MC_OK;
+    return launch_walk(a, det, rn, t, m.phase, 1, rn.n_photons, nullptr, (hipStream_t)stream);
 }
 
 extern "C" uint64_t mc_workspace_bytes(const mc_detector_t *detector)
 {
-    if (!detector || detector->side_nx < 1 || detector->side_ny < 1 || detector->trans_nx < 1 ||
-        detector->trans_ny < 1)
-        return 0;
+    if (!detector || !mcmie::dims_ok(*detector)) return 0;
     return mcmie::workspace_words(*detector) * 8;
+}
+
+extern "C" uint64_t mc_workspace_bytes_batch(const mc_detector_t *detector, uint32_t n_items)
+{
+    if (!detector || !mcmie::dims_ok(*detector) || n_items < 1 || n_items > MC_MAX_BATCH) return 0;
+    return mcmie::batch_workspace_words(*detector, n_items) * 8;
+}
+
+extern "C" int mc_simulate_batch(const mc_batch_item_t *items, uint32_t n_items, int32_t n_cdf,
+                                 const mc_source_t *source, const mc_geometry_t *geometry,
+                                 const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,
+                                 void *stream)
+{
+    using namespace mcmie;
+    clear_error();
+    WalkArgs a{};
+    std::vector<BatchInst> sched;
+    uint64_t total = 0;
+    if (int rc = prepare_batch("mc_simulate_batch", items, n_items, n_cdf, source, geometry, detector, run, tally,
+                               1.0, a, sched, total))
+        return rc;
+    return launch_walk(a, *detector, *run, *tally, MC_PHASE_MIE, n_items, total, &sched, (hipStream_t)stream);
+}
+
+extern "C" int mc_autotune_batch(const mc_batch_item_t *items, uint32_t n_items, int32_t n_cdf,
+                                 const mc_source_t *source, const mc_geometry_t *geometry,
+                                 const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,
+                                 double sample_fraction, int32_t *block_size, uint32_t *chunk, double *best_ms,
+                                 double *candidate_ms, void *stream)
+{
+    using namespace mcmie;
+    clear_error();
+    if (!block_size || !chunk || !best_ms) return fail(MC_EINVAL, "mc_autotune_batch: null output");
+    if (!(sample_fraction > 0.0 && sample_fraction <= 1.0))
+        return fail(MC_EINVAL, "mc_autotune_batch: sample_fraction must be in (0, 1]");
+    WalkArgs a0{};
+    std::vector<BatchInst> sched;
+    uint64_t total = 0;
+    if (int rc = prepare_batch("mc_autotune_batch", items, n_items, n_cdf, source, geometry, detector, run, tally,
+                               sample_fraction, a0, sched, total))
+        return rc;
+    static const int32_t blocks[3] = {256, 512, 1024};
+    static const uint32_t chunks[5] = {256, 512, 1024, 2048, 4096};
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    MC_HIP_CHECK(hipEventCreate(&e0));
+    MC_HIP_CHECK(hipEventCreate(&e1));
+    double best = INFINITY;
+    int32_t bb = 0;
+    uint32_t bc = 0;
+    int rc = MC_OK;
+    for (int i = 0; i < 3 && rc == MC_OK; ++i) {
+        for (int j = 0; j < 5 && rc == MC_OK; ++j) {
+            mc_run_t rn = *run;
+            rn.block_size = blocks[i];
+            rn.chunk = chunks[j];
+            rn.grid_blocks = 0;
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && rc == MC_OK; ++rep) {
+                WalkArgs a = a0;
+                if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = fail(MC_EDEVICE, "hipEventRecord failed");
+                if (rc == MC_OK) rc = launch_walk(a, *detector, rn, *tally, MC_PHASE_MIE, n_items, total, &sched, st);
+                if (rc == MC_OK && rep == 1) {
+                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                        rc = fail(MC_EDEVICE, "mc_autotune_batch: event timing failed");
+                }
+            }
+            if (rc != MC_OK) break;
+            if (candidate_ms) candidate_ms[i * 5 + j] = ms;
+            if (ms < best) {
+                best = ms;
+                bb = blocks[i];
+                bc = chunks[j];
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != MC_OK) return rc;
+    *block_size = bb;
+    *chunk = bc;
+    *best_ms = best;
+    return MC_OK;
 }
 
 extern "C" int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry, const mc_detector_t *detector,

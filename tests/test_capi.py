@@ -29,7 +29,8 @@ def _declared_functions():
 def test_header_declares_the_entry_points():
     names = set(_declared_functions())
     assert {"mie_table_build", "mc_simulate", "mc_grad", "mc_last_error", "mc_philox_blocks",
-            "mc_version", "mc_workspace_bytes", "mie_table_enqueue"} <= names
+            "mc_version", "mc_workspace_bytes", "mie_table_enqueue", "mc_simulate_batch",
+            "mc_autotune_batch", "mc_workspace_bytes_batch"} <= names
 
 
 def test_library_exports_every_declared_symbol():
@@ -45,7 +46,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_empty_error():
     import paper_2507_23189_amd as mc
     _lib_path()
-    assert mc.mc_version() == 200
+    assert mc.mc_version() == 300
     assert mc.lib().mc_last_error() == b""
 
 
@@ -217,3 +218,66 @@ def test_mc_simulate_moments_need_buffers():
     tal.side_wk = tal.side_wl = 0x1000
     rc = sim(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run), C.byref(tal), None)
     assert rc == mc.MC_EINVAL and b"PIXEL2" in mc.lib().mc_last_error()
+
+def _batch_args(n=3):
+    import paper_2507_23189_amd as mc
+    import workloads as W
+    ws = W.batch_workloads(n, photon_scale=1e-3)
+    _, _, src, geo, det, run = mc.args_from_workload(ws[0])
+    items = (mc.BatchItem * n)()
+    for i, w in enumerate(ws):
+        items[i] = mc.BatchItem(tau=w.tau, albedo=w.albedo, inv_cdf=0x1000, n_photons=w.n_photons, instance=i)
+    return items, src, geo, det, run
+
+
+def test_batch_workspace_size():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    items, src, geo, det, run = _batch_args()
+    n_pix = det.side_nx * det.side_ny + det.trans_nx * det.trans_ny
+    sched_words = (5 * 48 + 7) // 8                    # one 48-byte schedule entry per medium
+    assert mc.mc_workspace_bytes_batch(det, 5) == 8 * (5 * 32 + 8 * 5 * n_pix + sched_words)
+    det.flags = mc.MC_SIGMA
+    assert mc.mc_workspace_bytes_batch(det, 5) == 8 * (5 * 32 + 16 * 5 * n_pix + sched_words)
+    assert mc.mc_workspace_bytes_batch(det, 0) == 0
+    assert mc.mc_workspace_bytes_batch(det, mc.MC_MAX_BATCH + 1) == 0
+
+
+def test_batch_rejects_invalid_arguments():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    L = mc.lib()
+    items, src, geo, det, run = _batch_args()
+    tal = mc._capi._TallyC()
+    tal.side = tal.trans = tal.scalars = tal.workspace = 0x1000
+    tal.workspace_bytes = mc.mc_workspace_bytes_batch(det, 3)
+
+    def call(n=3, n_cdf=4096):
+        return L.mc_simulate_batch(items, n, n_cdf, C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                                   C.byref(tal), None)
+    assert call(n=0) == mc.MC_EINVAL and b"n_items" in L.mc_last_error()
+    assert call(n_cdf=1) == mc.MC_EINVAL
+    items[1].albedo = 1.5
+    assert call() == mc.MC_EINVAL and b"item 1" in L.mc_last_error()
+    items[1].albedo = 0.99
+    items[2].inv_cdf = None
+    assert call() == mc.MC_EINVAL and b"item 2" in L.mc_last_error()
+    items[2].inv_cdf = 0x1000
+    det.flags = mc.MC_RECORD
+    assert call() == mc.MC_EUNSUPPORTED
+    det.flags = mc.MC_MOMENTS
+    assert call() == mc.MC_EUNSUPPORTED
+    det.flags = 0
+    run.chunk = 70000
+    assert call() == mc.MC_EINVAL and b"chunk" in L.mc_last_error()
+    run.chunk = 0
+    tal.workspace_bytes -= 8
+    assert call() == mc.MC_EINVAL and b"workspace" in L.mc_last_error()
+    tal.workspace_bytes += 8
+    blk, chk, best = C.c_int32(), C.c_uint32(), C.c_double()
+    rc = L.mc_autotune_batch(items, 3, 4096, C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                             C.byref(tal), 0.0, C.byref(blk), C.byref(chk), C.byref(best), None, None)
+    assert rc == mc.MC_EINVAL and b"sample_fraction" in L.mc_last_error()
+    rc = L.mc_autotune_batch(items, 3, 4096, C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                             C.byref(tal), 0.5, None, C.byref(chk), C.byref(best), None, None)
+    assert rc == mc.MC_EINVAL

@@ -104,6 +104,23 @@ def batch_instances(n: int = 256, seed: int = 2507) -> List[BatchInstance]:
             for a, b, c, e in zip(d, tau, alb, nph)]
 
 
+# Batched media share the cuvette, beam and detector of the parity workload
+# (4096-entry tables, 128 x 128 images); instance i draws Philox counter word
+# 1 = i.
+BATCH_BASE = Workload(name="batch", tau=1.0, n_cdf=4096, side_px=128, trans_px=128, n_photons=0)
+
+
+def batch_workloads(n: int = 256, seed: int = 2507, photon_scale: float = 1.0) -> List[Workload]:
+    """One Workload per batched medium (batch_instances), photon counts scaled
+    by photon_scale (at least one photon each)."""
+    out = []
+    for i, b in enumerate(batch_instances(n, seed)):
+        part = dataclasses.replace(BATCH_BASE.particle, diameter_um=b.diameter_um)
+        out.append(BATCH_BASE.replace(name=f"batch{n}_{i}", particle=part, tau=b.tau, albedo=b.albedo,
+                                      n_photons=max(1, int(round(b.n_photons * photon_scale))), instance=i))
+    return out
+
+
 def sample_ids(n_total: int, n_sample: int, seed: int = 7) -> np.ndarray:
     """Sorted distinct photon ids spread over [0, n_total) for sampled parity
     at full size (numpy PCG64)."""
