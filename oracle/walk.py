@@ -20,6 +20,7 @@ import numpy as np
 
 from . import build as _build
 from . import mie as _mie
+from . import poly as _poly
 
 N_SCALARS = 16
 S = dict(face=slice(0, 6), absorbed=6, roulette_net=7, capped_w=8, events=9, photons=10,
@@ -93,8 +94,10 @@ class Walk:
                  table_v: Optional[np.ndarray] = None):
         w = workload
         self.w = w
-        self.table = table if table is not None else (
-            _mie.table_from_workload(w) if table_v is None and (w.phase == 0 or g is None) else None)
+        if table is None and table_v is None and (w.phase == 0 or g is None):
+            table = (_poly.poly_table_from_workload(w) if getattr(w.particle, "n_bins", 1) > 1
+                     else _mie.table_from_workload(w))
+        self.table = table
         v = table_v if table_v is not None else (self.table.v if self.table is not None else np.zeros(2))
         self._v = np.ascontiguousarray(v, dtype=np.float64)
         p = _Params()

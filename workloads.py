@@ -30,6 +30,8 @@ class Particle:
     m_im: float = 0.0            # particle index, imaginary part (>= 0 absorbs)
     n_medium: float = 1.33       # water
     wavelength_nm: float = 532.0
+    sigma_ln: float = 0.0        # lognormal width of ln d (diameter_um is then the median)
+    n_bins: int = 1              # Gauss-Hermite bins in ln d (1: a single size)
 
 
 @dataclass(frozen=True)
@@ -82,6 +84,13 @@ HEADLINE = paper_scale(4.0)
 # at tau = 4.5 with seed 99.
 DIFF = paper_scale(4.0, n_photons=10_000_000).replace(name="diff_tau4_1e7")
 DIFF_TARGET = DIFF.replace(name="diff_target_tau4.5", tau=4.5, seed=99)
+
+
+# Polydisperse heavy scattering: lognormal sizes (median 5 um, sigma_ln 0.05,
+# 64 Gauss-Hermite bins), tau = 16, 1e9 photons, 1024 x 1024 images in int64
+# fixed point; the oracle checks it on its first 1e6 photons.
+HEAVY = Workload(name="heavy_poly_tau16_1e9", particle=Particle(sigma_ln=0.05, n_bins=64), tau=16.0,
+                 n_cdf=16384, side_px=1024, trans_px=1024, n_photons=1_000_000_000)
 
 
 @dataclass(frozen=True)
