@@ -26,7 +26,12 @@ The JSON line also carries
                 5.75e8 photons): launch shape from mc_autotune_batch on a
                 1/16 photon sample, then scatter events/s of the batched
                 launch against the best rate any of its media reaches when
-                run alone with mc_simulate (--no-batch skips it).
+                run alone with mc_simulate (--no-batch skips it);
+  heavy         polydisperse heavy scattering: lognormal sizes (median 5 um,
+                sigma_ln 0.05, 64 bins), tau = 16, 1e9 photons, 1024 x 1024
+                int64 fixed-point images; table build time, forward scatter
+                events/s, and forward + adjoint against forward time
+                (--no-heavy skips it).
 
     python bench.py [--steps K] [--warmup W]
 """
@@ -213,6 +218,52 @@ def batch_timing(mc, W, dev, args):
                          "candidates_ms": {f"{b}x{c}": v for (b, c), v in table.items()}}}
 
 
+def heavy_timing(mc, W, dev, args):
+    """The polydisperse tau = 16 workload: table, forward, forward + adjoint."""
+    import torch
+    w = W.HEAVY
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    table = mc.table_for_workload(w, dev)
+    table_ms = (time.perf_counter() - t0) * 1e3
+    _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=mc.MC_FIX64)
+    _, med_a, _, _, det_a, _ = mc.args_from_workload(w, table, flags=mc.MC_FIX64 | mc.MC_MOMENTS)
+    t_f = mc.Tally.alloc(det, dev, fix64=True)
+    t_a = mc.Tally.alloc(det_a, dev, fix64=True, moments=True)
+    dloss = torch.ones((w.side_px, w.side_px), dtype=torch.float64, device=dev)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    def clock(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            out.append((time.perf_counter() - t) * 1e3)
+        return min(out)
+
+    def fwd():
+        ev[0].record()
+        mc.mc_simulate(med, src, geo, det, run, t_f)
+        ev[1].record()
+
+    def adj():
+        mc.mc_simulate(med_a, src, geo, det_a, run, t_a)
+        mc.mc_grad(med_a, geo, det_a, t_a, dloss, d2loss_uniform=2.0)
+
+    fwd_ms = clock(fwd)
+    kernel_ms = ev[0].elapsed_time(ev[1])
+    adj_ms = clock(adj)
+    s = t_f.scalars.cpu().numpy()
+    return {"workload": w.name, "photons": w.n_photons, "tau": w.tau, "bins": w.particle.n_bins,
+            "images": [w.side_px, w.trans_px], "events": float(s[9]),
+            "events_per_photon": float(s[9] / s[10]), "table_ms": table_ms, "fwd_ms": fwd_ms,
+            "mc_simulate_ms": kernel_ms, "events_per_s": float(s[9]) / (kernel_ms * 1e-3),
+            "fwd_adjoint_ms": adj_ms, "adjoint_ratio": adj_ms / fwd_ms}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +277,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-heavy", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -289,6 +341,8 @@ def main():
     log("bench: adjoint timing done")
     batch = None if args.no_batch else batch_timing(mc, W, dev, args)
     log("bench: batch timing done")
+    heavy = None if args.no_heavy else heavy_timing(mc, W, dev, args)
+    log("bench: heavy timing done")
 
     scal = [t.scalars.cpu().numpy() for t in tallies[args.warmup:]]
     events = float(sum(s[9] for s in scal))
@@ -329,6 +383,7 @@ def main():
         "adjoint_ratio": adjoint["ratio"],
         "adjoint": adjoint,
         "batch": batch,
+        "heavy": heavy,
     }
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")

@@ -94,6 +94,7 @@ extern "C" {
 #define MC_MAX_N_CDF 16384    /* largest inverse table (64 KB, held in LDS) */
 #define MC_MAX_N_ANGLES 3001  /* largest phase-function grid */
 #define MC_MAX_TERMS 1024     /* largest Mie series length (x up to ~980) */
+#define MC_MAX_BINS 64        /* most size bins of a polydisperse table */
 
 /* ------------------------------------------------------------------ Mie */
 
@@ -147,6 +148,37 @@ int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void *stream);
  * table->result).  For pipelines that need the table only on the device.
  */
 int mie_table_enqueue(const mie_spec_t *spec, mie_table_t *table, void *stream);
+
+/*
+ * Polydisperse table.  Diameters follow a lognormal number distribution whose
+ * median is spec->diameter_um: ln d ~ Normal(ln d_med, sigma_ln^2),
+ * discretised by n_bins-point Gauss-Hermite quadrature in ln d (bins
+ * d_k = d_med exp(sqrt(2) sigma_ln t_k), probabilities p_k = W_k / sqrt(pi);
+ * mc_lognormal_bins returns them).  Each bin runs the single-size series and
+ * phase function of mie_table_build (one workgroup per bin); the table is
+ * built from the scattering-weighted mixture
+ *     P(theta) = sum_k p_k C_sca,k P_k(theta) / sum_k p_k C_sca,k
+ * (each P_k normalised as Eq. 10, so P is too), with the number-averaged
+ * cross-sections sigma = sum_k p_k Q_k pi d_k^2 / 4 (Eq. 14 per bin) and the
+ * same mixture of the per-bin asymmetries (Eq. 12).  The table's q_* are
+ * those cross-sections over the median's pi d_med^2 / 4, x is the median's
+ * size parameter and n_terms the longest bin series; coef must be NULL.
+ * Waits for the stream (like mie_table_build).
+ */
+typedef struct {
+    double sigma_ln;       /* width of ln d, >= 0 (0 with any n_bins gives the single size) */
+    int32_t n_bins;        /* Gauss-Hermite bins, 1..MC_MAX_BINS */
+    int32_t reserved;      /* set to 0 */
+    double *work;          /* DEVICE scratch of at least mie_poly_work_bytes(spec, poly) bytes */
+    uint64_t work_bytes;
+} mie_poly_t;
+
+uint64_t mie_poly_work_bytes(const mie_spec_t *spec, const mie_poly_t *poly);
+int mie_table_build_poly(const mie_spec_t *spec, const mie_poly_t *poly, mie_table_t *table, void *stream);
+
+/* Host: the bins of the lognormal discretisation above (diameters in um,
+ * probabilities summing to 1), n_bins entries each. */
+int mc_lognormal_bins(double median_um, double sigma_ln, int32_t n_bins, double *diameters_um, double *probs);
 
 /* -------------------------------------------------------------- the walk */
 

@@ -13,9 +13,10 @@ from ._capi import (MC_ACCUMULATE, MC_EDEVICE, MC_EINVAL, MC_ENOMEM, MC_EUNSUPPO
                     MC_SIGMA, Detector, Geometry, McError, Medium, MieSpec, MieTable, Run, Source, Tally, lib,
                     mc_grad, mc_philox_blocks, mc_simulate, mc_version, mc_workspace_bytes, mie_table_build,
                     BatchItem, MC_MAX_BATCH, AUTOTUNE_BLOCKS, AUTOTUNE_CHUNKS, mc_simulate_batch,
-                    mc_autotune_batch, mc_workspace_bytes_batch,
+                    mc_autotune_batch, mc_workspace_bytes_batch, MiePoly, MC_MAX_BINS, mie_table_build_poly,
+                    mc_lognormal_bins,
                     mie_table_enqueue)
-from .args import args_from_workload, batch_item
+from .args import args_from_workload, batch_item, table_for_workload
 from .autograd import SideImage, side_image, side_l2_loss
 
 __all__ = [n for n in dir() if not n.startswith("_")]

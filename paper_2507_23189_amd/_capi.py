@@ -21,6 +21,7 @@ MC_S_SIDE_W2, MC_S_SIDE_W2K, MC_S_SIDE_W2L = 16, 17, 18
 MC_REC_I_N, MC_REC_F_N = 4, 9
 MC_MAX_N_CDF, MC_MAX_N_ANGLES, MC_MAX_TERMS = 16384, 3001, 1024
 MC_MAX_BATCH = 512
+MC_MAX_BINS = 64
 # Candidates mc_autotune_batch times, in its block-major order.
 AUTOTUNE_BLOCKS, AUTOTUNE_CHUNKS = (256, 512, 1024), (256, 512, 1024, 2048, 4096)
 
@@ -38,6 +39,12 @@ class _MieTableC(C.Structure):
                 ("n_terms", C.c_int32), ("n_cdf", C.c_int32),
                 ("inv_cdf", C.c_void_p), ("phase", C.c_void_p), ("cdf", C.c_void_p), ("coef", C.c_void_p),
                 ("coef_capacity", C.c_int32), ("result", C.c_void_p)]
+
+
+class MiePoly(C.Structure):
+    """Lognormal size distribution of mie_table_build_poly (mie_poly_t)."""
+    _fields_ = [("sigma_ln", C.c_double), ("n_bins", C.c_int32), ("reserved", C.c_int32),
+                ("work", C.c_void_p), ("work_bytes", C.c_uint64)]
 
 
 class Medium(C.Structure):
@@ -106,6 +113,12 @@ def lib():
                               C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]
         L.mc_philox_blocks.argtypes = [C.c_uint64, C.c_uint32, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
                                        C.c_void_p, C.c_void_p]
+        L.mie_table_build_poly.argtypes = [C.POINTER(MieSpec), C.POINTER(MiePoly), C.POINTER(_MieTableC),
+                                           C.c_void_p]
+        L.mie_poly_work_bytes.argtypes = [C.POINTER(MieSpec), C.POINTER(MiePoly)]
+        L.mie_poly_work_bytes.restype = C.c_uint64
+        L.mc_lognormal_bins.argtypes = [C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
         L.mc_workspace_bytes.argtypes = [C.POINTER(Detector)]
         L.mc_workspace_bytes.restype = C.c_uint64
         L.mc_workspace_bytes_batch.argtypes = [C.POINTER(Detector), C.c_uint32]
@@ -118,7 +131,7 @@ def lib():
         L.mc_last_error.restype = C.c_char_p
         L.mc_version.restype = C.c_int
         for f in ("mie_table_build", "mie_table_enqueue", "mc_simulate", "mc_grad", "mc_philox_blocks",
-                  "mc_simulate_batch", "mc_autotune_batch"):
+                  "mc_simulate_batch", "mc_autotune_batch", "mie_table_build_poly", "mc_lognormal_bins"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -176,6 +189,36 @@ def mie_table_build(spec: MieSpec, device="cuda", *, phase=False, cdf=False, coe
     return MieTable(t.x, complex(t.m_rel_re, t.m_rel_im), t.q_ext, t.q_sca, t.q_abs, t.g, t.sigma_ext_mm2,
                     t.sigma_sca_mm2, t.sigma_abs_mm2, t.n_terms, inv, ph, cd,
                     co[: t.n_terms] if co is not None else None)
+
+
+def mie_table_build_poly(spec: MieSpec, sigma_ln: float, n_bins: int, device="cuda", *, phase=False, cdf=False,
+                         stream=None) -> MieTable:
+    """Polydisperse table: lognormal diameters with median spec.diameter_um
+    and width sigma_ln of ln d on n_bins Gauss-Hermite bins (blocks until the
+    scalars are back)."""
+    import torch
+    dev = torch.device(device)
+    inv = torch.empty(max(int(spec.n_cdf), 1), dtype=torch.float32, device=dev)
+    ph = torch.empty(max(int(spec.n_angles), 1), dtype=torch.float64, device=dev) if phase else None
+    cd = torch.empty(max(int(spec.n_angles), 1), dtype=torch.float64, device=dev) if cdf else None
+    q = MiePoly(sigma_ln=float(sigma_ln), n_bins=int(n_bins))
+    nbytes = int(lib().mie_poly_work_bytes(C.byref(spec), C.byref(q)))
+    work = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=dev)
+    q.work, q.work_bytes = _ptr(work), nbytes
+    t = _MieTableC()
+    t.inv_cdf, t.phase, t.cdf = _ptr(inv), _ptr(ph), _ptr(cd)
+    with torch.cuda.device(dev):
+        _check(lib().mie_table_build_poly(C.byref(spec), C.byref(q), C.byref(t), _stream(stream)))
+    return MieTable(t.x, complex(t.m_rel_re, t.m_rel_im), t.q_ext, t.q_sca, t.q_abs, t.g, t.sigma_ext_mm2,
+                    t.sigma_sca_mm2, t.sigma_abs_mm2, t.n_terms, inv, ph, cd)
+
+
+def mc_lognormal_bins(median_um: float, sigma_ln: float, n_bins: int):
+    """(diameters_um, probabilities) of the library's Gauss-Hermite bins (host)."""
+    d = (C.c_double * max(int(n_bins), 1))()
+    p = (C.c_double * max(int(n_bins), 1))()
+    _check(lib().mc_lognormal_bins(float(median_um), float(sigma_ln), int(n_bins), d, p))
+    return list(d)[: int(n_bins)], list(p)[: int(n_bins)]
 
 
 def mie_table_enqueue(spec: MieSpec, device="cuda", *, inv_cdf=None, result=None, stream=None) -> MieTable:

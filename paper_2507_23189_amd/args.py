@@ -39,3 +39,13 @@ def batch_item(w, table) -> BatchItem:
     """BatchItem for workload `w` with its Mie table (from mie_table_build)."""
     return BatchItem(tau=w.tau, albedo=w.albedo, inv_cdf=table.inv_cdf.data_ptr(), n_photons=w.n_photons,
                      instance=w.instance)
+
+
+def table_for_workload(w, device="cuda"):
+    """The Mie table a workload asks for: single size, or the lognormal
+    mixture when its particle has more than one size bin."""
+    from ._capi import mie_table_build, mie_table_build_poly
+    spec = args_from_workload(w)[0]
+    if getattr(w.particle, "n_bins", 1) > 1:
+        return mie_table_build_poly(spec, w.particle.sigma_ln, w.particle.n_bins, device)
+    return mie_table_build(spec, device)

@@ -58,115 +58,96 @@ struct MieArgs {
     double *result;          // q_ext, q_sca, g, n_terms
 };
 
-__global__ __launch_bounds__(kBlock) void mie_table_kernel(MieArgs a)
+// Step 1 on one lane: the series for size parameter x and relative index m.
+// Leaves a_n, b_n in s_a, s_b (n = 1..N at index n - 1) and returns Q_ext,
+// Q_sca and g.
+__device__ void mie_series(double x, double m_re, double m_im, int N, int n_start, cplx *s_a, cplx *s_b,
+                           double *q_ext_out, double *q_sca_out, double *g_out)
 {
-    __shared__ cplx s_a[MC_MAX_TERMS];
-    __shared__ cplx s_b[MC_MAX_TERMS];
-    __shared__ double s_ang[MC_MAX_N_ANGLES];
-    __shared__ double s_part[kBlock];
-    __shared__ double s_qsca;
+    const cplx m = {m_re, m_im};
+    const cplx mx = x * m;
+    const cplx inv_mx = cplx{1.0, 0.0} / mx;
+    cplx D = {0.0, 0.0};
+    for (int n = n_start; n >= 1; --n) {
+        // D_{n-1} = n/(mx) - 1 / (D_n + n/(mx)); keep D_n for n <= N.
+        if (n <= N) s_a[n - 1] = D;
+        const cplx nmx = (double)n * inv_mx;
+        D = nmx - cplx{1.0, 0.0} / (D + nmx);
+    }
+    double psi_prev = cos(x), psi = sin(x);        // psi_{-1}, psi_0
+    double chi_prev = -sin(x), chi = cos(x);       // chi_{-1}, chi_0
+    double sum_ext = 0.0, sum_sca = 0.0, sum_g1 = 0.0, sum_g2 = 0.0;
+    cplx an_prev = {0.0, 0.0}, bn_prev = {0.0, 0.0};
+    const cplx inv_m = cplx{1.0, 0.0} / m;
+    for (int n = 1; n <= N; ++n) {
+        const double f = (2.0 * n - 1.0) / x;
+        const double psi_n = f * psi - psi_prev;
+        const double chi_n = f * chi - chi_prev;
+        const cplx xi_n = {psi_n, -chi_n};
+        const cplx xi_nm1 = {psi, -chi};
+        const cplx Dn = s_a[n - 1];
+        const double nx = (double)n / x;
+        const cplx da = Dn * inv_m + nx;
+        const cplx db = m * Dn + nx;
+        const cplx an = (psi_n * da - cplx{psi, 0.0}) / (da * xi_n - xi_nm1);
+        const cplx bn = (psi_n * db - cplx{psi, 0.0}) / (db * xi_n - xi_nm1);
+        s_a[n - 1] = an;
+        s_b[n - 1] = bn;
+        const double w = 2.0 * n + 1.0;
+        sum_ext += w * (an.re + bn.re);
+        sum_sca += w * (norm2(an) + norm2(bn));
+        // asymmetry: (n-1)(n+1)/n Re(a_{n-1} a_n* + b_{n-1} b_n*) + (2n+1)/(n(n+1)) Re(a_n b_n*)
+        if (n > 1) {
+            const double c = (double)(n - 1) * (n + 1) / n;
+            sum_g1 += c * (an_prev.re * an.re + an_prev.im * an.im + bn_prev.re * bn.re + bn_prev.im * bn.im);
+        }
+        sum_g2 += w / ((double)n * (n + 1)) * (an.re * bn.re + an.im * bn.im);
+        an_prev = an;
+        bn_prev = bn;
+        psi_prev = psi;
+        psi = psi_n;
+        chi_prev = chi;
+        chi = chi_n;
+    }
+    const double inv_x2 = 1.0 / (x * x);
+    const double q_ext = 2.0 * inv_x2 * sum_ext;
+    const double q_sca = 2.0 * inv_x2 * sum_sca;
+    *q_ext_out = q_ext;
+    *q_sca_out = q_sca;
+    *g_out = 4.0 * inv_x2 * (sum_g1 + sum_g2) / q_sca;
+}
 
+// Step 2 at one angle: |S1|^2 + |S2|^2 (Eqs. 5-6) with pi_n, tau_n upward.
+__device__ double mie_intensity(double th, int N, const cplx *s_a, const cplx *s_b)
+{
+    const double mu = cos(th);
+    double pi_prev = 0.0, pi_n = 1.0;              // pi_0, pi_1
+    cplx S1 = {0.0, 0.0}, S2 = {0.0, 0.0};
+    for (int n = 1; n <= N; ++n) {
+        if (n > 1) {
+            const double p = ((2.0 * n - 1.0) * mu * pi_n - (double)n * pi_prev) / (double)(n - 1);
+            pi_prev = pi_n;
+            pi_n = p;
+        }
+        const double tau_n = (double)n * mu * pi_n - (double)(n + 1) * pi_prev;
+        const double c = (2.0 * n + 1.0) / ((double)n * (n + 1));
+        const cplx an = s_a[n - 1], bn = s_b[n - 1];
+        S1 = S1 + c * (pi_n * an + tau_n * bn);
+        S2 = S2 + c * (tau_n * an + pi_n * bn);
+    }
+    return norm2(S1) + norm2(S2);
+}
+
+// Steps 3-4 by the whole workgroup: s_ang holds P sin(theta) on the na-point
+// grid on entry.  Trapezoid CDF by a chunked in-place scan, written back to
+// s_ang (and to cdf_out if given); then each inverse-table entry
+// u_i = i / (nc - 1) finds the first angle with F >= u_i by binary search and
+// interpolates theta linearly, storing v = 1 - cos(theta) = 2 sin^2(theta/2).
+__device__ void cdf_and_inverse(double *s_ang, double *s_part, double *s_total, int na, int nc, float *inv_cdf,
+                                double *cdf_out)
+{
     const int tid = threadIdx.x;
-    const int N = a.n_terms;
-    const double x = a.x;
-
-    // ---- 1. series (one lane) ----------------------------------------
-    if (tid == 0) {
-        const cplx m = {a.m_re, a.m_im};
-        const cplx mx = x * m;
-        const cplx inv_mx = cplx{1.0, 0.0} / mx;
-        cplx D = {0.0, 0.0};
-        for (int n = a.n_start; n >= 1; --n) {
-            // D_{n-1} = n/(mx) - 1 / (D_n + n/(mx)); keep D_n for n <= N.
-            if (n <= N) s_a[n - 1] = D;
-            const cplx nmx = (double)n * inv_mx;
-            D = nmx - cplx{1.0, 0.0} / (D + nmx);
-        }
-        double psi_prev = cos(x), psi = sin(x);        // psi_{-1}, psi_0
-        double chi_prev = -sin(x), chi = cos(x);       // chi_{-1}, chi_0
-        double sum_ext = 0.0, sum_sca = 0.0, sum_g1 = 0.0, sum_g2 = 0.0;
-        cplx an_prev = {0.0, 0.0}, bn_prev = {0.0, 0.0};
-        const cplx inv_m = cplx{1.0, 0.0} / m;
-        for (int n = 1; n <= N; ++n) {
-            const double f = (2.0 * n - 1.0) / x;
-            const double psi_n = f * psi - psi_prev;
-            const double chi_n = f * chi - chi_prev;
-            const cplx xi_n = {psi_n, -chi_n};
-            const cplx xi_nm1 = {psi, -chi};
-            const cplx Dn = s_a[n - 1];
-            const double nx = (double)n / x;
-            const cplx da = Dn * inv_m + nx;
-            const cplx db = m * Dn + nx;
-            const cplx an = (psi_n * da - cplx{psi, 0.0}) / (da * xi_n - xi_nm1);
-            const cplx bn = (psi_n * db - cplx{psi, 0.0}) / (db * xi_n - xi_nm1);
-            s_a[n - 1] = an;
-            s_b[n - 1] = bn;
-            const double w = 2.0 * n + 1.0;
-            sum_ext += w * (an.re + bn.re);
-            sum_sca += w * (norm2(an) + norm2(bn));
-            // asymmetry: (n-1)(n+1)/n Re(a_{n-1} a_n* + b_{n-1} b_n*) + (2n+1)/(n(n+1)) Re(a_n b_n*)
-            if (n > 1) {
-                const double c = (double)(n - 1) * (n + 1) / n;
-                sum_g1 += c * (an_prev.re * an.re + an_prev.im * an.im + bn_prev.re * bn.re +
-                               bn_prev.im * bn.im);
-            }
-            sum_g2 += w / ((double)n * (n + 1)) * (an.re * bn.re + an.im * bn.im);
-            an_prev = an;
-            bn_prev = bn;
-            psi_prev = psi;
-            psi = psi_n;
-            chi_prev = chi;
-            chi = chi_n;
-        }
-        const double inv_x2 = 1.0 / (x * x);
-        const double q_ext = 2.0 * inv_x2 * sum_ext;
-        const double q_sca = 2.0 * inv_x2 * sum_sca;
-        const double g = 4.0 * inv_x2 * (sum_g1 + sum_g2) / q_sca;
-        s_qsca = q_sca;
-        a.result[0] = q_ext;
-        a.result[1] = q_sca;
-        a.result[2] = g;
-        a.result[3] = (double)N;
-    }
-    __syncthreads();
-
-    if (a.coef) {
-        for (int n = tid; n < N; n += kBlock) {
-            a.coef[4 * n + 0] = s_a[n].re;
-            a.coef[4 * n + 1] = s_a[n].im;
-            a.coef[4 * n + 2] = s_b[n].re;
-            a.coef[4 * n + 3] = s_b[n].im;
-        }
-    }
-
-    // ---- 2. phase function on the angle grid --------------------------
-    const int na = a.n_angles;
     const double dth = M_PI / (double)(na - 1);
-    const double pnorm = 2.0 / (x * x * s_qsca);
-    for (int j = tid; j < na; j += kBlock) {
-        const double th = (double)j * dth;
-        const double mu = cos(th);
-        double pi_prev = 0.0, pi_n = 1.0;              // pi_0, pi_1
-        cplx S1 = {0.0, 0.0}, S2 = {0.0, 0.0};
-        for (int n = 1; n <= N; ++n) {
-            if (n > 1) {
-                const double p = ((2.0 * n - 1.0) * mu * pi_n - (double)n * pi_prev) / (double)(n - 1);
-                pi_prev = pi_n;
-                pi_n = p;
-            }
-            const double tau_n = (double)n * mu * pi_n - (double)(n + 1) * pi_prev;
-            const double c = (2.0 * n + 1.0) / ((double)n * (n + 1));
-            const cplx an = s_a[n - 1], bn = s_b[n - 1];
-            S1 = S1 + c * (pi_n * an + tau_n * bn);
-            S2 = S2 + c * (tau_n * an + pi_n * bn);
-        }
-        const double P = pnorm * (norm2(S1) + norm2(S2));
-        if (a.phase) a.phase[j] = P;
-        s_ang[j] = P * sin(th);
-    }
-    __syncthreads();
-
-    // ---- 3. trapezoid CDF, chunked in-place scan -----------------------
     const int lo = tid * kChunk;
     const int hi = min(lo + kChunk, na);
     double f_left = (lo >= 1 && lo < na) ? s_ang[lo - 1] : 0.0;
@@ -184,12 +165,12 @@ __global__ __launch_bounds__(kBlock) void mie_table_kernel(MieArgs a)
             s_part[t] = run;
             run += v;
         }
-        s_qsca = run;      // reuse: total integral
+        *s_total = run;
     }
     __syncthreads();
     {
         double acc = s_part[tid];
-        const double total = s_qsca;
+        const double total = *s_total;
         double prev = f_left;
         for (int j = lo; j < hi; ++j) {
             const double f = s_ang[j];
@@ -202,11 +183,8 @@ __global__ __launch_bounds__(kBlock) void mie_table_kernel(MieArgs a)
         }
     }
     __syncthreads();
-    if (a.cdf)
-        for (int j = tid; j < na; j += kBlock) a.cdf[j] = s_ang[j];
-
-    // ---- 4. inverse table ----------------------------------------------
-    const int nc = a.n_cdf;
+    if (cdf_out)
+        for (int j = tid; j < na; j += kBlock) cdf_out[j] = s_ang[j];
     for (int i = tid; i < nc; i += kBlock) {
         const double u = (double)i / (double)(nc - 1);
         int l = 0, r = na;                 // first j with F_j >= u
@@ -223,8 +201,134 @@ __global__ __launch_bounds__(kBlock) void mie_table_kernel(MieArgs a)
             th = th_p + (u - s_ang[j - 1]) / (s_ang[j] - s_ang[j - 1]) * (th_j - th_p);
         }
         const double sh = sin(0.5 * th);
-        a.inv_cdf[i] = (float)(2.0 * sh * sh);
+        inv_cdf[i] = (float)(2.0 * sh * sh);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void mie_table_kernel(MieArgs a)
+{
+    __shared__ cplx s_a[MC_MAX_TERMS];
+    __shared__ cplx s_b[MC_MAX_TERMS];
+    __shared__ double s_ang[MC_MAX_N_ANGLES];
+    __shared__ double s_part[kBlock];
+    __shared__ double s_qsca;
+
+    const int tid = threadIdx.x;
+    const int N = a.n_terms;
+    const double x = a.x;
+
+    // ---- 1. series (one lane) ----------------------------------------
+    if (tid == 0) {
+        double q_ext, q_sca, g;
+        mie_series(x, a.m_re, a.m_im, N, a.n_start, s_a, s_b, &q_ext, &q_sca, &g);
+        s_qsca = q_sca;
+        a.result[0] = q_ext;
+        a.result[1] = q_sca;
+        a.result[2] = g;
+        a.result[3] = (double)N;
+    }
+    __syncthreads();
+
+    if (a.coef) {
+        for (int n = tid; n < N; n += kBlock) {
+            a.coef[4 * n + 0] = s_a[n].re;
+            a.coef[4 * n + 1] = s_a[n].im;
+            a.coef[4 * n + 2] = s_b[n].re;
+            a.coef[4 * n + 3] = s_b[n].im;
+        }
+    }
+
+    // ---- 2. phase function on the angle grid, normalised (Eq. 10) -----
+    const int na = a.n_angles;
+    const double dth = M_PI / (double)(na - 1);
+    const double pnorm = 2.0 / (x * x * s_qsca);
+    for (int j = tid; j < na; j += kBlock) {
+        const double th = (double)j * dth;
+        const double P = pnorm * mie_intensity(th, N, s_a, s_b);
+        if (a.phase) a.phase[j] = P;
+        s_ang[j] = P * sin(th);
+    }
+    __syncthreads();
+
+    // ---- 3-4. CDF and inverse table ----------------------------------------
+    cdf_and_inverse(s_ang, s_part, &s_qsca, na, a.n_cdf, a.inv_cdf, a.cdf);
+}
+
+// ---- polydisperse: one workgroup per size bin, then the mixture ----------
+
+struct PolyArgs {
+    double x[MC_MAX_BINS];         // size parameter of each bin
+    double c[MC_MAX_BINS];         // probability x geometric cross-section (mm^2) of each bin
+    int n_terms[MC_MAX_BINS], n_start[MC_MAX_BINS];
+    double m_re, m_im;
+    int n_bins, n_angles, n_cdf;
+    double geo_median;             // geometric cross-section of the median diameter (mm^2)
+    double *rows;                  // n_bins x n_angles: c_k Q_sca,k P_k(theta_j)
+    double *bins;                  // n_bins x 4: Q_ext,k, Q_sca,k, g_k, N_k
+    float *inv_cdf;
+    double *phase, *cdf;
+    double *result;                // q_ext, q_sca (over geo_median), g, max N
+};
+
+__global__ __launch_bounds__(kBlock) void mie_bin_kernel(PolyArgs a)
+{
+    __shared__ cplx s_a[MC_MAX_TERMS];
+    __shared__ cplx s_b[MC_MAX_TERMS];
+    __shared__ double s_w;
+    const int k = blockIdx.x, tid = threadIdx.x;
+    const double x = a.x[k];
+    const int N = a.n_terms[k];
+    if (tid == 0) {
+        double q_ext, q_sca, g;
+        mie_series(x, a.m_re, a.m_im, N, a.n_start[k], s_a, s_b, &q_ext, &q_sca, &g);
+        a.bins[4 * k + 0] = q_ext;
+        a.bins[4 * k + 1] = q_sca;
+        a.bins[4 * k + 2] = g;
+        a.bins[4 * k + 3] = (double)N;
+        // c_k Q_sca,k P_k with P_k = 2 (|S1|^2 + |S2|^2) / (x^2 Q_sca,k): the Q_sca,k cancel.
+        s_w = a.c[k] * 2.0 / (x * x);
+    }
+    __syncthreads();
+    const int na = a.n_angles;
+    const double dth = M_PI / (double)(na - 1);
+    for (int j = tid; j < na; j += kBlock)
+        a.rows[(uint64_t)k * na + j] = s_w * mie_intensity((double)j * dth, N, s_a, s_b);
+}
+
+__global__ __launch_bounds__(kBlock) void mie_mix_kernel(PolyArgs a)
+{
+    __shared__ double s_ang[MC_MAX_N_ANGLES];
+    __shared__ double s_part[kBlock];
+    __shared__ double s_sca;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        // Number-averaged cross-sections and the C_sca-weighted asymmetry, in bin order.
+        double ext = 0.0, sca = 0.0, gs = 0.0, nmax = 0.0;
+        for (int k = 0; k < a.n_bins; ++k) {
+            ext += a.c[k] * a.bins[4 * k + 0];
+            sca += a.c[k] * a.bins[4 * k + 1];
+            gs += a.c[k] * a.bins[4 * k + 1] * a.bins[4 * k + 2];
+            nmax = fmax(nmax, a.bins[4 * k + 3]);
+        }
+        s_sca = sca;
+        a.result[0] = ext / a.geo_median;
+        a.result[1] = sca / a.geo_median;
+        a.result[2] = gs / sca;
+        a.result[3] = nmax;
+    }
+    __syncthreads();
+    const int na = a.n_angles;
+    const double dth = M_PI / (double)(na - 1);
+    const double inv_sca = 1.0 / s_sca;
+    for (int j = tid; j < na; j += kBlock) {
+        double mix = 0.0;
+        for (int k = 0; k < a.n_bins; ++k) mix += a.rows[(uint64_t)k * na + j];
+        const double P = mix * inv_sca;
+        if (a.phase) a.phase[j] = P;
+        s_ang[j] = P * sin((double)j * dth);
+    }
+    __syncthreads();
+    cdf_and_inverse(s_ang, s_part, &s_sca, na, a.n_cdf, a.inv_cdf, a.cdf);
 }
 
 // Per-device scratch for the four scalar results (allocated once, kept).
@@ -293,8 +397,184 @@ void set_scalars(mie_table_t *table, const mie_spec_t &s, const double res[3])
     table->sigma_abs_mm2 = (res[0] - res[1]) * geo_mm2;
 }
 
+// The caller's result buffer, or the library's per-device scratch (then
+// `lock` holds the scratch until the results are back on the host).
+int result_buffer(mie_table_t *table, std::unique_lock<std::mutex> &lock, double **out, const char *who)
+{
+    *out = table->result;
+    if (*out) return MC_OK;
+    int dev = 0;
+    MC_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(MC_EDEVICE, "device index %d out of range", dev);
+    lock.lock();
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        if (hipMalloc(&p, 8 * sizeof(double)) != hipSuccess) return fail(MC_ENOMEM, "%s: scratch allocation failed", who);
+        g_scratch[dev] = (double *)p;
+    }
+    *out = g_scratch[dev];
+    return MC_OK;
+}
+
+// Orthonormal Hermite polynomial h_n(t) for the weight exp(-t^2), by the
+// three-term recurrence h_{j+1} = sqrt(2/(j+1)) t h_j - sqrt(j/(j+1)) h_{j-1}
+// from h_0 = pi^(-1/4), together with sum_{j<n} h_j(t)^2.
+void hermite_orthonormal(int n, double t, double *h_n, double *sum_sq)
+{
+    double h_prev = 0.0, h = std::pow(M_PI, -0.25), s = 0.0;
+    for (int j = 0; j < n; ++j) {
+        s += h * h;
+        const double h_next = std::sqrt(2.0 / (j + 1)) * t * h - std::sqrt((double)j / (j + 1)) * h_prev;
+        h_prev = h;
+        h = h_next;
+    }
+    *h_n = h;
+    *sum_sq = s;
+}
+
+// Gauss-Hermite rule for the weight exp(-t^2): the nodes are the n roots of
+// h_n, all inside (-sqrt(2n+1), sqrt(2n+1)); each is bracketed by a sign
+// change on a grid far finer than the root spacing and bisected to machine
+// precision.  The weights are the Christoffel numbers 1 / sum_{j<n} h_j(t)^2.
+int gauss_hermite(int n, double *t, double *w)
+{
+    if (n == 1) {
+        t[0] = 0.0;
+        w[0] = std::sqrt(M_PI);
+        return MC_OK;
+    }
+    const double R = std::sqrt(2.0 * n + 1.0) + 1.0;
+    const int steps = 400 * n;
+    int found = 0;
+    double t_prev = -R, h_prev, s;
+    hermite_orthonormal(n, t_prev, &h_prev, &s);
+    for (int i = 1; i <= steps && found < n; ++i) {
+        const double ti = -R + 2.0 * R * (double)i / steps;
+        double hi;
+        hermite_orthonormal(n, ti, &hi, &s);
+        if ((h_prev < 0.0) != (hi < 0.0) || hi == 0.0) {
+            double lo = t_prev, up = ti, h_lo = h_prev;
+            for (int it = 0; it < 200 && hi != 0.0; ++it) {
+                const double mid = 0.5 * (lo + up);
+                if (mid <= lo || mid >= up) break;
+                double hm;
+                hermite_orthonormal(n, mid, &hm, &s);
+                if ((hm < 0.0) == (h_lo < 0.0)) {
+                    lo = mid;
+                    h_lo = hm;
+                } else {
+                    up = mid;
+                }
+            }
+            const double root = hi == 0.0 ? ti : 0.5 * (lo + up);
+            double hr;
+            hermite_orthonormal(n, root, &hr, &s);
+            t[found] = root;
+            w[found] = 1.0 / s;
+            ++found;
+            // Step past an exact zero so it is not found twice.
+            hermite_orthonormal(n, ti, &hi, &s);
+            if (hi == 0.0) hi = -h_prev;
+        }
+        t_prev = ti;
+        h_prev = hi;
+    }
+    return found == n ? MC_OK : fail(MC_EINVAL, "Gauss-Hermite: found %d of %d nodes", found, n);
+}
+
+int lognormal_bins(double median_um, double sigma_ln, int n, double *d, double *p)
+{
+    if (!(median_um > 0.0) || !std::isfinite(median_um) || !(sigma_ln >= 0.0) || !std::isfinite(sigma_ln))
+        return fail(MC_EINVAL, "lognormal bins: median must be > 0 and sigma_ln >= 0, both finite");
+    if (n < 1 || n > MC_MAX_BINS) return fail(MC_EINVAL, "lognormal bins: n_bins %d outside 1..%d", n, MC_MAX_BINS);
+    double t[MC_MAX_BINS], w[MC_MAX_BINS];
+    if (int rc = gauss_hermite(n, t, w)) return rc;
+    for (int k = 0; k < n; ++k) {
+        d[k] = median_um * std::exp(std::sqrt(2.0) * sigma_ln * t[k]);
+        p[k] = w[k] / std::sqrt(M_PI);
+    }
+    return MC_OK;
+}
+
+uint64_t poly_work_words(int n_angles, int n_bins) { return (uint64_t)n_bins * n_angles + 4ull * n_bins; }
+
 }  // namespace
 }  // namespace mcmie
+
+extern "C" int mc_lognormal_bins(double median_um, double sigma_ln, int32_t n_bins, double *diameters_um,
+                                 double *probs)
+{
+    using namespace mcmie;
+    clear_error();
+    if (!diameters_um || !probs) return fail(MC_EINVAL, "mc_lognormal_bins: null output");
+    return lognormal_bins(median_um, sigma_ln, n_bins, diameters_um, probs);
+}
+
+extern "C" uint64_t mie_poly_work_bytes(const mie_spec_t *spec, const mie_poly_t *poly)
+{
+    if (!spec || !poly || spec->n_angles < 3 || spec->n_angles > MC_MAX_N_ANGLES || poly->n_bins < 1 ||
+        poly->n_bins > MC_MAX_BINS)
+        return 0;
+    return mcmie::poly_work_words(spec->n_angles, poly->n_bins) * 8;
+}
+
+extern "C" int mie_table_build_poly(const mie_spec_t *spec, const mie_poly_t *poly, mie_table_t *table, void *stream)
+{
+    using namespace mcmie;
+    clear_error();
+    const char *who = "mie_table_build_poly";
+    MieArgs med;
+    if (int rc = prepare_table(spec, table, &med, who)) return rc;
+    if (!poly) return fail(MC_EINVAL, "%s: null poly", who);
+    const mie_spec_t s = *spec;
+    const mie_poly_t q = *poly;
+    if (table->coef) return fail(MC_EINVAL, "%s: coef is not produced for a size distribution (set it to NULL)", who);
+    if (!q.work || ((uintptr_t)q.work & 7) || q.work_bytes < poly_work_words(s.n_angles, q.n_bins) * 8)
+        return fail(MC_EINVAL, "%s: work needs %llu bytes, 8-byte aligned", who,
+                    (unsigned long long)(poly_work_words(s.n_angles, std::max(1, q.n_bins)) * 8));
+    double d[MC_MAX_BINS], p[MC_MAX_BINS];
+    if (int rc = lognormal_bins(s.diameter_um, q.sigma_ln, q.n_bins, d, p)) return rc;
+    PolyArgs a{};
+    a.m_re = med.m_re;
+    a.m_im = med.m_im;
+    a.n_bins = q.n_bins;
+    a.n_angles = s.n_angles;
+    a.n_cdf = s.n_cdf;
+    for (int k = 0; k < q.n_bins; ++k) {
+        // Each bin's parameters as prepare_table derives them for one size.
+        const double x = M_PI * d[k] * 1e3 * s.n_medium / s.wavelength_nm;
+        const double mx_abs = x * std::hypot(med.m_re, med.m_im);
+        const int n_terms = (int)std::lround(x + 4.0 * std::cbrt(x) + 2.0);
+        if (n_terms > MC_MAX_TERMS)
+            return fail(MC_EINVAL, "%s: bin %d needs %d series terms, more than %d", who, k, n_terms, MC_MAX_TERMS);
+        a.x[k] = x;
+        a.n_terms[k] = n_terms;
+        a.n_start[k] = (int)std::ceil(std::max((double)n_terms, mx_abs)) + 16 + (int)std::ceil(8.0 * std::cbrt(mx_abs));
+        a.c[k] = p[k] * M_PI * (d[k] * 1e-3) * (d[k] * 1e-3) / 4.0;
+    }
+    a.geo_median = M_PI * (s.diameter_um * 1e-3) * (s.diameter_um * 1e-3) / 4.0;
+    a.rows = q.work;
+    a.bins = q.work + (uint64_t)q.n_bins * s.n_angles;
+    a.inv_cdf = table->inv_cdf;
+    a.phase = table->phase;
+    a.cdf = table->cdf;
+    std::unique_lock<std::mutex> lock(g_scratch_mu, std::defer_lock);
+    if (int rc = result_buffer(table, lock, &a.result, who)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(mie_bin_kernel, dim3(q.n_bins), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(mie_mix_kernel, dim3(1), dim3(kBlock), 0, st, a);
+    MC_HIP_CHECK(hipGetLastError());
+    double res[4];
+    MC_HIP_CHECK(hipMemcpyAsync(res, a.result, sizeof res, hipMemcpyDeviceToHost, st));
+    MC_HIP_CHECK(hipStreamSynchronize(st));
+    table->x = med.x;
+    table->m_rel_re = med.m_re;
+    table->m_rel_im = med.m_im;
+    table->n_terms = (int)res[3];
+    table->n_cdf = s.n_cdf;
+    set_scalars(table, s, res);
+    return MC_OK;
+}
 
 extern "C" int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void *stream)
 {
@@ -303,23 +583,9 @@ extern "C" int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void 
     hipStream_t st = (hipStream_t)stream;
     MieArgs args;
     if (int rc = prepare_table(spec, table, &args, "mie_table_build")) return rc;
-    double *result = table->result;
+    double *result = nullptr;
     std::unique_lock<std::mutex> lock(g_scratch_mu, std::defer_lock);
-    if (!result) {
-        // No caller buffer: the library's per-device scratch, held until the
-        // results are back on the host.
-        int dev = 0;
-        MC_HIP_CHECK(hipGetDevice(&dev));
-        if (dev < 0 || dev >= 64) return fail(MC_EDEVICE, "device index %d out of range", dev);
-        lock.lock();
-        if (!g_scratch[dev]) {
-            void *p = nullptr;
-            if (hipMalloc(&p, 8 * sizeof(double)) != hipSuccess)
-                return fail(MC_ENOMEM, "mie_table_build: scratch allocation failed");
-            g_scratch[dev] = (double *)p;
-        }
-        result = g_scratch[dev];
-    }
+    if (int rc = result_buffer(table, lock, &result, "mie_table_build")) return rc;
     if (int rc = launch_table(args, table, st, result)) return rc;
     double res[4];
     MC_HIP_CHECK(hipMemcpyAsync(res, result, sizeof res, hipMemcpyDeviceToHost, st));

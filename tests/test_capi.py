@@ -281,3 +281,55 @@ def test_batch_rejects_invalid_arguments():
     rc = L.mc_autotune_batch(items, 3, 4096, C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
                              C.byref(tal), 0.5, None, C.byref(chk), C.byref(best), None, None)
     assert rc == mc.MC_EINVAL
+
+
+@pytest.mark.parametrize("sigma", [0.05, 0.3])
+def test_host_lognormal_bins_reproduce_moments(sigma):
+    """The library's own Gauss-Hermite bins (host code): 64 bins reproduce the
+    closed-form lognormal moments E[d^j] = d_med^j exp(j^2 sigma^2 / 2) to
+    rounding; the 2-point rule is d_med exp(+-sigma) with probability 1/2 each;
+    the 7-point rule matches numpy's Gauss-Hermite nodes and weights."""
+    import math
+    import numpy as np
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    d, p = mc.mc_lognormal_bins(5.0, sigma, 64)
+    assert sum(p) == pytest.approx(1.0, abs=1e-14)
+    for j in range(1, 7):
+        exact = 5.0 ** j * math.exp(j * j * sigma * sigma / 2.0)
+        assert sum(pk * dk ** j for pk, dk in zip(p, d)) == pytest.approx(exact, rel=1e-12)
+    assert d == sorted(d)
+    d2, p2 = mc.mc_lognormal_bins(5.0, sigma, 2)
+    assert d2 == pytest.approx([5.0 * math.exp(-sigma), 5.0 * math.exp(sigma)], rel=1e-14)
+    assert p2 == pytest.approx([0.5, 0.5], rel=1e-14)
+    t, w = np.polynomial.hermite.hermgauss(7)
+    d7, p7 = mc.mc_lognormal_bins(5.0, sigma, 7)
+    np.testing.assert_allclose(d7, 5.0 * np.exp(math.sqrt(2.0) * sigma * t), rtol=1e-14)
+    np.testing.assert_allclose(p7, w / math.sqrt(math.pi), rtol=1e-12)
+
+
+def test_host_lognormal_bins_and_poly_table_validate():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    L = mc.lib()
+    d = (C.c_double * 70)()
+    p = (C.c_double * 70)()
+    for med, sig, n in ((5.0, 0.05, 0), (5.0, 0.05, mc.MC_MAX_BINS + 1), (5.0, -0.1, 8), (0.0, 0.1, 8)):
+        assert L.mc_lognormal_bins(med, sig, n, d, p) == mc.MC_EINVAL
+    spec = mc.MieSpec(n_medium=1.33, m_re=1.59, m_im=0.0, diameter_um=5.0, wavelength_nm=532.0,
+                      n_angles=1801, n_cdf=4096)
+    q = mc.MiePoly(sigma_ln=0.05, n_bins=64)
+    assert L.mie_poly_work_bytes(C.byref(spec), C.byref(q)) == 8 * (64 * 1801 + 4 * 64)
+    t = mc._capi._MieTableC()
+    t.inv_cdf = 0x1000
+    assert L.mie_table_build_poly(C.byref(spec), None, C.byref(t), None) == mc.MC_EINVAL
+    q.work, q.work_bytes = 0x1000, 8 * (64 * 1801 + 4 * 64) - 8
+    assert L.mie_table_build_poly(C.byref(spec), C.byref(q), C.byref(t), None) == mc.MC_EINVAL
+    assert b"work" in L.mc_last_error()
+    q.work_bytes += 8
+    t.coef = 0x1000
+    assert L.mie_table_build_poly(C.byref(spec), C.byref(q), C.byref(t), None) == mc.MC_EINVAL
+    assert b"coef" in L.mc_last_error()
+    t.coef = None
+    q.n_bins = 0
+    assert L.mie_table_build_poly(C.byref(spec), C.byref(q), C.byref(t), None) == mc.MC_EINVAL
