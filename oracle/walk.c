@@ -53,6 +53,7 @@ typedef struct {
     uint32_t max_steps;
     double roulette_w, roulette_p;
     int32_t side_nx, side_ny, trans_nx, trans_ny;
+    double beam_radius;      /* radius of the parallel beam's disk on the z = 0 face (mm), 0: pencil */
 } oracle_params;
 
 enum { S_FACE0 = 0, S_ABSORBED = 6, S_ROULETTE_NET = 7, S_CAPPED_W = 8, S_EVENTS = 9,
@@ -167,6 +168,19 @@ static photon_end walk_one(const oracle_params *p, uint64_t id, double *scal)
     d[2] = sqrt(fmax(0.0, 1.0 - tang2));
     double w = 1.0 - oracle_fresnel(cos_i, p->n_out, p->n_med);
     double pos[3] = {p->src_pos[0], p->src_pos[1], p->src_pos[2]};
+    if (p->beam_radius > 0.0) {
+        /* A beam of finite width (Sec. 4.1): the entry point is uniform on the
+         * disk of that radius around the source position, drawn from the
+         * photon's Philox block at the reserved step counter 2^32 - 1:
+         * radius R sqrt(u0), azimuth 2 pi u1. */
+        uint32_t ctr[4] = {0xFFFFFFFFu, p->instance, (uint32_t)id, (uint32_t)(id >> 32)};
+        uint32_t r[4];
+        oracle_philox4x32_10(ctr, key, r);
+        const double rho = p->beam_radius * sqrt(uniform_of(r[0]));
+        const double phi = 2.0 * M_PI * uniform_of(r[1]);
+        pos[0] += rho * cos(phi);
+        pos[1] += rho * sin(phi);
+    }
     double L = 0.0, A = 0.0;
     uint32_t k = 0, step = 0, refl = 0;
     int face = -1, cause = CAUSE_CAPPED;

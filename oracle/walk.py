@@ -38,7 +38,7 @@ class _Params(C.Structure):
                 ("seed", C.c_uint64), ("instance", C.c_uint32), ("max_steps", C.c_uint32),
                 ("roulette_w", C.c_double), ("roulette_p", C.c_double),
                 ("side_nx", C.c_int32), ("side_ny", C.c_int32),
-                ("trans_nx", C.c_int32), ("trans_ny", C.c_int32)]
+                ("trans_nx", C.c_int32), ("trans_ny", C.c_int32), ("beam_radius", C.c_double)]
 
 
 _lib = None
@@ -109,6 +109,7 @@ class Walk:
         p.n_out = w.n_outside
         # Eq. 1: OD = mu_ext * l along the beam (z extent).
         p.mu_t = w.tau / w.size_mm[2]
+        p.beam_radius = getattr(w, "beam_radius_mm", 0.0)
         p.albedo = w.albedo
         p.phase = w.phase
         p.n_table = len(self._v)

@@ -45,6 +45,7 @@ class Workload:
     n_outside: float = 1.0                # index outside the walls (air)
     src_pos_mm: tuple = (5.0, 5.0, 0.0)   # pencil beam at the z = 0 face centre
     src_dir: tuple = (0.0, 0.0, 1.0)
+    beam_radius_mm: float = 0.0           # parallel beam of this radius (0: pencil)
     n_angles: int = 1801                  # 0.1 degree phase table
     n_cdf: int = 4096
     phase: int = PHASE_MIE
