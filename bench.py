@@ -31,7 +31,14 @@ The JSON line also carries
                 sigma_ln 0.05, 64 bins), tau = 16, 1e9 photons, 1024 x 1024
                 int64 fixed-point images; table build time, forward scatter
                 events/s, and forward + adjoint against forward time
-                (--no-heavy skips it).
+                (--no-heavy skips it);
+  analysis      the paper's image comparison on simulated side images: at
+                each optical depth of Tables 3 and 4, a Mie and an HG run
+                with the 1.25 mm-radius parallel beam (1e8 photons, 512 x 512)
+                and an independent Mie run (other seed) as the reference;
+                RMSE and r of both against it, the three radial zone errors,
+                the radial correlation and the share of annuli where Mie is
+                closer, and the time of mc_image_metrics (--no-analysis skips it).
 
     python bench.py [--steps K] [--warmup W]
 """
@@ -264,6 +271,37 @@ def heavy_timing(mc, W, dev, args):
             "fwd_adjoint_ms": adj_ms, "adjoint_ratio": adj_ms / fwd_ms}
 
 
+def analysis_timing(mc, W, dev, args):
+    """Tables 3 and 4's measures between simulated images, per optical depth."""
+    import torch
+    rows = []
+    metric_ms = []
+    for od in W.ANALYSIS_ODS:
+        wm = W.analysis_workload(od)
+        table = mc.mie_table_build(mc.args_from_workload(wm)[0], dev)
+        imgs = {}
+        for name, w, g in (("mie", wm, None), ("ref", wm.replace(seed=W.ANALYSIS_REF_SEED), None),
+                           ("hg", wm.replace(phase=W.PHASE_HG), table.g)):
+            _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g)
+            t = mc.Tally.alloc(det, dev)
+            mc.mc_simulate(med, src, geo, det, run, t)
+            imgs[name] = t.side
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m_mie = mc.image_metrics(imgs["mie"], imgs["ref"], imgs["hg"])
+        metric_ms.append((time.perf_counter() - t0) * 1e3)
+        m_hg = mc.image_metrics(imgs["hg"], imgs["ref"])
+        rows.append({"od": od,
+                     "rmse": {"hg": m_hg["rmse"], "mie": m_mie["rmse"]},
+                     "r": {"hg": m_hg["r"], "mie": m_mie["r"]},
+                     "zone_rmse": {"hg": m_hg["zone_rmse"], "mie": m_mie["zone_rmse"]},
+                     "radial_r": {"hg": m_hg["radial_r"], "mie": m_mie["radial_r"]},
+                     "mie_better": m_mie["better"]})
+    return {"images": "side, 512 x 512, 1e8 photons, beam radius 1.25 mm; reference: Mie, seed "
+                      f"{W.ANALYSIS_REF_SEED}", "per_od": rows,
+            "metrics_ms": sorted(metric_ms)[len(metric_ms) // 2]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,6 +316,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-heavy", action="store_true")
+    ap.add_argument("--no-analysis", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -343,6 +382,8 @@ def main():
     log("bench: batch timing done")
     heavy = None if args.no_heavy else heavy_timing(mc, W, dev, args)
     log("bench: heavy timing done")
+    analysis = None if args.no_analysis else analysis_timing(mc, W, dev, args)
+    log("bench: analysis done")
 
     scal = [t.scalars.cpu().numpy() for t in tallies[args.warmup:]]
     events = float(sum(s[9] for s in scal))
@@ -384,6 +425,7 @@ def main():
         "adjoint": adjoint,
         "batch": batch,
         "heavy": heavy,
+        "analysis": analysis,
     }
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")

@@ -194,11 +194,16 @@ typedef struct {
     double sigma_abs_mm2;  /* concentration derivative; 0 and 0 make that derivative NaN */
 } mc_medium_t;
 
-/* Collimated pencil beam entering the z = 0 face (Sec. 3.1.3: parallel beam,
- * all photons with the same initial direction). */
+/* Collimated beam entering the z = 0 face (Sec. 3.1.3: parallel beam, all
+ * photons with the same initial direction), a pencil or a disk. */
 typedef struct {
     double pos_mm[3];      /* entry point: z must be 0, x and y inside the face */
     double dir[3];         /* incident direction outside the cuboid, dir[2] > 0 (normalised here) */
+    double beam_radius_mm; /* 0: pencil beam; > 0: a parallel beam whose photons enter uniformly
+                              on the disk of this radius around pos_mm (Sec. 4.1), drawn from each
+                              photon's Philox block at the reserved step counter 2^32 - 1 (radius
+                              R sqrt(u0), azimuth 2 pi u1); the disk must lie inside the z = 0 face
+                              and max_steps must then be below 2^32 - 1 */
 } mc_source_t;
 
 /* Cuboid cuvette (Sec. 4.3) with one refractive-index step at every wall. */
@@ -371,6 +376,43 @@ int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry, const mc_d
  */
 int mc_philox_blocks(uint64_t seed, uint32_t instance, const uint64_t *ids, uint64_t n_ids,
                      uint32_t step0, uint32_t n_steps, uint32_t *out, void *stream);
+
+/* ------------------------------------------------------- image measures */
+
+/*
+ * Comparison measures of Sec. 5.2 (Tables 3 and 4) between two images a and
+ * b (b the reference), and optionally a third c, all DEVICE row-major
+ * ny x nx doubles (at most 2^24 pixels).  Each image is divided by its largest
+ * pixel first.  out[] (host) receives:
+ *   0 RMSE over pixels of the difference of the normalised images (Table 3)
+ *   1 Pearson's r over pixels (Table 3; NaN when an image is constant)
+ *   2, 3, 4  radial RMSE of the normalised images' annulus profiles in the
+ *      forward (theta < 30 deg), intermediate (30..120 deg) and edge
+ *      (> 120 deg) zones (Table 4), with theta = 180 deg (k + 0.5) / r_max for
+ *      annulus k (k <= rho < k + 1 pixels around (cx, cy), pixel centres at
+ *      (column + 0.5, row + 0.5)); empty zones give 0
+ *   5 Pearson's r of the two profiles over non-empty annuli (Table 4)
+ *   6 annuli ceil(r_max);  7, 8, 9 largest pixel of a, b, c
+ *   10 with c: share of non-empty annuli where a's profile is closer to b's
+ *      than c's is (Table 4, last column); NaN without c
+ *   11 pixels compared
+ * profiles, if not NULL, receives 4 x annuli doubles on the device: the
+ * profiles of a, b, c and the pixel count of each annulus.  work is DEVICE
+ * scratch of mc_metrics_work_bytes bytes.  Sums over pixels use a fixed
+ * partition and tree reductions; annulus sums are int64 fixed point, so the
+ * results do not depend on scheduling.  Waits for the stream.
+ */
+#define MC_METRICS_N 12
+#define MC_MAX_ANNULI 2048
+typedef struct {
+    double cx, cy;         /* radial centre in pixel units (column, row), e.g. nx / 2, ny / 2 */
+    double r_max;          /* outer radius in pixels, 0 < r_max <= MC_MAX_ANNULI */
+} mc_radial_t;
+
+uint64_t mc_metrics_work_bytes(int32_t nx, int32_t ny, const mc_radial_t *radial);
+int mc_image_metrics(const double *a, const double *b, const double *c, int32_t nx, int32_t ny,
+                     const mc_radial_t *radial, double *profiles, void *work, uint64_t work_bytes,
+                     double out[MC_METRICS_N], void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *mc_last_error(void);

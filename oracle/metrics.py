@@ -52,7 +52,8 @@ def radial_profile(img: np.ndarray, cx: float, cy: float, r_max: float):
     n = normalise(img)
     ny, nx = n.shape
     yy, xx = np.meshgrid(np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
-    rho = np.hypot(xx - cx, yy - cy)
+    dx, dy = xx - cx, yy - cy
+    rho = np.sqrt(dx * dx + dy * dy)
     n_r = int(math.ceil(r_max))
     keep = rho < r_max
     k = np.floor(rho[keep]).astype(np.int64)

@@ -4,6 +4,7 @@ torch tensors; work is enqueued on torch's current HIP stream."""
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 from typing import Optional
@@ -22,6 +23,7 @@ MC_REC_I_N, MC_REC_F_N = 4, 9
 MC_MAX_N_CDF, MC_MAX_N_ANGLES, MC_MAX_TERMS = 16384, 3001, 1024
 MC_MAX_BATCH = 512
 MC_MAX_BINS = 64
+MC_METRICS_N, MC_MAX_ANNULI = 12, 2048
 # Candidates mc_autotune_batch times, in its block-major order.
 AUTOTUNE_BLOCKS, AUTOTUNE_CHUNKS = (256, 512, 1024), (256, 512, 1024, 2048, 4096)
 
@@ -47,6 +49,11 @@ class MiePoly(C.Structure):
                 ("work", C.c_void_p), ("work_bytes", C.c_uint64)]
 
 
+class Radial(C.Structure):
+    """Centre (column, row) and outer radius in pixels of the radial analysis (mc_radial_t)."""
+    _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("r_max", C.c_double)]
+
+
 class Medium(C.Structure):
     _fields_ = [("tau", C.c_double), ("albedo", C.c_double), ("phase", C.c_int32), ("n_cdf", C.c_int32),
                 ("inv_cdf", C.c_void_p), ("g", C.c_double), ("sigma_sca_mm2", C.c_double),
@@ -54,7 +61,7 @@ class Medium(C.Structure):
 
 
 class Source(C.Structure):
-    _fields_ = [("pos_mm", C.c_double * 3), ("dir", C.c_double * 3)]
+    _fields_ = [("pos_mm", C.c_double * 3), ("dir", C.c_double * 3), ("beam_radius_mm", C.c_double)]
 
 
 class Geometry(C.Structure):
@@ -119,6 +126,10 @@ def lib():
         L.mie_poly_work_bytes.restype = C.c_uint64
         L.mc_lognormal_bins.argtypes = [C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
+        L.mc_metrics_work_bytes.argtypes = [C.c_int32, C.c_int32, C.POINTER(Radial)]
+        L.mc_metrics_work_bytes.restype = C.c_uint64
+        L.mc_image_metrics.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Radial),
+                                       C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_double), C.c_void_p]
         L.mc_workspace_bytes.argtypes = [C.POINTER(Detector)]
         L.mc_workspace_bytes.restype = C.c_uint64
         L.mc_workspace_bytes_batch.argtypes = [C.POINTER(Detector), C.c_uint32]
@@ -131,7 +142,8 @@ def lib():
         L.mc_last_error.restype = C.c_char_p
         L.mc_version.restype = C.c_int
         for f in ("mie_table_build", "mie_table_enqueue", "mc_simulate", "mc_grad", "mc_philox_blocks",
-                  "mc_simulate_batch", "mc_autotune_batch", "mie_table_build_poly", "mc_lognormal_bins"):
+                  "mc_simulate_batch", "mc_autotune_batch", "mie_table_build_poly", "mc_lognormal_bins",
+                  "mc_image_metrics"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -375,6 +387,31 @@ def mc_autotune_batch(items, n_cdf: int, source: Source, geometry: Geometry, det
     table = {(b, c): cand[i * len(AUTOTUNE_CHUNKS) + j]
              for i, b in enumerate(AUTOTUNE_BLOCKS) for j, c in enumerate(AUTOTUNE_CHUNKS)}
     return blk.value, chk.value, best.value, table
+
+
+def image_metrics(a, b, c=None, *, cx=None, cy=None, r_max=None, profiles=False, stream=None) -> dict:
+    """Comparison measures of Tables 3 and 4 between images a and b (b the
+    reference) and optionally c (float64 device tensors of one shape); the
+    radial centre defaults to the image centre and r_max to half the shorter
+    side.  Waits for the stream."""
+    import torch
+    ny, nx = (int(v) for v in a.shape)
+    rad = Radial(nx / 2.0 if cx is None else cx, ny / 2.0 if cy is None else cy,
+                 min(nx, ny) / 2.0 if r_max is None else r_max)
+    nbytes = int(lib().mc_metrics_work_bytes(nx, ny, C.byref(rad)))
+    if nbytes == 0:
+        raise ValueError("invalid image shape or radial settings")
+    work = torch.empty(nbytes // 8, dtype=torch.float64, device=a.device)
+    n_r = int(math.ceil(rad.r_max))
+    prof = torch.empty((4, n_r), dtype=torch.float64, device=a.device) if profiles else None
+    out = (C.c_double * MC_METRICS_N)()
+    _check(lib().mc_image_metrics(_ptr(a), _ptr(b), _ptr(c), nx, ny, C.byref(rad), _ptr(prof), _ptr(work), nbytes,
+                                  out, _stream(stream)))
+    res = dict(rmse=out[0], r=out[1], zone_rmse=[out[2], out[3], out[4]], radial_r=out[5], n_annuli=int(out[6]),
+               max=[out[7], out[8], out[9]], better=out[10], pixels=int(out[11]))
+    if profiles:
+        res["profile_a"], res["profile_b"], res["profile_c"], res["count"] = prof[0], prof[1], prof[2], prof[3]
+    return res
 
 
 def mc_philox_blocks(seed: int, instance: int, ids, step0: int, n_steps: int, out, stream=None) -> None:

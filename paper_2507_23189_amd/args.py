@@ -22,6 +22,7 @@ def args_from_workload(w, table=None, *, g=None, flags=0, record_stride=1, block
     for i in range(3):
         src.pos_mm[i] = w.src_pos_mm[i]
         src.dir[i] = w.src_dir[i]
+    src.beam_radius_mm = getattr(w, "beam_radius_mm", 0.0)
     geo = Geometry()
     for i in range(3):
         geo.size_mm[i] = w.size_mm[i]

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmcmie.so")
-SOURCES = ["capi.cpp", "mie_table.hip", "walk.hip"]
+SOURCES = ["capi.cpp", "mie_table.hip", "walk.hip", "metrics.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

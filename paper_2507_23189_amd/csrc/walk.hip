@@ -68,6 +68,7 @@ struct WalkArgs {
     float n12;                // n_med / n_out (exit refraction, records only)
     int matched;              // n_out == n_med: no Fresnel term
     float pos0[3], dir0[3], w0;
+    float beam_radius;        // > 0: entry points uniform on the disk of this radius around pos0
     float roulette_w, roulette_p, inv_roulette_p;
     int phase, n_cdf;
     const float *inv_cdf;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         const float da = ax == 0 ? a.dir0[0] : (ax == 1 ? a.dir0[1] : a.dir0[2]);
         int face = -1;
         uint32_t key = 0;
-        if (da > 0.f && (ax == 0 || ax == 2) && !(MOMENTS && ax == 0)) {
+        if (da > 0.f && (ax == 0 || ax == 2) && !(MOMENTS && ax == 0) && !(a.beam_radius > 0.f)) {
             face = 2 * ax + 1;
             key = ax == 0 ? (uint32_t)(pixel(by, a.size[1], a.side_ny) * a.side_nx + pixel(bz, a.size[2], a.side_nx))
                           : a.n_side + (uint32_t)(pixel(by, a.size[1], a.trans_ny) * a.trans_nx +
@@ -356,6 +357,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 }
                 alive = true;
                 px = a.pos0[0]; py = a.pos0[1]; pz = a.pos0[2];
+                if (a.beam_radius > 0.f) {
+                    // Finite beam: entry point uniform on the disk, from the
+                    // photon's Philox block at the reserved step counter.
+                    uint32_t k0 = a.key0, k1 = a.key1;
+                    const Block4 rb = philox4x32_10(0xFFFFFFFFu, l_ctr, (uint32_t)id, (uint32_t)(id >> 32), k0, k1);
+                    const float rho = a.beam_radius * __builtin_amdgcn_sqrtf(uniform01(rb.r0));
+                    const float u1 = uniform01(rb.r1);
+                    px = fmaf(rho, __builtin_amdgcn_cosf(u1), px);    // cos(2 pi u1)
+                    py = fmaf(rho, __builtin_amdgcn_sinf(u1), py);    // sin(2 pi u1)
+                }
                 dx = a.dir0[0]; dy = a.dir0[1]; dz = a.dir0[2];
                 w = a.w0; L = 0.f; A = 0.f; k = 0; step = 0;
             }
@@ -796,6 +807,14 @@ int check_setup(const char *fn, const mc_source_t &src, const mc_geometry_t &geo
     const double dl = std::sqrt(src.dir[0] * src.dir[0] + src.dir[1] * src.dir[1] + src.dir[2] * src.dir[2]);
     if (!(dl > 0.0) || !std::isfinite(dl) || !(src.dir[2] > 0.0))
         return fail(MC_EINVAL, "%s: the source direction must point into the cuboid (dir[2] > 0)", fn);
+    const double R = src.beam_radius_mm;
+    if (!(R >= 0.0) || !std::isfinite(R))
+        return fail(MC_EINVAL, "%s: beam_radius_mm must be finite and >= 0", fn);
+    if (R > 0.0 && (src.pos_mm[0] - R < 0.0 || src.pos_mm[0] + R > geo.size_mm[0] || src.pos_mm[1] - R < 0.0 ||
+                    src.pos_mm[1] + R > geo.size_mm[1]))
+        return fail(MC_EINVAL, "%s: the beam disk must lie inside the z = 0 face", fn);
+    if (R > 0.0 && rn.max_steps == 0xFFFFFFFFu)
+        return fail(MC_EINVAL, "%s: a finite beam reserves step counter 2^32 - 1 (max_steps must be lower)", fn);
     if (!dims_ok(det)) return fail(MC_EINVAL, "%s: image dimensions must be >= 1", fn);
     if (!t.side || !t.trans || !t.scalars) return fail(MC_EINVAL, "%s: side, trans and scalars are required", fn);
     if ((det.flags & MC_SIGMA) && (!t.side_w2 || !t.trans_w2))
@@ -857,6 +876,7 @@ void fill_common(WalkArgs &a, const mc_source_t &src, const mc_geometry_t &geo, 
         a.dir0[i] = (float)d0[i];
     }
     a.w0 = (float)(1.0 - R0);
+    a.beam_radius = (float)src.beam_radius_mm;
     a.roulette_w = (float)rn.roulette_w;
     a.roulette_p = (float)rn.roulette_p;
     a.inv_roulette_p = (float)(1.0 / rn.roulette_p);

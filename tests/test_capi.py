@@ -333,3 +333,40 @@ def test_host_lognormal_bins_and_poly_table_validate():
     t.coef = None
     q.n_bins = 0
     assert L.mie_table_build_poly(C.byref(spec), C.byref(q), C.byref(t), None) == mc.MC_EINVAL
+
+
+def test_finite_beam_validation():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, med, src, geo, det, run = _valid_args()
+    tal = _tally_stub(det)
+
+    def call():
+        return mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                                    C.byref(tal), None)
+    for radius in (-1.0, float("nan"), 5.5):           # negative, NaN, disk leaving the 10 mm face
+        src.beam_radius_mm = radius
+        assert call() == mc.MC_EINVAL
+    src.beam_radius_mm = 1.25
+    run.max_steps = 0xFFFFFFFF                           # the reserved step counter
+    assert call() == mc.MC_EINVAL and b"reserves" in mc.lib().mc_last_error()
+
+
+def test_metrics_work_size_and_validation():
+    import math
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    L = mc.lib()
+    rad = mc.Radial(64.0, 64.0, 64.0)
+    grid = max(1, min(256, math.ceil(128 * 128 / (256 * 16))))
+    assert L.mc_metrics_work_bytes(128, 128, C.byref(rad)) == 8 * (3 * grid + 7 * grid + 4 * 64 + mc.MC_METRICS_N)
+    assert L.mc_metrics_work_bytes(0, 128, C.byref(rad)) == 0
+    assert L.mc_metrics_work_bytes(128, 128, C.byref(mc.Radial(0, 0, 3000.0))) == 0
+    out = (C.c_double * mc.MC_METRICS_N)()
+    nb = L.mc_metrics_work_bytes(128, 128, C.byref(rad))
+    assert L.mc_image_metrics(None, 0x1000, None, 128, 128, C.byref(rad), None, 0x1000, nb, out, None) == mc.MC_EINVAL
+    assert L.mc_image_metrics(0x1000, 0x1000, None, 5000, 5000, C.byref(rad), None, 0x1000, nb, out, None) \
+        == mc.MC_EINVAL
+    assert L.mc_image_metrics(0x1000, 0x1000, None, 128, 128, C.byref(rad), None, 0x1000, nb - 8, out, None) \
+        == mc.MC_EINVAL
+    assert b"work" in L.mc_last_error()

@@ -94,6 +94,21 @@ HEAVY = Workload(name="heavy_poly_tau16_1e9", particle=Particle(sigma_ln=0.05, n
                  n_cdf=16384, side_px=1024, trans_px=1024, n_photons=1_000_000_000)
 
 
+# The paper's image comparison (Sec. 5.2): a 2.5 mm wide parallel beam (Sec.
+# 4.1, radius 1.25 mm) at the optical depths of Tables 3 and 4, 512 x 512
+# images of 1e8 photons per phase function; an independent Mie run (seed
+# 4321) stands in for the experimental reference image.
+ANALYSIS_ODS = (5.0, 7.5, 8.0, 10.0, 12.5)
+ANALYSIS_REF_SEED = 4321
+
+
+def analysis_workload(tau: float, phase: int = PHASE_MIE, seed: int = 1234,
+                      n_photons: int = 100_000_000) -> "Workload":
+    tag = "mie" if phase == PHASE_MIE else "hg"
+    return Workload(name=f"analysis_od{tau:g}_{tag}_s{seed}", tau=tau, n_cdf=16384, side_px=512,
+                    trans_px=512, n_photons=n_photons, phase=phase, seed=seed, beam_radius_mm=1.25)
+
+
 @dataclass(frozen=True)
 class BatchInstance:
     diameter_um: float
