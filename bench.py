@@ -78,8 +78,8 @@ PEAK_SLOTS_PER_S = 256 * 64 * 2.4e9
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters
 # read for a 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); valid
 # only for the kernel sources it was measured on (profiles/walk_tau4_counters.md).
-TRAFFIC = {"sources_sha256": "30ae587a4d24252b90ecb126b9cc21c638dab5575a47ddeba7bbc0e1b4d73053",
-           "fetch_kib": 326.5, "write_kib": 2103600.0, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"sources_sha256": "d65161baf14c695d2238539b09cb2b5b7e28a384ab0646929cc760cc0466e78c",
+           "fetch_kib": 337.0, "write_kib": 2105060.0, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 

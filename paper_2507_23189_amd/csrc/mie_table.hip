@@ -419,12 +419,16 @@ int result_buffer(mie_table_t *table, std::unique_lock<std::mutex> &lock, double
 // Orthonormal Hermite polynomial h_n(t) for the weight exp(-t^2), by the
 // three-term recurrence h_{j+1} = sqrt(2/(j+1)) t h_j - sqrt(j/(j+1)) h_{j-1}
 // from h_0 = pi^(-1/4), together with sum_{j<n} h_j(t)^2.
-void hermite_orthonormal(int n, double t, double *h_n, double *sum_sq)
+struct HermiteCoef {
+    double a[MC_MAX_BINS], b[MC_MAX_BINS];   // sqrt(2 / (j + 1)), sqrt(j / (j + 1))
+};
+
+void hermite_orthonormal(const HermiteCoef &c, int n, double t, double *h_n, double *sum_sq)
 {
     double h_prev = 0.0, h = std::pow(M_PI, -0.25), s = 0.0;
     for (int j = 0; j < n; ++j) {
         s += h * h;
-        const double h_next = std::sqrt(2.0 / (j + 1)) * t * h - std::sqrt((double)j / (j + 1)) * h_prev;
+        const double h_next = c.a[j] * t * h - c.b[j] * h_prev;
         h_prev = h;
         h = h_next;
     }
@@ -443,22 +447,29 @@ int gauss_hermite(int n, double *t, double *w)
         w[0] = std::sqrt(M_PI);
         return MC_OK;
     }
+    HermiteCoef c;
+    for (int j = 0; j < n; ++j) {
+        c.a[j] = std::sqrt(2.0 / (j + 1));
+        c.b[j] = std::sqrt((double)j / (j + 1));
+    }
+    // Grid step 2R / (40 n) < 0.04 for n <= 64, well below the smallest
+    // spacing of neighbouring roots (about pi / sqrt(2n + 1) > 0.27).
     const double R = std::sqrt(2.0 * n + 1.0) + 1.0;
-    const int steps = 400 * n;
+    const int steps = 40 * n;
     int found = 0;
     double t_prev = -R, h_prev, s;
-    hermite_orthonormal(n, t_prev, &h_prev, &s);
+    hermite_orthonormal(c, n, t_prev, &h_prev, &s);
     for (int i = 1; i <= steps && found < n; ++i) {
         const double ti = -R + 2.0 * R * (double)i / steps;
         double hi;
-        hermite_orthonormal(n, ti, &hi, &s);
+        hermite_orthonormal(c, n, ti, &hi, &s);
         if ((h_prev < 0.0) != (hi < 0.0) || hi == 0.0) {
             double lo = t_prev, up = ti, h_lo = h_prev;
             for (int it = 0; it < 200 && hi != 0.0; ++it) {
                 const double mid = 0.5 * (lo + up);
                 if (mid <= lo || mid >= up) break;
                 double hm;
-                hermite_orthonormal(n, mid, &hm, &s);
+                hermite_orthonormal(c, n, mid, &hm, &s);
                 if ((hm < 0.0) == (h_lo < 0.0)) {
                     lo = mid;
                     h_lo = hm;
@@ -468,12 +479,12 @@ int gauss_hermite(int n, double *t, double *w)
             }
             const double root = hi == 0.0 ? ti : 0.5 * (lo + up);
             double hr;
-            hermite_orthonormal(n, root, &hr, &s);
+            hermite_orthonormal(c, n, root, &hr, &s);
             t[found] = root;
             w[found] = 1.0 / s;
             ++found;
             // Step past an exact zero so it is not found twice.
-            hermite_orthonormal(n, ti, &hi, &s);
+            hermite_orthonormal(c, n, ti, &hi, &s);
             if (hi == 0.0) hi = -h_prev;
         }
         t_prev = ti;
