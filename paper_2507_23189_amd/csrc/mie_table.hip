@@ -24,7 +24,8 @@
 namespace mcmie {
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kThreads = 1024;     // workgroup size: angles and inverse-table entries spread over all of it
+constexpr int kBlock = 256;        // the CDF scan's partition: lanes 0..255 own kChunk angles each
 constexpr int kChunk = (MC_MAX_N_ANGLES + kBlock - 1) / kBlock;
 
 struct cplx {
@@ -156,7 +157,7 @@ __device__ void cdf_and_inverse(double *s_ang, double *s_part, double *s_total, 
         const double th_j = (double)j * dth, th_p = (double)(j - 1) * dth;
         local += 0.5 * (th_j - th_p) * (s_ang[j - 1] + s_ang[j]);
     }
-    s_part[tid] = local;
+    if (tid < kBlock) s_part[tid] = local;   // lanes past the partition own no angles
     __syncthreads();
     if (tid == 0) {   // exclusive scan of the per-lane sums (256 adds)
         double run = 0.0;
@@ -168,7 +169,7 @@ __device__ void cdf_and_inverse(double *s_ang, double *s_part, double *s_total, 
         *s_total = run;
     }
     __syncthreads();
-    {
+    if (tid < kBlock) {
         double acc = s_part[tid];
         const double total = *s_total;
         double prev = f_left;
@@ -184,8 +185,8 @@ __device__ void cdf_and_inverse(double *s_ang, double *s_part, double *s_total, 
     }
     __syncthreads();
     if (cdf_out)
-        for (int j = tid; j < na; j += kBlock) cdf_out[j] = s_ang[j];
-    for (int i = tid; i < nc; i += kBlock) {
+        for (int j = tid; j < na; j += kThreads) cdf_out[j] = s_ang[j];
+    for (int i = tid; i < nc; i += kThreads) {
         const double u = (double)i / (double)(nc - 1);
         int l = 0, r = na;                 // first j with F_j >= u
         while (l < r) {
@@ -205,7 +206,7 @@ __device__ void cdf_and_inverse(double *s_ang, double *s_part, double *s_total, 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void mie_table_kernel(MieArgs a)
+__global__ __launch_bounds__(kThreads) void mie_table_kernel(MieArgs a)
 {
     __shared__ cplx s_a[MC_MAX_TERMS];
     __shared__ cplx s_b[MC_MAX_TERMS];
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void mie_table_kernel(MieArgs a)
     __syncthreads();
 
     if (a.coef) {
-        for (int n = tid; n < N; n += kBlock) {
+        for (int n = tid; n < N; n += kThreads) {
             a.coef[4 * n + 0] = s_a[n].re;
             a.coef[4 * n + 1] = s_a[n].im;
             a.coef[4 * n + 2] = s_b[n].re;
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void mie_table_kernel(MieArgs a)
     const int na = a.n_angles;
     const double dth = M_PI / (double)(na - 1);
     const double pnorm = 2.0 / (x * x * s_qsca);
-    for (int j = tid; j < na; j += kBlock) {
+    for (int j = tid; j < na; j += kThreads) {
         const double th = (double)j * dth;
         const double P = pnorm * mie_intensity(th, N, s_a, s_b);
         if (a.phase) a.phase[j] = P;
@@ -270,7 +271,7 @@ struct PolyArgs {
     double *result;                // q_ext, q_sca (over geo_median), g, max N
 };
 
-__global__ __launch_bounds__(kBlock) void mie_bin_kernel(PolyArgs a)
+__global__ __launch_bounds__(kThreads) void mie_bin_kernel(PolyArgs a)
 {
     __shared__ cplx s_a[MC_MAX_TERMS];
     __shared__ cplx s_b[MC_MAX_TERMS];
@@ -291,11 +292,11 @@ __global__ __launch_bounds__(kBlock) void mie_bin_kernel(PolyArgs a)
     __syncthreads();
     const int na = a.n_angles;
     const double dth = M_PI / (double)(na - 1);
-    for (int j = tid; j < na; j += kBlock)
+    for (int j = tid; j < na; j += kThreads)
         a.rows[(uint64_t)k * na + j] = s_w * mie_intensity((double)j * dth, N, s_a, s_b);
 }
 
-__global__ __launch_bounds__(kBlock) void mie_mix_kernel(PolyArgs a)
+__global__ __launch_bounds__(kThreads) void mie_mix_kernel(PolyArgs a)
 {
     __shared__ double s_ang[MC_MAX_N_ANGLES];
     __shared__ double s_part[kBlock];
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void mie_mix_kernel(PolyArgs a)
     const int na = a.n_angles;
     const double dth = M_PI / (double)(na - 1);
     const double inv_sca = 1.0 / s_sca;
-    for (int j = tid; j < na; j += kBlock) {
+    for (int j = tid; j < na; j += kThreads) {
         double mix = 0.0;
         for (int k = 0; k < a.n_bins; ++k) mix += a.rows[(uint64_t)k * na + j];
         const double P = mix * inv_sca;
@@ -375,7 +376,7 @@ int prepare_table(const mie_spec_t *spec, const mie_table_t *table, MieArgs *arg
 int launch_table(MieArgs args, mie_table_t *table, hipStream_t st, double *result)
 {
     args.result = result;
-    hipLaunchKernelGGL(mie_table_kernel, dim3(1), dim3(kBlock), 0, st, args);
+    hipLaunchKernelGGL(mie_table_kernel, dim3(1), dim3(kThreads), 0, st, args);
     MC_HIP_CHECK(hipGetLastError());
     table->x = args.x;
     table->m_rel_re = args.m_re;
@@ -572,8 +573,8 @@ extern "C" int mie_table_build_poly(const mie_spec_t *spec, const mie_poly_t *po
     std::unique_lock<std::mutex> lock(g_scratch_mu, std::defer_lock);
     if (int rc = result_buffer(table, lock, &a.result, who)) return rc;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(mie_bin_kernel, dim3(q.n_bins), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(mie_mix_kernel, dim3(1), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(mie_bin_kernel, dim3(q.n_bins), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL(mie_mix_kernel, dim3(1), dim3(kThreads), 0, st, a);
     MC_HIP_CHECK(hipGetLastError());
     double res[4];
     MC_HIP_CHECK(hipMemcpyAsync(res, a.result, sizeof res, hipMemcpyDeviceToHost, st));

@@ -76,6 +76,7 @@ struct WalkArgs {
     uint32_t key0, key1, instance, max_steps;
     uint64_t n_photons, photon_offset;
     uint32_t chunk;
+    uint32_t refill_min;      // free lanes that trigger end-of-photon work and refill (1..64)
     uint32_t flags;
     int cache_bits;           // log2 of the tally-cache slots (0: no cache)
     uint32_t n_side;          // pixels of the side image (cache key offset of the transmitted image)
@@ -305,10 +306,99 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         acc_events = acc_steps = acc_refl = acc_photons = acc_ball = 0;
     };
 
+    // A lane whose photon has ended keeps its state until the end-of-photon
+    // work (tallies, records, the exit queue) and the refill run for several
+    // lanes at once: when at least refill_min lanes are free, or none is still
+    // walking.  Few lanes finish in any one step, so doing that work every
+    // step would run it with most lanes masked off.
+    bool pending = false;
+    int cause = 0, face = -1, axis = 0;
+
     for (;;) {
-        // ---- refill lanes whose photon has ended -------------------------
         const uint64_t need = __ballot(!alive);
-        if (need) {
+        if (need && ((uint32_t)__popcll(need) >= a.refill_min || __ballot(alive) == 0)) {
+            // ---- end-of-photon work of the waiting lanes ----------------------
+            if (pending) {
+                const uint32_t scal_at = BATCH ? l_slot * kBatchScal : 0u;
+                // Faces +x and +z are totalled from their images when finalizing.
+                if (cause == 0 && face != 1 && face != 5) atomicAdd(&s_scal[scal_at + MC_S_FACE + face], fix(w));
+                if (MOMENTS && cause == 0 && face == 1) {
+                    // Path moments of the side image (perturbation Monte Carlo):
+                    // first order per pixel, second order summed over the image
+                    // in the block's LDS (per pixel as well when asked for).
+                    const uint32_t key = (uint32_t)(pixel(py, a.size[1], a.side_ny) * a.side_nx +
+                                                    pixel(pz, a.size[2], a.side_nx));
+                    const double wd = (double)w, wk = wd * (double)k, wl = wd * (double)L;
+                    atomicAdd(a.side_wk + key, wk);
+                    atomicAdd(a.side_wl + key, wl);
+                    double *s_m2 = (double *)(s_scal + MC_S_SIDE_W2);
+                    atomicAdd(s_m2 + 0, wd * wd);
+                    atomicAdd(s_m2 + 1, wd * wk);
+                    atomicAdd(s_m2 + 2, wd * wl);
+                    if (a.side_w2k) {
+                        atomicAdd(a.side_w2k + key, wd * wk);
+                        atomicAdd(a.side_w2l + key, wd * wl);
+                    }
+                }
+                acc_abs += fix(A);
+                acc_events += k;
+                acc_steps += step;
+                ++acc_photons;
+                if (RECORD) {
+                    const uint64_t rel = id - a.photon_offset;
+                    if (rel % a.record_stride == 0 && rel / a.record_stride < a.rec_rows) {
+                        const uint64_t row = rel / a.record_stride, n = a.rec_rows;
+                        float ox = dx, oy = dy, oz = dz;
+                        if (cause == 0 && !a.matched) {
+                            // Refracted direction outside the wall (Snell).
+                            ox *= a.n12; oy *= a.n12; oz *= a.n12;
+                            const float t2 = (axis == 0 ? oy * oy + oz * oz
+                                                        : (axis == 1 ? ox * ox + oz * oz : ox * ox + oy * oy));
+                            const float on = copysignf(sqrtf(fmaxf(1.f - t2, 0.f)),
+                                                       axis == 0 ? dx : (axis == 1 ? dy : dz));
+                            if (axis == 0) ox = on; else if (axis == 1) oy = on; else oz = on;
+                        }
+                        a.rec_i[MC_REC_I_FACE * n + row] = face;
+                        a.rec_i[MC_REC_I_CAUSE * n + row] = cause;
+                        a.rec_i[MC_REC_I_K * n + row] = (int32_t)k;
+                        a.rec_i[MC_REC_I_STEPS * n + row] = (int32_t)step;
+                        a.rec_f[(MC_REC_F_POS + 0) * n + row] = px;
+                        a.rec_f[(MC_REC_F_POS + 1) * n + row] = py;
+                        a.rec_f[(MC_REC_F_POS + 2) * n + row] = pz;
+                        a.rec_f[(MC_REC_F_DIR + 0) * n + row] = ox;
+                        a.rec_f[(MC_REC_F_DIR + 1) * n + row] = oy;
+                        a.rec_f[(MC_REC_F_DIR + 2) * n + row] = oz;
+                        a.rec_f[MC_REC_F_W * n + row] = w;
+                        a.rec_f[MC_REC_F_L * n + row] = L;
+                        a.rec_f[MC_REC_F_A * n + row] = A;
+                    }
+                }
+            }
+            // ---- queue exits through the imaged faces (+x side, +z transmitted) ----
+            const bool ballistic = pending && cause == 0 && k == 0 && step == 1 && face == beam_face;
+            acc_ball += ballistic ? 1u : 0u;
+            const bool to_img = pending && cause == 0 && (face == 1 || face == 5) && !ballistic;
+            const uint64_t m = __ballot(to_img);
+            if (m) {
+                const uint32_t n_push = __popcll(m);
+                if (q_n + n_push > (uint32_t)kQueue) {
+                    flush(q_n);
+                    q_n = 0;
+                }
+                if (to_img) {
+                    const uint32_t at = q_n + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    q_y[at] = py;
+                    q_b[at] = face == 1 ? pz : px;
+                    q_w[at] = __uint_as_float(__float_as_uint(w) | (face == 1 ? 0x80000000u : 0u));
+                    if (BATCH) q_s[at] = __uint_as_float(l_slot);
+                }
+                q_n += n_push;
+            }
+
+            pending = false;
+
+            // ---- refill free lanes ---------------------------------------------
             if (q_rem == 0 && !exhausted) {
                 // Single medium: claim the next `chunk` photon ids.  Batched:
                 // claim the next work unit, `chunk` photons of one medium.
@@ -377,9 +467,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         if (__ballot(alive) == 0) break;
 
         bool ended = false;
-        int cause = 0, face = -1, axis = 0;
         const uint32_t scal_at = BATCH ? l_slot * kBatchScal : 0u;   // the medium's LDS scalars
         if (alive) {
+            cause = 0;
+            face = -1;
             // ---- one step ---------------------------------------------------
             // The round keys derive from the seed inside the loop (scalar adds)
             // rather than living in 20 scalar registers across it.
@@ -479,83 +570,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 atomicAdd(&s_scal[scal_at + MC_S_CAPPED], 1ull);
             }
             if (ended) {
-                // Faces +x and +z are totalled from their images when finalizing.
-                if (cause == 0 && face != 1 && face != 5) atomicAdd(&s_scal[scal_at + MC_S_FACE + face], fix(w));
-                if (MOMENTS && cause == 0 && face == 1) {
-                    // Path moments of the side image (perturbation Monte Carlo):
-                    // first order per pixel, second order summed over the image
-                    // in the block's LDS (per pixel as well when asked for).
-                    const uint32_t key = (uint32_t)(pixel(py, a.size[1], a.side_ny) * a.side_nx +
-                                                    pixel(pz, a.size[2], a.side_nx));
-                    const double wd = (double)w, wk = wd * (double)k, wl = wd * (double)L;
-                    atomicAdd(a.side_wk + key, wk);
-                    atomicAdd(a.side_wl + key, wl);
-                    double *s_m2 = (double *)(s_scal + MC_S_SIDE_W2);
-                    atomicAdd(s_m2 + 0, wd * wd);
-                    atomicAdd(s_m2 + 1, wd * wk);
-                    atomicAdd(s_m2 + 2, wd * wl);
-                    if (a.side_w2k) {
-                        atomicAdd(a.side_w2k + key, wd * wk);
-                        atomicAdd(a.side_w2l + key, wd * wl);
-                    }
-                }
-                acc_abs += fix(A);
-                acc_events += k;
-                acc_steps += step;
-                ++acc_photons;
-                if (RECORD) {
-                    const uint64_t rel = id - a.photon_offset;
-                    if (rel % a.record_stride == 0 && rel / a.record_stride < a.rec_rows) {
-                        const uint64_t row = rel / a.record_stride, n = a.rec_rows;
-                        float ox = dx, oy = dy, oz = dz;
-                        if (cause == 0 && !a.matched) {
-                            // Refracted direction outside the wall (Snell).
-                            ox *= a.n12; oy *= a.n12; oz *= a.n12;
-                            const float t2 = (axis == 0 ? oy * oy + oz * oz
-                                                        : (axis == 1 ? ox * ox + oz * oz : ox * ox + oy * oy));
-                            const float on = copysignf(sqrtf(fmaxf(1.f - t2, 0.f)),
-                                                       axis == 0 ? dx : (axis == 1 ? dy : dz));
-                            if (axis == 0) ox = on; else if (axis == 1) oy = on; else oz = on;
-                        }
-                        a.rec_i[MC_REC_I_FACE * n + row] = face;
-                        a.rec_i[MC_REC_I_CAUSE * n + row] = cause;
-                        a.rec_i[MC_REC_I_K * n + row] = (int32_t)k;
-                        a.rec_i[MC_REC_I_STEPS * n + row] = (int32_t)step;
-                        a.rec_f[(MC_REC_F_POS + 0) * n + row] = px;
-                        a.rec_f[(MC_REC_F_POS + 1) * n + row] = py;
-                        a.rec_f[(MC_REC_F_POS + 2) * n + row] = pz;
-                        a.rec_f[(MC_REC_F_DIR + 0) * n + row] = ox;
-                        a.rec_f[(MC_REC_F_DIR + 1) * n + row] = oy;
-                        a.rec_f[(MC_REC_F_DIR + 2) * n + row] = oz;
-                        a.rec_f[MC_REC_F_W * n + row] = w;
-                        a.rec_f[MC_REC_F_L * n + row] = L;
-                        a.rec_f[MC_REC_F_A * n + row] = A;
-                    }
-                }
+                pending = true;
                 alive = false;
             }
-        }
-
-        // ---- queue exits through the imaged faces (+x side, +z transmitted) ----
-        const bool ballistic = ended && cause == 0 && k == 0 && step == 1 && face == beam_face;
-        acc_ball += ballistic ? 1u : 0u;
-        const bool to_img = ended && cause == 0 && (face == 1 || face == 5) && !ballistic;
-        const uint64_t m = __ballot(to_img);
-        if (m) {
-            const uint32_t n_push = __popcll(m);
-            if (q_n + n_push > (uint32_t)kQueue) {
-                flush(q_n);
-                q_n = 0;
-            }
-            if (to_img) {
-                const uint32_t at = q_n + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                q_y[at] = py;
-                q_b[at] = face == 1 ? pz : px;
-                q_w[at] = __uint_as_float(__float_as_uint(w) | (face == 1 ? 0x80000000u : 0u));
-                if (BATCH) q_s[at] = __uint_as_float(l_slot);
-            }
-            q_n += n_push;
         }
     }
     flush(q_n);
@@ -903,6 +920,7 @@ void fill_medium(float &neg_ln2_over_mu, float &albedo, float &absorb, double ta
 // whose arguments carry up to kInstPerCopy media each (no host buffer has to
 // outlive the call).
 constexpr int kInstPerCopy = 32;
+constexpr uint32_t kRefillMin = 16;        // free lanes of a wave that trigger end-of-photon work
 struct InstChunk {
     BatchInst v[kInstPerCopy];
     uint32_t n, first;
@@ -953,6 +971,7 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
         chunk = std::max<uint64_t>(64, std::min<uint64_t>(1024, (chunk + 63) / 64 * 64));
     }
     a.chunk = (uint32_t)chunk;
+    a.refill_min = kRefillMin;
 
     const int zero_all = (det.flags & MC_ACCUMULATE) ? 0 : 1;
     const bool sig = (det.flags & MC_SIGMA) != 0, rec = (det.flags & MC_RECORD) != 0;
