@@ -59,6 +59,13 @@ extern "C" {
 #define MC_MOMENTS_PIXEL2 32u /* with MC_MOMENTS: also per pixel sum(w^2 k) and sum(w^2 L)
                                  (side_w2k, side_w2l), for losses whose second derivative
                                  varies from pixel to pixel */
+#define MC_EXIT_LOG 64u       /* gather image exits in a log in the workspace and sum them in a
+                                 second pass instead of adding each to the images as it happens;
+                                 the results are identical bit for bit.  The log fills the
+                                 workspace beyond mc_workspace_bytes (size it with
+                                 mc_workspace_bytes_log); exits that find their part of it full
+                                 are added directly, so any size is correct.  Not with
+                                 MC_RECORD or MC_MOMENTS, nor in batched launches. */
 
 /* Scalar tallies: mc_tally_t.scalars holds MC_N_SCALARS doubles. */
 #define MC_S_FACE 0           /* 0..5: weight leaving faces -x, +x, -y, +y, -z, +z */
@@ -265,6 +272,18 @@ typedef struct {
  * MC_SIGMA) plus scalar accumulators.  0 for a NULL or invalid detector.
  */
 uint64_t mc_workspace_bytes(const mc_detector_t *detector);
+
+/*
+ * Bytes of workspace for a walk of n_photons photons with MC_EXIT_LOG set in
+ * detector->flags: mc_workspace_bytes plus a log in which each wave of a full
+ * launch owns the same number of chunks (64 entries of 8 bytes and a fill
+ * byte) in each of 64 key ranges: 1.5 chunks per 64 of the wave's share of
+ * photons in a range, plus one (about 12 bytes per photon plus 269 MB).
+ * Exits spread over the images normally never find that full.  0 for a NULL
+ * or invalid detector, or one without MC_EXIT_LOG.  The log is scratch: walks
+ * run one after another on one stream may share a workspace.
+ */
+uint64_t mc_workspace_bytes_log(const mc_detector_t *detector, uint64_t n_photons);
 
 /*
  * Run the photon walk of Sec. 3.1.3 for run->n_photons photons: start at the

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libmcmie.so")
 MC_OK, MC_EINVAL, MC_EDEVICE, MC_ENOMEM, MC_EUNSUPPORTED = 0, -1, -2, -3, -4
 MC_PHASE_MIE, MC_PHASE_HG = 0, 1
 MC_ACCUMULATE, MC_SIGMA, MC_RECORD, MC_FIX64, MC_MOMENTS, MC_MOMENTS_PIXEL2 = 1, 2, 4, 8, 16, 32
+MC_EXIT_LOG = 64
 MC_N_SCALARS = 20
 MC_S_FACE, MC_S_ABSORBED, MC_S_ROULETTE_NET, MC_S_CAPPED_W, MC_S_EVENTS = 0, 6, 7, 8, 9
 MC_S_PHOTONS, MC_S_ROULETTE_KILLS, MC_S_CAPPED, MC_S_REFLECTIONS, MC_S_STEPS, MC_S_RESERVED = 10, 11, 12, 13, 14, 15
@@ -134,6 +135,8 @@ def lib():
         L.mc_workspace_bytes.restype = C.c_uint64
         L.mc_workspace_bytes_batch.argtypes = [C.POINTER(Detector), C.c_uint32]
         L.mc_workspace_bytes_batch.restype = C.c_uint64
+        L.mc_workspace_bytes_log.argtypes = [C.POINTER(Detector), C.c_uint64]
+        L.mc_workspace_bytes_log.restype = C.c_uint64
         _batch_args = [C.POINTER(BatchItem), C.c_uint32, C.c_int32, C.POINTER(Source), C.POINTER(Geometry),
                        C.POINTER(Detector), C.POINTER(Run), C.POINTER(_TallyC)]
         L.mc_simulate_batch.argtypes = _batch_args + [C.c_void_p]
@@ -252,6 +255,10 @@ def mc_workspace_bytes(det: Detector) -> int:
     return int(lib().mc_workspace_bytes(C.byref(det)))
 
 
+def mc_workspace_bytes_log(det: Detector, n_photons: int) -> int:
+    return int(lib().mc_workspace_bytes_log(C.byref(det), int(n_photons)))
+
+
 def mc_workspace_bytes_batch(det: Detector, n_items: int) -> int:
     return int(lib().mc_workspace_bytes_batch(C.byref(det), int(n_items)))
 
@@ -275,16 +282,26 @@ class Tally:
 
     @staticmethod
     def alloc(det: Detector, device="cuda", *, sigma=False, record_rows=0, fix64=False,
-              moments=False, pixel2=False) -> "Tally":
+              moments=False, pixel2=False, log_photons=None, workspace=None) -> "Tally":
+        """With det.flags & MC_EXIT_LOG, the workspace also holds an exit log
+        sized for log_photons photons.  `workspace` (an int64 device tensor
+        from a previous alloc) is shared instead of allocating one: walks
+        enqueued one after another on one stream may share it."""
         import torch
         dev = torch.device(device)
         img = dict(dtype=torch.int64 if fix64 else torch.float64, device=dev)
         probe = Detector(det.side_nx, det.side_ny, det.trans_nx, det.trans_ny,
                          det.flags | (MC_SIGMA if sigma else 0))
-        ws_bytes = mc_workspace_bytes(probe)
+        if det.flags & MC_EXIT_LOG:
+            ws_bytes = mc_workspace_bytes_log(probe, int(log_photons or 0))
+        else:
+            ws_bytes = mc_workspace_bytes(probe)
+        if workspace is None:
+            workspace = torch.empty((ws_bytes + 7) // 8, dtype=torch.int64, device=dev)
+        elif workspace.dtype != torch.int64 or workspace.numel() * 8 < ws_bytes:
+            raise ValueError(f"shared workspace must be int64 with at least {ws_bytes} bytes")
         t = Tally(torch.empty((det.side_ny, det.side_nx), **img), torch.empty((det.trans_ny, det.trans_nx), **img),
-                  torch.empty(MC_N_SCALARS, dtype=torch.float64, device=dev),
-                  torch.empty((ws_bytes + 7) // 8, dtype=torch.int64, device=dev))
+                  torch.empty(MC_N_SCALARS, dtype=torch.float64, device=dev), workspace)
         if sigma:
             t.side_w2 = torch.empty_like(t.side)
             t.trans_w2 = torch.empty_like(t.trans)

@@ -39,4 +39,4 @@ int device_cu_count(int *out)
 
 extern "C" const char *mc_last_error(void) { return mcmie::g_msg; }
 
-extern "C" int mc_version(void) { return 300; }   // 0.3.0
+extern "C" int mc_version(void) { return 400; }   // 0.4.0

@@ -90,6 +90,12 @@ struct WalkArgs {
     double *side_wk, *side_wl;     // MC_MOMENTS: per side pixel, sum w k and sum w L
     double *side_w2k, *side_w2l;   // MC_MOMENTS_PIXEL2: per side pixel, sum w^2 k and sum w^2 L
     uint64_t rec_rows, record_stride;
+    // Exit log (kOptLog): the fill of every chunk (bytes, zeroed first) and
+    // the entries; chunk (range, wave, j) is (range * waves + wave) * log_chunks + j.
+    unsigned long long *log;
+    uint8_t *log_fill;
+    uint32_t log_chunks, log_bits;   // log_bits: scrambled group index width, >= 6
+    uint32_t log_waves;              // waves in the launch
     // Batched launch: media in schedule order, work units over all of them.
     const BatchInst *insts;
     uint32_t n_inst;          // media (slots) in the launch
@@ -157,36 +163,68 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 constexpr int kQueue = 64;                 // queued image exits per wave
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;   // free tally-cache slot
 
-constexpr int kOptSigma = 1, kOptRecord = 2, kOptMoments = 4, kOptBatch = 8;
+constexpr int kOptSigma = 1, kOptRecord = 2, kOptMoments = 4, kOptBatch = 8, kOptLog = 16;
+// Exit log: image exits appended as (key << 32 | weight bits) to chunks of
+// kLogChunk entries.  Keys fall into kLogBuckets ranges; in each range's
+// region every wave of the launch owns log_chunks chunks, which it fills in
+// turn (no claim, no global atomic).  Keys go to ranges by groups of eight (one 64-byte line of a tally
+// copy): the group g is scrambled by p = g * kLogHashMul mod 2^bits (odd
+// multiplier, so a bijection), its top six bits pick the range and the rest,
+// with the key's place in its group, index the key within the range.  Bright
+// spots of an image thus spread evenly over the ranges.
+constexpr uint32_t kLogChunk = 64;
+constexpr uint32_t kLogBuckets = 64;
+constexpr uint32_t kLogMaxChunks = 255;    // chunks per wave and range (an 8-bit cursor field)
+constexpr uint32_t kLogHistBits = 13;      // keys per binning block: 2^13 (64 KB of int64 sums)
+constexpr uint32_t kLogHashMul = 0x9E3779B1u;
+__device__ __forceinline__ uint32_t log_scramble(uint32_t key, uint32_t bits)
+{
+    return ((key >> 3) * kLogHashMul) & ((1u << bits) - 1u);
+}
+__device__ __forceinline__ uint32_t log_bucket(uint32_t key, uint32_t bits) { return log_scramble(key, bits) >> (bits - 6); }
+__device__ __forceinline__ uint32_t log_index(uint32_t key, uint32_t bits)
+{
+    return ((log_scramble(key, bits) & ((1u << (bits - 6)) - 1u)) << 3) | (key & 7u);
+}
 constexpr int kBatchScal = 16;             // LDS scalar words per medium in a batched launch
 constexpr uint64_t kWsScalarWords = 32;    // workspace scalar words per medium
 constexpr int kLdsBallistic = 15;          // LDS scalar word (per medium) counting first-step exits
 constexpr int kWsBallistic = 19;           // workspace word (per medium) of that count
 constexpr int kWsBeamKey = 20;             // workspace word (first medium): beam exit key + 1, or 0
+constexpr int kWsLogFallback = 21;         // workspace word: exits added directly because the log was full
 
 template <int PHASE, int OPT>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void walk_kernel(WalkArgs a)
 {
     constexpr bool SIGMA = OPT & kOptSigma, RECORD = OPT & kOptRecord, MOMENTS = OPT & kOptMoments;
-    constexpr bool BATCH = OPT & kOptBatch;
+    constexpr bool BATCH = OPT & kOptBatch, LOG = OPT & kOptLog;
+    constexpr bool GLOBAL_TABLE = BATCH;   // batched: each medium's inverse table stays in global memory
     // LDS layout: inverse table (n_cdf floats, padded to 4; batched launches
     // read each medium's table from global memory instead), scalar words
     // (MC_N_SCALARS, or kBatchScal per medium), tally cache (slots words of
     // weight, [SIGMA] slots words of squared weight, slots uint32 keys),
-    // per-wave exit queues (3 x kQueue floats, a fourth for the medium's slot).
+    // per-wave exit queues (3 x kQueue floats, a fourth for the medium's slot),
+    // with the exit log then 64 16-bit log cursors per wave.
     // (The kernel declares no static LDS: the dynamic array starts at offset 0,
     // and its 16-byte alignment keeps the 64-bit words below aligned.)
     extern __shared__ __attribute__((aligned(16))) float s_table[];
     constexpr int kQueueArrays = BATCH ? 4 : 3;
-    unsigned long long *s_scal = (unsigned long long *)(s_table + (BATCH ? 0 : ((a.n_cdf + 3) & ~3)));
+    unsigned long long *s_scal = (unsigned long long *)(s_table + (GLOBAL_TABLE ? 0 : ((a.n_cdf + 3) & ~3)));
     const int n_scal = BATCH ? (int)a.n_inst * kBatchScal : MC_N_SCALARS;
     const int slots = a.cache_bits ? 1 << a.cache_bits : 0;
     unsigned long long *s_cw = s_scal + n_scal;
     unsigned long long *s_cw2 = s_cw + (SIGMA ? slots : 0);
     uint32_t *s_key = (uint32_t *)(s_cw2 + slots);
     float *s_queue = (float *)(s_key + slots);
+    // Exit log cursor of each wave and key range, 16 bits (two ranges per
+    // word): open chunk j (of the wave's log_chunks in the range) << 8 |
+    // entries taken (at most 64 between flushes).  j = log_chunks: the wave
+    // has filled all its chunks of the range.
+    uint32_t *s_cur = (uint32_t *)(s_queue + (blockDim.x >> 6) * (kQueueArrays * kQueue));
+    if (LOG)
+        for (int i = threadIdx.x; i < (int)(blockDim.x >> 6) * (int)(kLogBuckets / 2); i += blockDim.x) s_cur[i] = 0u;
 
-    if (PHASE == MC_PHASE_MIE && !BATCH)
+    if (PHASE == MC_PHASE_MIE && !GLOBAL_TABLE)
         for (int i = threadIdx.x; i < a.n_cdf; i += blockDim.x) s_table[i] = a.inv_cdf[i];
     for (int i = threadIdx.x; i < n_scal; i += blockDim.x) s_scal[i] = 0ull;
     for (int i = threadIdx.x; i < slots; i += blockDim.x) {
@@ -220,6 +258,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         }
         beam_face = face;
     }
+    // Every wave reads the whole table and adds into the scalars, cache and
+    // log cursors set up above by the block's threads together.
+    __syncthreads();
 
     const int lane = __lane_id();
     const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) % kCopies;   // hwreg(HW_REG_XCC_ID, 0, 4)
@@ -233,21 +274,69 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 
     // Tally the first n queued exits, one per lane: pixel key, then the LDS
     // cache (claim or hit, up to four linear probes) or, when every probed
-    // slot holds another pixel, a global atomic.
+    // slot holds another pixel, a global atomic.  With the exit log the exits
+    // are appended to the log instead; a global atomic is then the fallback
+    // for a range whose region of the log is full.
+    uint32_t *my_cur = s_cur + (threadIdx.x >> 6) * (kLogBuckets / 2);
+    const uint32_t wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     auto flush = [&](uint32_t n) {
         __builtin_amdgcn_wave_barrier();
-        if ((uint32_t)lane < n) {
+        const bool act = (uint32_t)lane < n;
+        uint32_t key = 0;
+        float wf = 0.f;
+        unsigned long long wq = 0ull, wq2 = 0ull;
+        if (act) {
             const float y = q_y[lane], b = q_b[lane];
             const uint32_t wb = __float_as_uint(q_w[lane]);
             const bool side = wb >> 31;
-            const float wf = __uint_as_float(wb & 0x7FFFFFFFu);
-            const unsigned long long wq = fix(wf), wq2 = SIGMA ? fix(wf * wf) : 0ull;
+            wf = __uint_as_float(wb & 0x7FFFFFFFu);
             const uint32_t key_base = BATCH ? __float_as_uint(q_s[lane]) * a.n_pix_inst : 0u;
-            const uint32_t key =
-                key_base +
-                (side ? (uint32_t)(pixel(y, a.size[1], a.side_ny) * a.side_nx + pixel(b, a.size[2], a.side_nx))
-                      : a.n_side + (uint32_t)(pixel(y, a.size[1], a.trans_ny) * a.trans_nx +
-                                              pixel(b, a.size[0], a.trans_nx)));
+            key = key_base +
+                  (side ? (uint32_t)(pixel(y, a.size[1], a.side_ny) * a.side_nx + pixel(b, a.size[2], a.side_nx))
+                        : a.n_side + (uint32_t)(pixel(y, a.size[1], a.trans_ny) * a.trans_nx +
+                                                pixel(b, a.size[0], a.trans_nx)));
+        }
+        if (act) {
+            wq = fix(wf);
+            wq2 = SIGMA ? fix(wf * wf) : 0ull;
+        }
+        if (LOG) {
+            // Append to the wave's open chunk of the key's range: the LDS
+            // add hands out positions; those past the chunk's end (at most 64
+            // of them) continue in the wave's next chunk, and the lane that
+            // got position 64 records the full chunk and moves the cursor on
+            // by one chunk.  Past the wave's last chunk, exits are added
+            // directly.
+            const uint32_t bucket = log_bucket(key, a.log_bits);
+            const uint32_t sh = (bucket & 1u) * 16u;
+            uint32_t *word = &my_cur[bucket >> 1];
+            const uint32_t first = (bucket * a.log_waves + wave_id) * a.log_chunks;   // the wave's chunk 0
+            bool direct = false;
+            if (act) {
+                const uint32_t cur = (atomicAdd(word, 1u << sh) >> sh) & 0xFFFFu;
+                const uint32_t j = cur >> 8, f = cur & 0xFFu;   // f < 128
+                const uint32_t to = j + (f >> 6);
+                if (to < a.log_chunks)
+                    a.log[((uint64_t)(first + to) << 6) | (f & 63u)] =
+                        ((unsigned long long)key << 32) | __float_as_uint(wf);
+                else
+                    direct = true;
+                if (f == kLogChunk) {
+                    if (j < a.log_chunks) {
+                        a.log_fill[first + j] = (uint8_t)kLogChunk;
+                        atomicAdd(word, (256u - kLogChunk) << sh);   // j + 1, f - 64
+                    } else {
+                        atomicSub(word, kLogChunk << sh);            // stays past the last chunk
+                    }
+                }
+            }
+            if (direct) {
+                atomicAdd(my_img + key, wq);
+                if (SIGMA) atomicAdd(my_img2 + key, wq2);
+            }
+            const uint64_t took = __ballot(direct);
+            if (took && lane == 0) atomicAdd(a.ws_scal + kWsLogFallback, (unsigned long long)__popcll(took));
+        } else if (act) {
             bool cached = false;
             if (slots) {
                 uint32_t slot = (key * 2654435761u) >> (32 - a.cache_bits);
@@ -539,7 +628,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                         const float tt = u1 * tab_scale;
                         const int i = min((int)tt, tab_last);
                         const float f = tt - (float)i;
-                        const float t0 = BATCH ? l_tab[i] : s_table[i], t1 = BATCH ? l_tab[i + 1] : s_table[i + 1];
+                        const float t0 = GLOBAL_TABLE ? l_tab[i] : s_table[i];
+                        const float t1 = GLOBAL_TABLE ? l_tab[i + 1] : s_table[i + 1];
                         v = fmaf(f, t1 - t0, t0);
                     } else {
                         const float D = fmaf(-a.hg_b, u1, a.hg_a);
@@ -576,6 +666,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         }
     }
     flush(q_n);
+    if (LOG) {
+        // Close the wave's open chunks: lane i records the fill of range i's.
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t cur = (my_cur[lane >> 1] >> ((lane & 1) * 16)) & 0xFFFFu;
+        if ((cur >> 8) < a.log_chunks)
+            a.log_fill[(lane * a.log_waves + wave_id) * a.log_chunks + (cur >> 8)] = (uint8_t)(cur & 0xFFu);
+    }
 
     // ---- block-level flush of the scalar tallies and the cache ---------------
     if (BATCH) {
@@ -651,6 +748,83 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
     for (size_t i = t0; i < n_scalars; i += stride) scalars[i] = 0.0;
     for (size_t i = t0; i < (size_t)MC_REC_I_N * n_rec; i += stride) rec_i[i] = (i / n_rec == MC_REC_I_FACE) ? -1 : 0;
     for (size_t i = t0; i < (size_t)MC_REC_F_N * n_rec; i += stride) rec_f[i] = 0.f;
+}
+
+// Sum the exit log into the per-XCD image copies.  Block (range b, part p,
+// copy s) takes the s-th eighth of range b's chunks (empty ones have fill 0),
+// adds the fixed-point
+// weights (and squared weights) of the entries whose index within the range
+// lies in part p into an LDS histogram of 2^kLogHistBits sums, then adds the
+// non-zero sums into copy s.  Those keys of copy s have no other writer (the
+// walk's fallback atomics have completed), so plain loads and stores do.
+// The sums are of the same fix() values the walk would have added, so the
+// images equal those of the atomic path bit for bit.
+template <bool SIGMA>
+__global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, const uint8_t *fill,
+                                                uint64_t per_range_chunks, unsigned long long *copies,
+                                                unsigned long long *copies2, uint64_t n_total, uint32_t parts,
+                                                uint32_t bits, uint32_t inv_mul)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned long long s_hist[];
+    constexpr uint32_t H = 1u << kLogHistBits;
+    unsigned long long *s_hist2 = s_hist + H;
+    const uint32_t s = blockIdx.x % kCopies, rest = blockIdx.x / kCopies;
+    const uint32_t part = rest % parts, b = rest / parts;
+    for (uint32_t i = threadIdx.x; i < H; i += blockDim.x) {
+        s_hist[i] = 0ull;
+        if (SIGMA) s_hist2[i] = 0ull;
+    }
+    __syncthreads();
+    const uint64_t c0 = per_range_chunks * s / kCopies, c1 = per_range_chunks * (s + 1) / kCopies;
+    const uint64_t region = (uint64_t)b * per_range_chunks;
+    const uint32_t lane = threadIdx.x & 63u, waves = blockDim.x >> 6;
+    constexpr uint32_t U = 4;   // chunks in flight per wave
+    // Each wave reads the fills of 64 chunks at once, then the entries of
+    // the non-empty ones, U chunks at a time.
+    for (uint64_t g = c0 + (uint64_t)(threadIdx.x >> 6) * 64; g < c1; g += (uint64_t)waves * 64) {
+        const uint32_t my_fill = g + lane < c1 ? fill[region + g + lane] : 0u;
+        uint64_t left = __ballot(my_fill != 0u);
+        while (left) {
+            uint32_t at[U], f[U];
+            unsigned long long e[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                at[u] = left ? (uint32_t)__builtin_ctzll(left) : 0u;
+                f[u] = left ? __builtin_amdgcn_readlane(my_fill, at[u]) : 0u;
+                left &= left - 1;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                e[u] = lane < f[u] ? log[(region + g + at[u]) * kLogChunk + lane] : 0ull;
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                if (lane >= f[u]) continue;
+                const uint32_t h = log_index((uint32_t)(e[u] >> 32), bits);
+                if ((h >> kLogHistBits) != part) continue;
+                const float wf = __uint_as_float((uint32_t)e[u]);
+                atomicAdd(&s_hist[h & (H - 1)], fix(wf));
+                if (SIGMA) atomicAdd(&s_hist2[h & (H - 1)], fix(wf * wf));
+            }
+        }
+    }
+    __syncthreads();
+    unsigned long long *dst = copies + (uint64_t)s * n_total;
+    unsigned long long *dst2 = SIGMA ? copies2 + (uint64_t)s * n_total : nullptr;
+    const uint32_t per_range = 1u << (bits - 3);
+    for (uint32_t i = threadIdx.x; i < H; i += blockDim.x) {
+        const uint32_t h = part * H + i;
+        if (h >= per_range) break;
+        // Undo the scramble: p = range bits | group bits, g = p / kLogHashMul mod 2^bits.
+        const uint32_t p = (b << (bits - 6)) | (h >> 3);
+        const uint64_t key = ((uint64_t)((p * inv_mul) & ((1u << bits) - 1u)) << 3) | (h & 7u);
+        if (key >= n_total) continue;
+        const unsigned long long v = s_hist[i];
+        if (v) dst[key] += v;
+        if (SIGMA) {
+            const unsigned long long v2 = s_hist2[i];
+            if (v2) dst2[key] += v2;
+        }
+    }
 }
 
 // Sum the per-XCD fixed-point copies of every pixel (integer adds, so the
@@ -794,6 +968,19 @@ uint64_t workspace_words(const mc_detector_t &d, uint64_t n_inst = 1)
 {
     const uint64_t n_pix = (uint64_t)d.side_nx * d.side_ny + (uint64_t)d.trans_nx * d.trans_ny;
     return kWsScalarWords * n_inst + (uint64_t)kCopies * n_pix * n_inst * ((d.flags & MC_SIGMA) ? 2 : 1);
+}
+
+// The exit log (MC_EXIT_LOG) follows the workspace words: the fill bytes of
+// kLogBuckets x waves x K chunks (padded to 8 bytes), then their entries,
+// with K the largest count the caller's workspace holds.
+constexpr uint64_t kLogBytesPerChunk = kLogChunk * 8 + 1;
+constexpr uint64_t kLogSizingWaves = 256 * 32;   // resident waves of a full MI355X launch
+uint32_t log_chunks_for(uint64_t extra_bytes, uint64_t waves)
+{
+    if (extra_bytes < 8 || waves == 0) return 0;
+    const uint64_t k = (extra_bytes - 8) / (kLogBuckets * waves * kLogBytesPerChunk);
+    // Chunk indices are 32-bit in the kernel.
+    return (uint32_t)std::min<uint64_t>({k, (uint64_t)kLogMaxChunks, 0xFFFFFFFFull / (kLogBuckets * waves)});
 }
 
 uint64_t batch_workspace_words(const mc_detector_t &d, uint64_t n_items)
@@ -948,17 +1135,23 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     a.n_pix = n_total;
     a.n_inst = n_inst;
 
+    const bool use_log = (det.flags & MC_EXIT_LOG) != 0;
+    const uint64_t ws_words = batch ? workspace_words(det, n_inst) : workspace_words(det);
+
     // ---- launch shape: 1024-lane blocks, two per CU (32 waves), each with
     // the table (single medium), the scalar words, the per-wave exit queues and
-    // as large a tally cache as fits in half the CU's 160 KB LDS ----
+    // as large a tally cache as fits in half the CU's 160 KB LDS (with the exit
+    // log: the log cursors and no cache) ----
     const int block = rn.block_size ? rn.block_size : 1024;
     const size_t table_bytes = batch ? 0 : (size_t)((a.n_cdf + 3) & ~3) * sizeof(float);
     const size_t scal_bytes = (batch ? (size_t)n_inst * kBatchScal : MC_N_SCALARS) * sizeof(double);
-    const size_t lds_fixed = table_bytes + scal_bytes + (size_t)(block / 64) * (batch ? 4 : 3) * kQueue * sizeof(float);
+    const size_t queue_arrays = batch ? 4 : 3;
+    const size_t lds_fixed = table_bytes + scal_bytes + (size_t)(block / 64) * queue_arrays * kQueue * sizeof(float) +
+                             (use_log ? (size_t)(block / 64) * (kLogBuckets / 2) * sizeof(uint32_t) : 0);
     const size_t slot_bytes = sizeof(uint32_t) + sizeof(double) * ((det.flags & MC_SIGMA) ? 2 : 1);
     const size_t lds_half_cu = 80 * 1024;
     a.cache_bits = 0;
-    for (int b = 10; b >= 4; --b)
+    for (int b = 10; b >= 4 && !use_log; --b)
         if (lds_fixed + (slot_bytes << b) <= lds_half_cu) { a.cache_bits = b; break; }
     const size_t lds = lds_fixed + (a.cache_bits ? (slot_bytes << a.cache_bits) : 0);
     if (lds > 160 * 1024) return fail(MC_EINVAL, "mc_simulate: %zu bytes of LDS per block do not fit a CU", lds);
@@ -973,10 +1166,24 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     a.chunk = (uint32_t)chunk;
     a.refill_min = kRefillMin;
 
+    // ---- exit log: K chunks per wave and range in what the caller gave
+    // beyond the workspace words; the fill bytes are cleared with the words ----
+    uint64_t clear_words = ws_words;
+    if (use_log) {
+        a.log_waves = (uint32_t)waves_total;
+        a.log_chunks = log_chunks_for(t.workspace_bytes - ws_words * 8, waves_total);
+        const uint64_t n_chunks = (uint64_t)kLogBuckets * waves_total * a.log_chunks;
+        a.log_fill = (uint8_t *)(ws + ws_words);
+        a.log = ws + ws_words + (n_chunks + 7) / 8;
+        clear_words += (n_chunks + 7) / 8;
+        const uint64_t groups = (n_total + 7) / 8;
+        a.log_bits = 6;
+        while ((1ull << a.log_bits) < groups) ++a.log_bits;
+    }
+
     const int zero_all = (det.flags & MC_ACCUMULATE) ? 0 : 1;
     const bool sig = (det.flags & MC_SIGMA) != 0, rec = (det.flags & MC_RECORD) != 0;
-    const uint64_t ws_words = batch ? workspace_words(det, n_inst) : workspace_words(det);
-    hipLaunchKernelGGL(init_kernel, dim3(1024), dim3(256), 0, st, ws, (size_t)ws_words,
+    hipLaunchKernelGGL(init_kernel, dim3(1024), dim3(256), 0, st, ws, (size_t)clear_words,
                        (unsigned long long *)t.side, (unsigned long long *)t.trans,
                        sig ? (unsigned long long *)t.side_w2 : nullptr, sig ? (unsigned long long *)t.trans_w2 : nullptr,
                        (size_t)(n_side * n_inst), (size_t)(n_trans * n_inst), t.scalars,
@@ -1018,11 +1225,32 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
                                            walk_kernel<MC_PHASE_HG, 4>, walk_kernel<MC_PHASE_HG, 5>,
                                            walk_kernel<MC_PHASE_HG, 6>, walk_kernel<MC_PHASE_HG, 7>};
         kern = phase == MC_PHASE_MIE ? mie_kernels[opt] : hg_kernels[opt];
+        if (use_log) {
+            static const Kern log_kernels[4] = {
+                walk_kernel<MC_PHASE_MIE, kOptLog>, walk_kernel<MC_PHASE_MIE, kOptLog | kOptSigma>,
+                walk_kernel<MC_PHASE_HG, kOptLog>, walk_kernel<MC_PHASE_HG, kOptLog | kOptSigma>};
+            kern = log_kernels[(phase == MC_PHASE_MIE ? 0 : 2) + (sig ? 1 : 0)];
+        }
         units = total_photons;
     }
     if (units > 0) {
         MC_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, a);
+        MC_HIP_CHECK(hipGetLastError());
+    }
+    if (use_log && units > 0) {
+        // Keys of a range have indices below 2^(bits - 3); one part per
+        // 2^kLogHistBits of them.
+        const uint64_t per_range = 1ull << (a.log_bits - 3);
+        const uint32_t parts = (uint32_t)((per_range + (1u << kLogHistBits) - 1) >> kLogHistBits);
+        uint32_t inv = kLogHashMul;   // inverse of the odd multiplier mod 2^32 (Newton: x <- x (2 - m x))
+        for (int i = 0; i < 5; ++i) inv *= 2u - kLogHashMul * inv;
+        const size_t hist = ((size_t)8 << kLogHistBits) * (sig ? 2 : 1);
+        auto bin = sig ? log_bin<true> : log_bin<false>;
+        MC_HIP_CHECK(hipFuncSetAttribute((const void *)bin, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hist));
+        hipLaunchKernelGGL(bin, dim3(kLogBuckets * parts * kCopies), dim3(1024), hist, st,
+                           (const unsigned long long *)a.log, (const uint8_t *)a.log_fill,
+                           (uint64_t)waves_total * a.log_chunks, a.ws_img, a.ws_img2, n_total, parts, a.log_bits, inv);
         MC_HIP_CHECK(hipGetLastError());
     }
     // ---- finalize: per-XCD copies to the caller's images, scalars to doubles ----
@@ -1062,8 +1290,9 @@ int prepare_batch(const char *fn, const mc_batch_item_t *items, uint32_t n_items
     const mc_tally_t &t = *tally;
     if (int rc = check_geometry(fn, geo)) return rc;
     if (int rc = check_setup(fn, *source, geo, det, rn, t)) return rc;
-    if (det.flags & (MC_RECORD | MC_MOMENTS | MC_MOMENTS_PIXEL2))
-        return fail(MC_EUNSUPPORTED, "%s: MC_RECORD and MC_MOMENTS are not available for batched launches", fn);
+    if (det.flags & (MC_RECORD | MC_MOMENTS | MC_MOMENTS_PIXEL2 | MC_EXIT_LOG))
+        return fail(MC_EUNSUPPORTED, "%s: MC_RECORD, MC_MOMENTS and MC_EXIT_LOG are not available for batched "
+                                     "launches", fn);
     if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_FIX64))
         return fail(MC_EINVAL, "%s: unknown detector flags 0x%x", fn, det.flags);
     const uint64_t n_pix = (uint64_t)det.side_nx * det.side_ny + (uint64_t)det.trans_nx * det.trans_ny;
@@ -1149,8 +1378,10 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
         return fail(MC_EINVAL, "mc_simulate: MC_RECORD needs record_stride >= 1 and, for rec_rows > 0, "
                                "rec_i and rec_f");
     if (rn.photon_offset > UINT64_MAX - rn.n_photons) return fail(MC_EINVAL, "mc_simulate: photon ids overflow");
-    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64 | MC_MOMENTS | MC_MOMENTS_PIXEL2))
+    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64 | MC_MOMENTS | MC_MOMENTS_PIXEL2 | MC_EXIT_LOG))
         return fail(MC_EINVAL, "mc_simulate: unknown detector flags 0x%x", det.flags);
+    if ((det.flags & MC_EXIT_LOG) && (det.flags & (MC_RECORD | MC_MOMENTS)))
+        return fail(MC_EINVAL, "mc_simulate: MC_EXIT_LOG does not combine with MC_RECORD or MC_MOMENTS");
     if ((det.flags & MC_MOMENTS) && (!t.side_wk || !t.side_wl))
         return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS needs side_wk and side_wl");
     if ((det.flags & MC_MOMENTS_PIXEL2) && (!(det.flags & MC_MOMENTS) || !t.side_w2k || !t.side_w2l))
@@ -1189,6 +1420,20 @@ extern "C" uint64_t mc_workspace_bytes(const mc_detector_t *detector)
 {
     if (!detector || !mcmie::dims_ok(*detector)) return 0;
     return mcmie::workspace_words(*detector) * 8;
+}
+
+extern "C" uint64_t mc_workspace_bytes_log(const mc_detector_t *detector, uint64_t n_photons)
+{
+    if (!detector || !mcmie::dims_ok(*detector) || !(detector->flags & MC_EXIT_LOG)) return 0;
+    using namespace mcmie;
+    // Each photon leaves through an image at most once.  Spread evenly over
+    // the ranges and the waves of a full launch, a wave adds about
+    // n / (64 x waves) entries to a range; it gets half as many chunks again
+    // as those fill (for uneven spread and unequal shares of photons), plus
+    // one for its partly filled last chunk.
+    const uint64_t per = kLogBuckets * kLogSizingWaves * kLogChunk;
+    const uint64_t k = std::min<uint64_t>((n_photons + n_photons / 2 + per - 1) / per + 1, kLogMaxChunks);
+    return workspace_words(*detector) * 8 + 8 + kLogBuckets * kLogSizingWaves * k * kLogBytesPerChunk;
 }
 
 extern "C" uint64_t mc_workspace_bytes_batch(const mc_detector_t *detector, uint32_t n_items)

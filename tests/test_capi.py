@@ -30,7 +30,7 @@ def test_header_declares_the_entry_points():
     names = set(_declared_functions())
     assert {"mie_table_build", "mc_simulate", "mc_grad", "mc_last_error", "mc_philox_blocks",
             "mc_version", "mc_workspace_bytes", "mie_table_enqueue", "mc_simulate_batch",
-            "mc_autotune_batch", "mc_workspace_bytes_batch"} <= names
+            "mc_autotune_batch", "mc_workspace_bytes_batch", "mc_workspace_bytes_log"} <= names
 
 
 def test_library_exports_every_declared_symbol():
@@ -46,7 +46,7 @@ def test_library_exports_every_declared_symbol():
 def test_version_and_empty_error():
     import paper_2507_23189_amd as mc
     _lib_path()
-    assert mc.mc_version() == 300
+    assert mc.mc_version() == 400
     assert mc.lib().mc_last_error() == b""
 
 
@@ -69,7 +69,7 @@ def _valid_args():
 @pytest.mark.parametrize("field,value", [
     ("tau", -1.0), ("albedo", 1.5), ("g", 1.0), ("phase", 7),
     ("src_z", 0.5), ("src_x", 11.0), ("dir_z", -1.0), ("size", 0.0), ("n_out", 0.0),
-    ("side_nx", 0), ("max_steps", 0), ("roulette_p", 0.0), ("block_size", 100), ("flags", 64),
+    ("side_nx", 0), ("max_steps", 0), ("roulette_p", 0.0), ("block_size", 100), ("flags", 128),
 ])
 def test_mc_simulate_rejects_invalid_arguments(field, value):
     import paper_2507_23189_amd as mc
@@ -119,6 +119,35 @@ def test_workspace_size_and_checks():
     rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
                               C.byref(tal), None)
     assert rc == mc.MC_EINVAL
+
+
+def test_exit_log_sizes_and_checks():
+    """MC_EXIT_LOG: the workspace words are unchanged and the log comes on
+    top, in whole sets of one chunk (64 entries and a fill byte) per range
+    and wave of a full launch (64 ranges, 8192 waves): 1.5 chunks per 64
+    photons of a wave's share, plus one.  The flag is refused with records
+    or path moments."""
+    import math
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, med, src, geo, det, run = _valid_args()
+    base = mc.mc_workspace_bytes(det)
+    assert mc.mc_workspace_bytes_log(det, 10**6) == 0           # flag not set
+    det.flags = mc.MC_EXIT_LOG
+    assert mc.mc_workspace_bytes(det) == base
+    one_set = 64 * 8192 * (64 * 8 + 1)
+    for n in (0, 1, 10**6, 10**8, 10**9):
+        k = math.ceil(1.5 * n / (64 * 8192 * 64)) + 1
+        assert mc.mc_workspace_bytes_log(det, n) == base + 8 + k * one_set, n
+    assert mc.mc_workspace_bytes_log(mc.Detector(0, 1, 1, 1, mc.MC_EXIT_LOG), 10) == 0
+    for extra in (mc.MC_RECORD, mc.MC_MOMENTS):
+        det.flags = mc.MC_EXIT_LOG | extra
+        tal = _tally_stub(det)
+        run.record_stride = 1
+        rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                                  C.byref(tal), None)
+        assert rc == mc.MC_EINVAL, extra
+        assert b"MC_EXIT_LOG" in mc.lib().mc_last_error()
 
 
 def test_fixed_point_overflow_bound():

@@ -1,0 +1,169 @@
+"""GPU checks of the exit-log tally path (MC_EXIT_LOG).  It computes the same
+integer sums as the atomic path, so its images and scalars must equal that
+path's bit for bit on the same photons.  The atomic path is itself checked
+against the oracle elsewhere; one case here also compares the log path with
+the oracle directly.  Covered: both phase functions, with and without squared
+weights, float64 and int64 outputs, ragged image shapes (keys that do not
+fill the last 512-key group), a log too small for the walk (exits fall back
+to atomics), no log at all, accumulation into earlier results, a workspace
+shared by walks in a row, and the full 1e8-photon tau = 4 launch."""
+import numpy as np
+import pytest
+
+import workloads as W
+from _helpers import image_within_3sigma
+from oracle import walk as owalk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mc():
+    import paper_2507_23189_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def table(mc, cuda_device):
+    w = W.paper_scale(4.0)
+    spec, *_ = mc.args_from_workload(w)
+    return mc.mie_table_build(spec, cuda_device)
+
+
+def _run(mc, dev, w, table, flags, *, n_photons, det_shape=None, log_photons=None, workspace=None,
+         tally=None, phase=None, grid_blocks=0):
+    import torch
+    w = w if phase is None else w.replace(phase=phase)
+    _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=flags, n_photons=n_photons,
+                                                       grid_blocks=grid_blocks)
+    if det_shape is not None:
+        det.side_nx, det.side_ny, det.trans_nx, det.trans_ny = det_shape
+    if tally is None:
+        tally = mc.Tally.alloc(det, dev, sigma=bool(flags & mc.MC_SIGMA), fix64=bool(flags & mc.MC_FIX64),
+                               log_photons=log_photons if log_photons is not None else n_photons,
+                               workspace=workspace)
+    mc.mc_simulate(med, src, geo, det, run, tally)
+    torch.cuda.synchronize()
+    out = {k: getattr(tally, k).cpu().numpy() for k in ("side", "trans", "scalars")}
+    if flags & mc.MC_SIGMA:
+        out["side_w2"] = tally.side_w2.cpu().numpy()
+        out["trans_w2"] = tally.trans_w2.cpu().numpy()
+    out["tally"] = tally
+    out["fallback"] = int(tally.workspace[21].item())   # exits added directly: the log was full
+    return out
+
+
+def _same(a, b):
+    for k in ("side", "trans", "scalars", "side_w2", "trans_w2"):
+        if k in a or k in b:
+            assert a[k].dtype == b[k].dtype
+            assert np.array_equal(a[k], b[k]), k
+
+
+CASES = [
+    dict(phase="mie", fix64=True, sigma=False),
+    dict(phase="mie", fix64=True, sigma=True),
+    dict(phase="mie", fix64=False, sigma=False),
+    dict(phase="hg", fix64=True, sigma=True),
+    dict(phase="hg", fix64=False, sigma=False),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c['phase']}-{'fix64' if c['fix64'] else 'f64'}"
+                         f"{'-sigma' if c['sigma'] else ''}")
+def test_log_equals_atomic_path(mc, cuda_device, table, case):
+    w = W.paper_scale(4.0)
+    phase = W.PHASE_MIE if case["phase"] == "mie" else W.PHASE_HG
+    flags = (mc.MC_FIX64 if case["fix64"] else 0) | (mc.MC_SIGMA if case["sigma"] else 0)
+    n = 2_000_000
+    a = _run(mc, cuda_device, w, table, flags, n_photons=n, phase=phase)
+    b = _run(mc, cuda_device, w, table, flags | mc.MC_EXIT_LOG, n_photons=n, phase=phase)
+    assert a["scalars"][10] == n
+    assert a["side"].sum() > 0 and a["trans"].sum() > 0
+    _same(a, b)
+
+
+@pytest.mark.parametrize("shape", [(37, 23, 61, 19), (1, 1, 1, 1), (5, 300, 700, 3), (512, 512, 1024, 1024)])
+def test_log_ragged_shapes(mc, cuda_device, table, shape):
+    """Image sizes whose key count is not a multiple of 512, a single pixel
+    per image, and keys beyond one histogram part of a range."""
+    w = W.paper_scale(4.0)
+    flags = mc.MC_FIX64 | mc.MC_SIGMA
+    n = 500_000
+    a = _run(mc, cuda_device, w, table, flags, n_photons=n, det_shape=shape)
+    b = _run(mc, cuda_device, w, table, flags | mc.MC_EXIT_LOG, n_photons=n, det_shape=shape)
+    _same(a, b)
+
+
+@pytest.mark.parametrize("chunks", [0, 1, 3, 12])
+def test_log_capacity_fallback(mc, cuda_device, table, chunks):
+    """A launch of two 1024-lane blocks (32 waves) whose log holds 0, 1, 3
+    or 12 chunks per wave and range: each wave adds about 330 exits to every
+    range, so with few chunks most of them find the log full and are added
+    directly.  The results do not change."""
+    import torch
+    w = W.paper_scale(4.0)
+    flags = mc.MC_FIX64 | mc.MC_SIGMA
+    n = 1_000_000
+    _, _, _, _, det, _ = mc.args_from_workload(w, flags=flags | mc.MC_EXIT_LOG)
+    ws_bytes = mc.mc_workspace_bytes(det) + 8 + chunks * 64 * 32 * (64 * 8 + 1)
+    small = mc.Tally.alloc(det, cuda_device, sigma=True, fix64=True, log_photons=0)
+    small.workspace = torch.empty((ws_bytes + 7) // 8, dtype=torch.int64, device=cuda_device)
+    a = _run(mc, cuda_device, w, table, flags, n_photons=n, grid_blocks=2)
+    b = _run(mc, cuda_device, w, table, flags | mc.MC_EXIT_LOG, n_photons=n, tally=small, grid_blocks=2)
+    _same(a, b)
+    print(f"chunks {chunks}: {b['fallback']} exits added directly")
+    if chunks <= 3:
+        assert b["fallback"] > 0
+
+
+def test_log_accumulate_and_shared_workspace(mc, cuda_device, table):
+    """Two walks in a row on one workspace: the second, with MC_ACCUMULATE,
+    adds its photons (ids after the first's) to the first's results."""
+    import torch
+    w = W.paper_scale(4.0)
+    flags = mc.MC_FIX64 | mc.MC_SIGMA
+    n = 1_000_000
+    full = _run(mc, cuda_device, w, table, flags, n_photons=2 * n)
+    t = _run(mc, cuda_device, w, table, flags | mc.MC_EXIT_LOG, n_photons=n)["tally"]
+    other = _run(mc, cuda_device, w, table, flags | mc.MC_EXIT_LOG, n_photons=n, workspace=t.workspace)
+    _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=flags | mc.MC_EXIT_LOG | mc.MC_ACCUMULATE,
+                                                       n_photons=n, photon_offset=n)
+    mc.mc_simulate(med, src, geo, det, run, t)
+    torch.cuda.synchronize()
+    got = {k: getattr(t, k).cpu().numpy() for k in ("side", "trans", "side_w2", "trans_w2")}
+    for k in ("side", "trans", "side_w2", "trans_w2"):
+        assert np.array_equal(got[k], full[k]), k
+    s = t.scalars.cpu().numpy()
+    assert s[10] == 2 * n and s[9] == full["scalars"][9]
+    # The walk that shared the workspace before still holds its own result.
+    first = _run(mc, cuda_device, w, table, flags, n_photons=n)
+    _same(first, {k: v for k, v in other.items() if k != "tally"})
+
+
+def test_log_against_oracle(mc, cuda_device):
+    """The log path on the tiny workload against the oracle's FP64 walk."""
+    w = W.TINY
+    spec, *_ = mc.args_from_workload(w)
+    tab = mc.mie_table_build(spec, cuda_device)
+    g = _run(mc, cuda_device, w, tab, mc.MC_SIGMA | mc.MC_EXIT_LOG, n_photons=w.n_photons)
+    o = owalk.Walk(w).run()
+    assert image_within_3sigma(g["side"], o.side, o.side_w2, w.n_photons).all()
+    assert image_within_3sigma(g["trans"], o.trans, o.trans_w2, w.n_photons).all()
+    np.testing.assert_allclose(g["scalars"][:7], o.scalars[:7], rtol=2e-3, atol=2.0)
+
+
+def test_log_full_size_launch(mc, cuda_device, table):
+    """The full tau = 4 launch of 1e8 photons (512 x 512 images) in the
+    launch configuration the benchmark times: the log path equals the atomic
+    path bit for bit, and nearly every exit went through the log."""
+    w = W.paper_scale(4.0)
+    a = _run(mc, cuda_device, w, table, mc.MC_FIX64, n_photons=w.n_photons)
+    b = _run(mc, cuda_device, w, table, mc.MC_FIX64 | mc.MC_EXIT_LOG, n_photons=w.n_photons)
+    _same(a, b)
+    assert a["scalars"][10] == w.n_photons
+    # Waves that take more than their share of photons can run out of chunks
+    # in a range; those few exits are added directly.
+    print(f"exits added directly: {b['fallback']}")
+    assert b["fallback"] <= 1e-3 * w.n_photons

@@ -202,6 +202,21 @@ def test_launch_shape_and_photon_ranges_are_invariant(mc, cuda_device):
     assert f["trans"].sum() * 2.0**-32 == f["scalars"][5]
 
 
+def test_full_chip_launches_are_bit_identical(mc, cuda_device):
+    """Full-chip launches of the tau = 4 workload (16384-entry table in LDS,
+    every CU busy): repeated runs and another block size give identical
+    fixed-point images and scalars.  Each photon's walk depends only on its
+    id, so any difference means a wave read shared state (the table, the
+    scalar words, the cache) before the block had finished setting it up."""
+    w = W.paper_scale(4.0)
+    a = gpu_run(w, fix64=True, n_photons=4_000_000)
+    runs = [gpu_run(w, fix64=True, n_photons=4_000_000, table=a["table"]) for _ in range(2)]
+    runs.append(gpu_run(w, fix64=True, n_photons=4_000_000, table=a["table"], block_size=256))
+    for other in runs:
+        for k in ("side", "trans", "side_w2", "trans_w2", "scalars"):
+            np.testing.assert_array_equal(a[k], other[k], err_msg=k)
+
+
 def test_fixed_point_tallies_are_exact_sums_of_record_weights(mc, cuda_device):
     """MC_FIX64 tallies hold, per pixel and per face, the sum of each exit
     weight rounded to nearest (ties to even) at 2^32 per unit, bit for bit:
