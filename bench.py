@@ -74,24 +74,32 @@ CENSUS = {"step": 91, "interaction": 49, "boundary": 31, "imaged_exit": 40, "oth
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock at the 2.4 GHz peak engine clock.
 PEAK_SLOTS_PER_S = 256 * 64 * 2.4e9
 
-# HBM traffic of one walk_kernel launch on this workload, from rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by what the same counters
-# read for a 256 MiB device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); valid
-# only for the kernel sources it was measured on (profiles/walk_tau4_counters.md).
-TRAFFIC = {"sources_sha256": "d65161baf14c695d2238539b09cb2b5b7e28a384ab0646929cc760cc0466e78c",
-           "fetch_kib": 337.0, "write_kib": 2105060.0, "fetch_factor": 2.0, "write_factor": 1.0}
+# HBM traffic of one walk_kernel launch on this workload with the exit log,
+# from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by
+# what the same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0); valid only for the tally path and kernel sources it was
+# measured on (profiles/walk_tau4_counters.md).
+TRAFFIC = {"tally": "log", "sources_sha256": "2937831ea9302339d1300f199851ac1982f55cc01cc5b3721e1a90d956d8959e",
+           "fetch_kib": 387.6, "write_kib": 1828500.0, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 
-def measured_traffic():
+def measured_traffic(args):
     """Bytes per launch if the walk kernel is the one the counters were taken on, else None."""
     import hashlib
+    if args.atomic_tally != (TRAFFIC["tally"] == "atomic"):
+        return None
     h = hashlib.sha256()
     for f in WALK_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest() != TRAFFIC["sources_sha256"]:
         return None
     return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] + TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
+
+
+def tally_flags(mc, args):
+    """Image exits go through the exit log unless --atomic-tally."""
+    return 0 if args.atomic_tally else mc.MC_EXIT_LOG
 
 
 def log(msg):
@@ -138,12 +146,15 @@ def adjoint_timing(mc, w, dev, args):
     table = mc.mie_table_build(spec, dev)
     g_hg = table.g if w.phase == mc.MC_PHASE_HG else None
     kw = dict(g=g_hg, block_size=args.block_size, grid_blocks=args.grid_blocks)
-    _, med, src, geo, det, run = mc.args_from_workload(w, table, **kw)
-    _, med_a, _, _, det_a, _ = mc.args_from_workload(w, table, flags=mc.MC_MOMENTS, **kw)
-    _, med_p, _, _, det_p, _ = mc.args_from_workload(w, table, flags=mc.MC_MOMENTS | mc.MC_MOMENTS_PIXEL2, **kw)
-    t_fwd = mc.Tally.alloc(det, dev)
-    t_adj = mc.Tally.alloc(det_a, dev, moments=True)
-    t_pix = mc.Tally.alloc(det_p, dev, moments=True, pixel2=True)
+    lg = tally_flags(mc, args)
+    _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=lg, **kw)
+    _, med_a, _, _, det_a, _ = mc.args_from_workload(w, table, flags=lg | mc.MC_MOMENTS, **kw)
+    _, med_p, _, _, det_p, _ = mc.args_from_workload(w, table, flags=lg | mc.MC_MOMENTS | mc.MC_MOMENTS_PIXEL2,
+                                                     **kw)
+    t_fwd = mc.Tally.alloc(det, dev, log_photons=w.n_photons)
+    t_adj = mc.Tally.alloc(det_a, dev, moments=True, log_photons=w.n_photons, workspace=t_fwd.workspace)
+    t_pix = mc.Tally.alloc(det_p, dev, moments=True, pixel2=True, log_photons=w.n_photons,
+                           workspace=t_fwd.workspace)
     gen = torch.Generator(device="cpu").manual_seed(7)
     dloss = torch.randn(w.side_px, w.side_px, generator=gen, dtype=torch.float64).to(dev)
     d2loss = torch.full_like(dloss, 2.0)
@@ -233,10 +244,11 @@ def heavy_timing(mc, W, dev, args):
     t0 = time.perf_counter()
     table = mc.table_for_workload(w, dev)
     table_ms = (time.perf_counter() - t0) * 1e3
-    _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=mc.MC_FIX64)
-    _, med_a, _, _, det_a, _ = mc.args_from_workload(w, table, flags=mc.MC_FIX64 | mc.MC_MOMENTS)
-    t_f = mc.Tally.alloc(det, dev, fix64=True)
-    t_a = mc.Tally.alloc(det_a, dev, fix64=True, moments=True)
+    lg = tally_flags(mc, args)
+    _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=mc.MC_FIX64 | lg)
+    _, med_a, _, _, det_a, _ = mc.args_from_workload(w, table, flags=mc.MC_FIX64 | mc.MC_MOMENTS | lg)
+    t_f = mc.Tally.alloc(det, dev, fix64=True, log_photons=w.n_photons)
+    t_a = mc.Tally.alloc(det_a, dev, fix64=True, moments=True, log_photons=w.n_photons, workspace=t_f.workspace)
     dloss = torch.ones((w.side_px, w.side_px), dtype=torch.float64, device=dev)
     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
 
@@ -280,10 +292,12 @@ def analysis_timing(mc, W, dev, args):
         wm = W.analysis_workload(od)
         table = mc.mie_table_build(mc.args_from_workload(wm)[0], dev)
         imgs = {}
+        ws = None
         for name, w, g in (("mie", wm, None), ("ref", wm.replace(seed=W.ANALYSIS_REF_SEED), None),
                            ("hg", wm.replace(phase=W.PHASE_HG), table.g)):
-            _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g)
-            t = mc.Tally.alloc(det, dev)
+            _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g, flags=tally_flags(mc, args))
+            t = mc.Tally.alloc(det, dev, log_photons=w.n_photons, workspace=ws)
+            ws = t.workspace
             mc.mc_simulate(med, src, geo, det, run, t)
             imgs[name] = t.side
         torch.cuda.synchronize()
@@ -305,8 +319,8 @@ def analysis_timing(mc, W, dev, args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tau", type=float, default=4.0)
     ap.add_argument("--photons", type=int, default=100_000_000)
     ap.add_argument("--phase", choices=("mie", "hg"), default="mie")
@@ -317,6 +331,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-heavy", action="store_true")
     ap.add_argument("--no-analysis", action="store_true")
+    ap.add_argument("--atomic-tally", action="store_true",
+                    help="tally image exits with global atomics instead of the exit log")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -339,8 +355,11 @@ def main():
     spec, *_ = mc.args_from_workload(w)
     stream = torch.cuda.current_stream()
 
-    det_probe = mc.args_from_workload(w)[4]
-    tallies = [mc.Tally.alloc(det_probe, dev) for _ in range(args.warmup + args.steps)]
+    flags = tally_flags(mc, args)
+    det_probe = mc.args_from_workload(w, flags=flags)[4]
+    tallies = [mc.Tally.alloc(det_probe, dev, log_photons=w.n_photons)]
+    tallies += [mc.Tally.alloc(det_probe, dev, log_photons=w.n_photons, workspace=tallies[0].workspace)
+                for _ in range(args.warmup + args.steps - 1)]
     walk_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.warmup + args.steps)]
 
@@ -356,8 +375,8 @@ def main():
             table = mc.mie_table_enqueue(spec, dev, inv_cdf=inv_cdf, result=result)
         else:
             table = mc.mie_table_build(spec, dev)
-        _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g_hg, block_size=args.block_size,
-                                                           grid_blocks=args.grid_blocks)
+        _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g_hg, flags=flags,
+                                                           block_size=args.block_size, grid_blocks=args.grid_blocks)
         e0, e1 = walk_ev[i]
         e0.record(stream)
         mc.mc_simulate(med, src, geo, det, run, tallies[i])
@@ -414,9 +433,11 @@ def main():
                    "seed": w.seed, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS_PER_S / 1e12,
                      "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S,
-                     "traffic": measured_traffic() if (args.tau == 4.0 and args.photons == 100_000_000
-                                                       and phase == W.PHASE_MIE) else None,
-                     "kernel": "mc_simulate (init, walk_kernel, finalize)",
+                     "traffic": measured_traffic(args) if (args.tau == 4.0 and args.photons == 100_000_000
+                                                           and phase == W.PHASE_MIE) else None,
+                     "kernel": ("mc_simulate (init, walk_kernel, finalize)" if args.atomic_tally else
+                                "mc_simulate (init, walk_kernel, log_bin, finalize)"),
+                     "tally": "atomic" if args.atomic_tally else "exit log",
                      "kernel_ms": walk_avg_s * 1e3, "slots_per_launch": slots},
         "photons_per_s": photons / elapsed,
         "events_per_photon": s_last[9] / s_last[10],

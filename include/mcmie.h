@@ -65,7 +65,7 @@ extern "C" {
                                  workspace beyond mc_workspace_bytes (size it with
                                  mc_workspace_bytes_log); exits that find their part of it full
                                  are added directly, so any size is correct.  Not with
-                                 MC_RECORD or MC_MOMENTS, nor in batched launches. */
+                                 MC_RECORD, nor in batched launches. */
 
 /* Scalar tallies: mc_tally_t.scalars holds MC_N_SCALARS doubles. */
 #define MC_S_FACE 0           /* 0..5: weight leaving faces -x, +x, -y, +y, -z, +z */

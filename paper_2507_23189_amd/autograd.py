@@ -18,12 +18,15 @@ from __future__ import annotations
 
 import math
 
-from ._capi import MC_MOMENTS, MC_S_SIDE_W2, Detector, Geometry, Medium, Run, Source, Tally, mc_grad, mc_simulate
+from ._capi import (MC_EXIT_LOG, MC_MOMENTS, MC_S_SIDE_W2, Detector, Geometry, Medium, Run, Source, Tally, mc_grad,
+                    mc_simulate)
 
 
 class SideImage:
     """Fixed parts of a walk (table, source, geometry, detector, run) whose
-    side image is differentiated with respect to (mu_sca, mu_abs)."""
+    side image is differentiated with respect to (mu_sca, mu_abs).  With
+    MC_EXIT_LOG in the detector flags, every walk of this object shares one
+    workspace holding the exit log."""
 
     def __init__(self, medium: Medium, source: Source, geometry: Geometry, detector: Detector, run: Run,
                  device="cuda"):
@@ -31,6 +34,7 @@ class SideImage:
         self.detector = Detector(detector.side_nx, detector.side_ny, detector.trans_nx, detector.trans_ny,
                                  detector.flags | MC_MOMENTS)
         self.device = device
+        self._workspace = None
 
     def medium_for(self, mu_sca: float, mu_abs: float) -> Medium:
         """Eq. 1 and Eq. 16: tau = (mu_sca + mu_abs) L_z, albedo = mu_sca / mu_ext."""
@@ -46,7 +50,10 @@ class SideImage:
 
     def run_walk(self, mu_sca: float, mu_abs: float):
         med = self.medium_for(mu_sca, mu_abs)
-        tally = Tally.alloc(self.detector, self.device, moments=True)
+        tally = Tally.alloc(self.detector, self.device, moments=True, log_photons=self.run.n_photons,
+                            workspace=self._workspace)
+        if self.detector.flags & MC_EXIT_LOG:
+            self._workspace = tally.workspace
         mc_simulate(med, self.source, self.geometry, self.detector, self.run, tally)
         return med, tally
 

@@ -1226,10 +1226,17 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
                                            walk_kernel<MC_PHASE_HG, 6>, walk_kernel<MC_PHASE_HG, 7>};
         kern = phase == MC_PHASE_MIE ? mie_kernels[opt] : hg_kernels[opt];
         if (use_log) {
-            static const Kern log_kernels[4] = {
+            // Exit log with optional squared weights and path moments (index
+            // sigma + 2 x moments); records take the atomic path.
+            static const Kern log_kernels[8] = {
                 walk_kernel<MC_PHASE_MIE, kOptLog>, walk_kernel<MC_PHASE_MIE, kOptLog | kOptSigma>,
-                walk_kernel<MC_PHASE_HG, kOptLog>, walk_kernel<MC_PHASE_HG, kOptLog | kOptSigma>};
-            kern = log_kernels[(phase == MC_PHASE_MIE ? 0 : 2) + (sig ? 1 : 0)];
+                walk_kernel<MC_PHASE_MIE, kOptLog | kOptMoments>,
+                walk_kernel<MC_PHASE_MIE, kOptLog | kOptMoments | kOptSigma>,
+                walk_kernel<MC_PHASE_HG, kOptLog>, walk_kernel<MC_PHASE_HG, kOptLog | kOptSigma>,
+                walk_kernel<MC_PHASE_HG, kOptLog | kOptMoments>,
+                walk_kernel<MC_PHASE_HG, kOptLog | kOptMoments | kOptSigma>};
+            kern = log_kernels[(phase == MC_PHASE_MIE ? 0 : 4) + (sig ? 1 : 0) +
+                               ((det.flags & MC_MOMENTS) ? 2 : 0)];
         }
         units = total_photons;
     }
@@ -1380,8 +1387,8 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     if (rn.photon_offset > UINT64_MAX - rn.n_photons) return fail(MC_EINVAL, "mc_simulate: photon ids overflow");
     if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64 | MC_MOMENTS | MC_MOMENTS_PIXEL2 | MC_EXIT_LOG))
         return fail(MC_EINVAL, "mc_simulate: unknown detector flags 0x%x", det.flags);
-    if ((det.flags & MC_EXIT_LOG) && (det.flags & (MC_RECORD | MC_MOMENTS)))
-        return fail(MC_EINVAL, "mc_simulate: MC_EXIT_LOG does not combine with MC_RECORD or MC_MOMENTS");
+    if ((det.flags & MC_EXIT_LOG) && (det.flags & MC_RECORD))
+        return fail(MC_EINVAL, "mc_simulate: MC_EXIT_LOG does not combine with MC_RECORD");
     if ((det.flags & MC_MOMENTS) && (!t.side_wk || !t.side_wl))
         return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS needs side_wk and side_wl");
     if ((det.flags & MC_MOMENTS_PIXEL2) && (!(det.flags & MC_MOMENTS) || !t.side_w2k || !t.side_w2l))

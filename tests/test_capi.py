@@ -125,8 +125,8 @@ def test_exit_log_sizes_and_checks():
     """MC_EXIT_LOG: the workspace words are unchanged and the log comes on
     top, in whole sets of one chunk (64 entries and a fill byte) per range
     and wave of a full launch (64 ranges, 8192 waves): 1.5 chunks per 64
-    photons of a wave's share, plus one.  The flag is refused with records
-    or path moments."""
+    photons of a wave's share, plus one.  The flag is refused with
+    records."""
     import math
     import paper_2507_23189_amd as mc
     _lib_path()
@@ -140,14 +140,13 @@ def test_exit_log_sizes_and_checks():
         k = math.ceil(1.5 * n / (64 * 8192 * 64)) + 1
         assert mc.mc_workspace_bytes_log(det, n) == base + 8 + k * one_set, n
     assert mc.mc_workspace_bytes_log(mc.Detector(0, 1, 1, 1, mc.MC_EXIT_LOG), 10) == 0
-    for extra in (mc.MC_RECORD, mc.MC_MOMENTS):
-        det.flags = mc.MC_EXIT_LOG | extra
-        tal = _tally_stub(det)
-        run.record_stride = 1
-        rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
-                                  C.byref(tal), None)
-        assert rc == mc.MC_EINVAL, extra
-        assert b"MC_EXIT_LOG" in mc.lib().mc_last_error()
+    det.flags = mc.MC_EXIT_LOG | mc.MC_RECORD
+    tal = _tally_stub(det)
+    run.record_stride = 1
+    rc = mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                              C.byref(tal), None)
+    assert rc == mc.MC_EINVAL
+    assert b"MC_EXIT_LOG" in mc.lib().mc_last_error()
 
 
 def test_fixed_point_overflow_bound():

@@ -167,3 +167,32 @@ def test_log_full_size_launch(mc, cuda_device, table):
     # in a range; those few exits are added directly.
     print(f"exits added directly: {b['fallback']}")
     assert b["fallback"] <= 1e-3 * w.n_photons
+
+
+@pytest.mark.parametrize("fix64", [True, False])
+def test_log_with_path_moments_and_adjoint(mc, cuda_device, table, fix64):
+    """MC_EXIT_LOG with MC_MOMENTS: the images equal the atomic path's bit
+    for bit; the FP64 path moments and second-moment scalars (sums whose order
+    differs from run to run) and the adjoint agree to rounding."""
+    import torch
+    w = W.paper_scale(4.0)
+    n = 2_000_000
+    base = mc.MC_MOMENTS | (mc.MC_FIX64 if fix64 else 0)
+    out = []
+    for flags in (base, base | mc.MC_EXIT_LOG):
+        _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=flags, n_photons=n)
+        t = mc.Tally.alloc(det, cuda_device, fix64=fix64, moments=True, log_photons=n)
+        mc.mc_simulate(med, src, geo, det, run, t)
+        g = (torch.arange(w.side_px * w.side_px, dtype=torch.float64, device=cuda_device) % 7 - 3.0).reshape(
+            w.side_px, w.side_px).contiguous()
+        grad = mc.mc_grad(med, geo, det, t, g, d2loss_uniform=2.0)
+        torch.cuda.synchronize()
+        out.append(dict(side=t.side.cpu().numpy(), trans=t.trans.cpu().numpy(), s=t.scalars.cpu().numpy(),
+                        wk=t.side_wk.cpu().numpy(), wl=t.side_wl.cpu().numpy(), grad=np.array(grad)))
+    a, b = out
+    assert np.array_equal(a["side"], b["side"]) and np.array_equal(a["trans"], b["trans"])
+    assert np.array_equal(a["s"][:16], b["s"][:16])
+    np.testing.assert_allclose(b["s"][16:19], a["s"][16:19], rtol=1e-12)
+    np.testing.assert_allclose(b["wk"], a["wk"], rtol=1e-12, atol=1e-12 * np.abs(a["wk"]).max())
+    np.testing.assert_allclose(b["wl"], a["wl"], rtol=1e-12, atol=1e-12 * np.abs(a["wl"]).max())
+    np.testing.assert_allclose(b["grad"], a["grad"], rtol=1e-9)
