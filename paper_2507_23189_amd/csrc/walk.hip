@@ -153,6 +153,13 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
     return v;
 }
 
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
 #pragma unroll
@@ -376,6 +383,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // Lane accumulators.
     unsigned long long acc_abs = 0ull;
     uint32_t acc_events = 0, acc_steps = 0, acc_refl = 0, acc_photons = 0, acc_ball = 0;
+    double acc_w2 = 0.0, acc_w2k = 0.0, acc_w2l = 0.0;   // MOMENTS: image-wide second moments
     // The medium of the lane's photon (batched launches change it per photon;
     // otherwise these stay the launch's values).
     uint32_t l_slot = kEmpty, q_p = 0;
@@ -414,16 +422,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 if (MOMENTS && cause == 0 && face == 1) {
                     // Path moments of the side image (perturbation Monte Carlo):
                     // first order per pixel, second order summed over the image
-                    // in the block's LDS (per pixel as well when asked for).
+                    // in lane registers (per pixel as well when asked for).
                     const uint32_t key = (uint32_t)(pixel(py, a.size[1], a.side_ny) * a.side_nx +
                                                     pixel(pz, a.size[2], a.side_nx));
                     const double wd = (double)w, wk = wd * (double)k, wl = wd * (double)L;
                     atomicAdd(a.side_wk + key, wk);
                     atomicAdd(a.side_wl + key, wl);
-                    double *s_m2 = (double *)(s_scal + MC_S_SIDE_W2);
-                    atomicAdd(s_m2 + 0, wd * wd);
-                    atomicAdd(s_m2 + 1, wd * wk);
-                    atomicAdd(s_m2 + 2, wd * wl);
+                    acc_w2 += wd * wd;
+                    acc_w2k += wd * wk;
+                    acc_w2l += wd * wl;
                     if (a.side_w2k) {
                         atomicAdd(a.side_w2k + key, wd * wk);
                         atomicAdd(a.side_w2l + key, wd * wl);
@@ -696,6 +703,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             atomicAdd(&s_scal[MC_S_STEPS], (unsigned long long)wst);
             atomicAdd(&s_scal[MC_S_REFLECTIONS], (unsigned long long)wrf);
             atomicAdd(&s_scal[MC_S_PHOTONS], (unsigned long long)wph);
+        }
+        if (MOMENTS) {
+            const double m0 = wave_sum(acc_w2), m1 = wave_sum(acc_w2k), m2 = wave_sum(acc_w2l);
+            if (lane == 0) {
+                double *s_m2 = (double *)(s_scal + MC_S_SIDE_W2);
+                atomicAdd(s_m2 + 0, m0);
+                atomicAdd(s_m2 + 1, m1);
+                atomicAdd(s_m2 + 2, m2);
+            }
         }
         __syncthreads();
         if (threadIdx.x < MC_S_RESERVED) {
