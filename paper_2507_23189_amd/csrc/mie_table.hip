@@ -1,18 +1,21 @@
 // Mie phase-function table on the device, FP64 (Sec. 2.2-2.6, Sec. 3.1.2).
 //
 // One workgroup builds one table:
-//   1. lane 0 runs the Bohren-Huffman series (Sec. 2.5): the logarithmic
-//      derivative D_n(mx) by downward recurrence, psi_n(x) and chi_n(x)
-//      upward, then a_n and b_n (Eqs. 7-8 divided through by psi_n(mx)),
-//      accumulating Q_ext (Eq. 13), Q_sca and the asymmetry sums (Eq. 12);
+//   1. the Bohren-Huffman series (Sec. 2.5): one lane runs the logarithmic
+//      derivative D_n(mx) by downward recurrence while a lane of another wave
+//      runs psi_n(x) and chi_n(x) upward; then every lane forms a_n and b_n
+//      for its n (Eqs. 7-8 divided through by psi_n(mx)), and Q_ext (Eq. 13),
+//      Q_sca and the asymmetry sums (Eq. 12) are added in a fixed order;
 //   2. every lane evaluates S1, S2 (Eqs. 5-6) at its share of the angle grid
-//      with the angular functions pi_n, tau_n by upward recurrence, giving the
-//      phase function normalised so that (1/4pi) int P dOmega = 1 (Eqs. 9-10);
+//      with the angular functions pi_n, tau_n by upward recurrence (the
+//      per-n divisions done once beforehand), giving the phase function
+//      normalised so that (1/4pi) int P dOmega = 1 (Eqs. 9-10);
 //   3. the trapezoid CDF of P sin(theta) is a chunked in-place block scan;
 //   4. each inverse-table entry u_i = i/(N-1) finds the first angle with
 //      F >= u_i by binary search and interpolates theta linearly; the table
 //      stores v = 1 - cos(theta) = 2 sin^2(theta/2) in FP32.
-// All arrays live in LDS (coefficients 32 KB, angle grid 24 KB at the limits).
+// All arrays live in LDS (coefficients 32 KB, 1/(n - 1) 8 KB, angle grid
+// 24 KB at the limits; gfx950 gives a workgroup up to 160 KB).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -50,6 +53,42 @@ __device__ __forceinline__ cplx operator/(cplx a, cplx b)
     return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
 }
 __device__ __forceinline__ double norm2(cplx a) { return a.re * a.re + a.im * a.im; }
+// 1 / z with one real division (|z|^2 stays far from overflow for the
+// recurrence it serves: |z| <= n / |mx| + |D_n|).
+__device__ __forceinline__ cplx reciprocal(cplx z)
+{
+    const double r = 1.0 / norm2(z);
+    return {z.re * r, -z.im * r};
+}
+
+// sin(t) for |t| <= pi/2 from its Taylor series through t^19/19!, in Horner
+// form in t^2 (truncation below (pi/2)^21/21! < 3e-16): no range reduction is
+// needed on this interval.
+__device__ __forceinline__ double sin_half_pi(double t)
+{
+    const double s = t * t;
+    double p = 1.0 / 121645100408832000.0;               // 1/19!
+    p = fma(p, s, -1.0 / 355687428096000.0);             // -1/17!
+    p = fma(p, s, 1.0 / 1307674368000.0);                // 1/15!
+    p = fma(p, s, -1.0 / 6227020800.0);                  // -1/13!
+    p = fma(p, s, 1.0 / 39916800.0);                     // 1/11!
+    p = fma(p, s, -1.0 / 362880.0);                      // -1/9!
+    p = fma(p, s, 1.0 / 5040.0);                         // 1/7!
+    p = fma(p, s, -1.0 / 120.0);                         // -1/5!
+    p = fma(p, s, 1.0 / 6.0);                            // 1/3! (subtracted below)
+    return t - t * s * p;
+}
+// sin and cos of theta in [0, pi].  sin by reflection onto [0, pi/2];
+// cos as 1 - 2 sin^2(theta/2) (or its mirror about pi/2), which keeps full
+// accuracy where cos is near +-1 and the angular functions are most sensitive.
+__device__ __forceinline__ double sin_0_pi(double th) { return sin_half_pi(th <= 0.5 * M_PI ? th : M_PI - th); }
+__device__ __forceinline__ double cos_0_pi(double th)
+{
+    const bool back = th > 0.5 * M_PI;
+    const double h = sin_half_pi(0.5 * (back ? M_PI - th : th));
+    const double c = 1.0 - 2.0 * h * h;
+    return back ? -c : c;
+}
 
 struct MieArgs {
     double x, m_re, m_im;
@@ -59,82 +98,134 @@ struct MieArgs {
     double *result;          // q_ext, q_sca, g, n_terms
 };
 
-// Step 1 on one lane: the series for size parameter x and relative index m.
-// Leaves a_n, b_n in s_a, s_b (n = 1..N at index n - 1) and returns Q_ext,
-// Q_sca and g.
-__device__ void mie_series(double x, double m_re, double m_im, int N, int n_start, cplx *s_a, cplx *s_b,
-                           double *q_ext_out, double *q_sca_out, double *g_out)
+// Step 1 by the whole workgroup: the series for size parameter x and relative
+// index m.  The two recurrences are serial and run at once on lanes of two
+// different waves: D_n(mx) downward from n_start (into s_a, n = 1..N at index
+// n - 1) and psi_n(x), chi_n(x) upward (into s_psi, s_chi at index n,
+// n = 0..N).  Then each lane forms a_n and b_n for its n (in place of D_n),
+// and the sums of Q_ext (Eq. 13), Q_sca and the asymmetry (Eq. 12) are
+// added per lane, per wave and over the waves in a fixed order.  On return
+// (after a barrier) s_sums holds Q_ext, Q_sca and g for every lane.
+__device__ void mie_series_block(double x, double m_re, double m_im, int N, int n_start, cplx *s_a, cplx *s_b,
+                                 double *s_psi, double *s_chi, double *s_red, double *s_sums)
 {
+    const int tid = threadIdx.x;
     const cplx m = {m_re, m_im};
-    const cplx mx = x * m;
-    const cplx inv_mx = cplx{1.0, 0.0} / mx;
-    cplx D = {0.0, 0.0};
-    for (int n = n_start; n >= 1; --n) {
-        // D_{n-1} = n/(mx) - 1 / (D_n + n/(mx)); keep D_n for n <= N.
-        if (n <= N) s_a[n - 1] = D;
-        const cplx nmx = (double)n * inv_mx;
-        D = nmx - cplx{1.0, 0.0} / (D + nmx);
+    if (tid == 0) {
+        const cplx mx = x * m;
+        const cplx inv_mx = cplx{1.0, 0.0} / mx;
+        cplx D = {0.0, 0.0};
+        for (int n = n_start; n >= 1; --n) {
+            // D_{n-1} = n/(mx) - 1 / (D_n + n/(mx)); keep D_n for n <= N.
+            if (n <= N) s_a[n - 1] = D;
+            const cplx nmx = (double)n * inv_mx;
+            D = nmx - reciprocal(D + nmx);
+        }
+    } else if (tid == 64) {
+        double psi_prev = cos(x), psi = sin(x);        // psi_{-1}, psi_0
+        double chi_prev = -sin(x), chi = cos(x);       // chi_{-1}, chi_0
+        s_psi[0] = psi;
+        s_chi[0] = chi;
+        for (int n = 1; n <= N; ++n) {
+            const double f = (2.0 * n - 1.0) / x;
+            const double psi_n = f * psi - psi_prev;
+            const double chi_n = f * chi - chi_prev;
+            s_psi[n] = psi_n;
+            s_chi[n] = chi_n;
+            psi_prev = psi;
+            psi = psi_n;
+            chi_prev = chi;
+            chi = chi_n;
+        }
     }
-    double psi_prev = cos(x), psi = sin(x);        // psi_{-1}, psi_0
-    double chi_prev = -sin(x), chi = cos(x);       // chi_{-1}, chi_0
-    double sum_ext = 0.0, sum_sca = 0.0, sum_g1 = 0.0, sum_g2 = 0.0;
-    cplx an_prev = {0.0, 0.0}, bn_prev = {0.0, 0.0};
+    __syncthreads();
     const cplx inv_m = cplx{1.0, 0.0} / m;
-    for (int n = 1; n <= N; ++n) {
-        const double f = (2.0 * n - 1.0) / x;
-        const double psi_n = f * psi - psi_prev;
-        const double chi_n = f * chi - chi_prev;
-        const cplx xi_n = {psi_n, -chi_n};
-        const cplx xi_nm1 = {psi, -chi};
+    for (int n = tid + 1; n <= N; n += blockDim.x) {
+        const double psi_n = s_psi[n], psi = s_psi[n - 1];
+        const cplx xi_n = {psi_n, -s_chi[n]};
+        const cplx xi_nm1 = {psi, -s_chi[n - 1]};
         const cplx Dn = s_a[n - 1];
         const double nx = (double)n / x;
         const cplx da = Dn * inv_m + nx;
         const cplx db = m * Dn + nx;
-        const cplx an = (psi_n * da - cplx{psi, 0.0}) / (da * xi_n - xi_nm1);
-        const cplx bn = (psi_n * db - cplx{psi, 0.0}) / (db * xi_n - xi_nm1);
-        s_a[n - 1] = an;
-        s_b[n - 1] = bn;
+        s_a[n - 1] = (psi_n * da - cplx{psi, 0.0}) / (da * xi_n - xi_nm1);
+        s_b[n - 1] = (psi_n * db - cplx{psi, 0.0}) / (db * xi_n - xi_nm1);
+    }
+    __syncthreads();
+    double sum_ext = 0.0, sum_sca = 0.0, sum_g = 0.0;
+    for (int n = tid + 1; n <= N; n += blockDim.x) {
+        const cplx an = s_a[n - 1], bn = s_b[n - 1];
         const double w = 2.0 * n + 1.0;
         sum_ext += w * (an.re + bn.re);
         sum_sca += w * (norm2(an) + norm2(bn));
         // asymmetry: (n-1)(n+1)/n Re(a_{n-1} a_n* + b_{n-1} b_n*) + (2n+1)/(n(n+1)) Re(a_n b_n*)
         if (n > 1) {
+            const cplx ap = s_a[n - 2], bp = s_b[n - 2];
             const double c = (double)(n - 1) * (n + 1) / n;
-            sum_g1 += c * (an_prev.re * an.re + an_prev.im * an.im + bn_prev.re * bn.re + bn_prev.im * bn.im);
+            sum_g += c * (ap.re * an.re + ap.im * an.im + bp.re * bn.re + bp.im * bn.im);
         }
-        sum_g2 += w / ((double)n * (n + 1)) * (an.re * bn.re + an.im * bn.im);
-        an_prev = an;
-        bn_prev = bn;
-        psi_prev = psi;
-        psi = psi_n;
-        chi_prev = chi;
-        chi = chi_n;
+        sum_g += w / ((double)n * (n + 1)) * (an.re * bn.re + an.im * bn.im);
     }
-    const double inv_x2 = 1.0 / (x * x);
-    const double q_ext = 2.0 * inv_x2 * sum_ext;
-    const double q_sca = 2.0 * inv_x2 * sum_sca;
-    *q_ext_out = q_ext;
-    *q_sca_out = q_sca;
-    *g_out = 4.0 * inv_x2 * (sum_g1 + sum_g2) / q_sca;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        sum_ext += __shfl_xor(sum_ext, off, 64);
+        sum_sca += __shfl_xor(sum_sca, off, 64);
+        sum_g += __shfl_xor(sum_g, off, 64);
+    }
+    const int waves = blockDim.x >> 6;
+    if ((tid & 63) == 0) {
+        s_red[3 * (tid >> 6) + 0] = sum_ext;
+        s_red[3 * (tid >> 6) + 1] = sum_sca;
+        s_red[3 * (tid >> 6) + 2] = sum_g;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double e = 0.0, q = 0.0, g = 0.0;
+        for (int w = 0; w < waves; ++w) {
+            e += s_red[3 * w + 0];
+            q += s_red[3 * w + 1];
+            g += s_red[3 * w + 2];
+        }
+        const double inv_x2 = 1.0 / (x * x);
+        const double q_sca = 2.0 * inv_x2 * q;
+        s_sums[0] = 2.0 * inv_x2 * e;
+        s_sums[1] = q_sca;
+        s_sums[2] = 4.0 * inv_x2 * g / q_sca;
+    }
+    __syncthreads();
 }
 
-// Step 2 at one angle: |S1|^2 + |S2|^2 (Eqs. 5-6) with pi_n, tau_n upward.
-__device__ double mie_intensity(double th, int N, const cplx *s_a, const cplx *s_b)
+// Before step 2: fold the angular weight (2n + 1)/(n(n + 1)) of Eqs. 5-6 into
+// a_n and b_n (in place) and tabulate 1/(n - 1) for the pi_n recurrence, so
+// the per-angle loop divides nothing.  Ends with a barrier.
+__device__ void prepare_angular(int N, cplx *s_a, cplx *s_b, double *s_rcp)
 {
-    const double mu = cos(th);
+    for (int n = threadIdx.x + 1; n <= N; n += blockDim.x) {
+        const double c = (2.0 * n + 1.0) / ((double)n * (n + 1));
+        s_a[n - 1] = c * s_a[n - 1];
+        s_b[n - 1] = c * s_b[n - 1];
+        s_rcp[n - 1] = n > 1 ? 1.0 / (double)(n - 1) : 0.0;
+    }
+    __syncthreads();
+}
+
+// Step 2 at one angle: |S1|^2 + |S2|^2 (Eqs. 5-6) with pi_n, tau_n upward,
+// on the coefficients prepared above.
+__device__ double mie_intensity(double th, int N, const cplx *s_a, const cplx *s_b, const double *s_rcp)
+{
+    const double mu = cos_0_pi(th);
     double pi_prev = 0.0, pi_n = 1.0;              // pi_0, pi_1
     cplx S1 = {0.0, 0.0}, S2 = {0.0, 0.0};
     for (int n = 1; n <= N; ++n) {
         if (n > 1) {
-            const double p = ((2.0 * n - 1.0) * mu * pi_n - (double)n * pi_prev) / (double)(n - 1);
+            const double p = ((2.0 * n - 1.0) * mu * pi_n - (double)n * pi_prev) * s_rcp[n - 1];
             pi_prev = pi_n;
             pi_n = p;
         }
         const double tau_n = (double)n * mu * pi_n - (double)(n + 1) * pi_prev;
-        const double c = (2.0 * n + 1.0) / ((double)n * (n + 1));
         const cplx an = s_a[n - 1], bn = s_b[n - 1];
-        S1 = S1 + c * (pi_n * an + tau_n * bn);
-        S2 = S2 + c * (tau_n * an + pi_n * bn);
+        S1 = S1 + (pi_n * an + tau_n * bn);
+        S2 = S2 + (tau_n * an + pi_n * bn);
     }
     return norm2(S1) + norm2(S2);
 }
@@ -142,8 +233,20 @@ __device__ double mie_intensity(double th, int N, const cplx *s_a, const cplx *s
 // Steps 3-4 by the whole workgroup: s_ang holds P sin(theta) on the na-point
 // grid on entry.  Trapezoid CDF by a chunked in-place scan, written back to
 // s_ang (and to cdf_out if given); then each inverse-table entry
-// u_i = i / (nc - 1) finds the first angle with F >= u_i by binary search and
-// interpolates theta linearly, storing v = 1 - cos(theta) = 2 sin^2(theta/2).
+// u_i = i / (nc - 1) finds the first angle with F >= u_i and interpolates
+// theta linearly, storing v = 1 - cos(theta) = 2 sin^2(theta/2).  Each lane
+// takes a run of consecutive entries: it searches the whole grid for the run's
+// first and last entry, and each entry between them only between those two.
+__device__ int first_at_least(const double *f, int l, int r, double u)
+{
+    while (l < r) {
+        const int mid = (l + r) >> 1;
+        if (f[mid] < u) l = mid + 1;
+        else r = mid;
+    }
+    return l;
+}
+
 __device__ void cdf_and_inverse(double *s_ang, double *s_part, double *s_total, int na, int nc, float *inv_cdf,
                                 double *cdf_out)
 {
@@ -186,23 +289,37 @@ __device__ void cdf_and_inverse(double *s_ang, double *s_part, double *s_total, 
     __syncthreads();
     if (cdf_out)
         for (int j = tid; j < na; j += kThreads) cdf_out[j] = s_ang[j];
-    for (int i = tid; i < nc; i += kThreads) {
+    const int per = (nc + kThreads - 1) / kThreads;
+    const int i0 = tid * per, i1 = min(i0 + per, nc);
+    if (i0 >= i1) return;
+    // u <= 1 = F at pi, so only rounding could leave an entry past the grid.
+    const int l_first = min(first_at_least(s_ang, 0, na, (double)i0 / (double)(nc - 1)), na - 1);
+    const int l_last = min(first_at_least(s_ang, l_first, na, (double)(i1 - 1) / (double)(nc - 1)), na - 1);
+    for (int i = i0; i < i1; ++i) {
         const double u = (double)i / (double)(nc - 1);
-        int l = 0, r = na;                 // first j with F_j >= u
-        while (l < r) {
-            const int mid = (l + r) >> 1;
-            if (s_ang[mid] < u) l = mid + 1;
-            else r = mid;
-        }
-        l = min(l, na - 1);                // u <= 1 = F at pi, so only rounding could get here
+        const int l = i == i0 ? l_first : (i == i1 - 1 ? l_last : first_at_least(s_ang, l_first, l_last, u));
         double th = 0.0;
         if (l > 0) {
             const int j = l;
             const double th_j = (double)j * dth, th_p = (double)(j - 1) * dth;
             th = th_p + (u - s_ang[j - 1]) / (s_ang[j] - s_ang[j - 1]) * (th_j - th_p);
         }
-        const double sh = sin(0.5 * th);
+        const double sh = sin_half_pi(0.5 * th);
         inv_cdf[i] = (float)(2.0 * sh * sh);
+    }
+}
+
+// Step 2 over the grid by the whole workgroup: scale x (|S1|^2 + |S2|^2) into
+// phase_out (if given) and, times sin(theta), into s_ang (if given).
+__device__ void phase_grid(int na, int N, double scale, const cplx *s_a, const cplx *s_b, const double *s_rcp,
+                           double *phase_out, double *s_ang)
+{
+    const double dth = M_PI / (double)(na - 1);
+    for (int j = threadIdx.x; j < na; j += blockDim.x) {
+        const double th = (double)j * dth;
+        const double P = scale * mie_intensity(th, N, s_a, s_b, s_rcp);
+        if (phase_out) phase_out[j] = P;
+        if (s_ang) s_ang[j] = P * sin_0_pi(th);
     }
 }
 
@@ -211,25 +328,23 @@ __global__ __launch_bounds__(kThreads) void mie_table_kernel(MieArgs a)
     __shared__ cplx s_a[MC_MAX_TERMS];
     __shared__ cplx s_b[MC_MAX_TERMS];
     __shared__ double s_ang[MC_MAX_N_ANGLES];
+    __shared__ double s_rcp[MC_MAX_TERMS];
     __shared__ double s_part[kBlock];
-    __shared__ double s_qsca;
+    __shared__ double s_red[3 * (kThreads / 64)];
+    __shared__ double s_sums[4];              // Q_ext, Q_sca, g; the CDF's total
 
     const int tid = threadIdx.x;
     const int N = a.n_terms;
     const double x = a.x;
 
-    // ---- 1. series (one lane) ----------------------------------------
+    // ---- 1. series; psi_n and chi_n borrow the angle grid's LDS ----------
+    mie_series_block(x, a.m_re, a.m_im, N, a.n_start, s_a, s_b, s_ang, s_ang + MC_MAX_TERMS + 1, s_red, s_sums);
     if (tid == 0) {
-        double q_ext, q_sca, g;
-        mie_series(x, a.m_re, a.m_im, N, a.n_start, s_a, s_b, &q_ext, &q_sca, &g);
-        s_qsca = q_sca;
-        a.result[0] = q_ext;
-        a.result[1] = q_sca;
-        a.result[2] = g;
+        a.result[0] = s_sums[0];
+        a.result[1] = s_sums[1];
+        a.result[2] = s_sums[2];
         a.result[3] = (double)N;
     }
-    __syncthreads();
-
     if (a.coef) {
         for (int n = tid; n < N; n += kThreads) {
             a.coef[4 * n + 0] = s_a[n].re;
@@ -238,21 +353,16 @@ __global__ __launch_bounds__(kThreads) void mie_table_kernel(MieArgs a)
             a.coef[4 * n + 3] = s_b[n].im;
         }
     }
+    __syncthreads();
+    prepare_angular(N, s_a, s_b, s_rcp);
 
     // ---- 2. phase function on the angle grid, normalised (Eq. 10) -----
-    const int na = a.n_angles;
-    const double dth = M_PI / (double)(na - 1);
-    const double pnorm = 2.0 / (x * x * s_qsca);
-    for (int j = tid; j < na; j += kThreads) {
-        const double th = (double)j * dth;
-        const double P = pnorm * mie_intensity(th, N, s_a, s_b);
-        if (a.phase) a.phase[j] = P;
-        s_ang[j] = P * sin(th);
-    }
+    const double pnorm = 2.0 / (x * x * s_sums[1]);
+    phase_grid(a.n_angles, N, pnorm, s_a, s_b, s_rcp, a.phase, s_ang);
     __syncthreads();
 
     // ---- 3-4. CDF and inverse table ----------------------------------------
-    cdf_and_inverse(s_ang, s_part, &s_qsca, na, a.n_cdf, a.inv_cdf, a.cdf);
+    cdf_and_inverse(s_ang, s_part, &s_sums[3], a.n_angles, a.n_cdf, a.inv_cdf, a.cdf);
 }
 
 // ---- polydisperse: one workgroup per size bin, then the mixture ----------
@@ -275,25 +385,23 @@ __global__ __launch_bounds__(kThreads) void mie_bin_kernel(PolyArgs a)
 {
     __shared__ cplx s_a[MC_MAX_TERMS];
     __shared__ cplx s_b[MC_MAX_TERMS];
-    __shared__ double s_w;
+    __shared__ double s_rec[2 * (MC_MAX_TERMS + 1)];   // psi_n, chi_n
+    __shared__ double s_rcp[MC_MAX_TERMS];
+    __shared__ double s_red[3 * (kThreads / 64)];
+    __shared__ double s_sums[3];
     const int k = blockIdx.x, tid = threadIdx.x;
     const double x = a.x[k];
     const int N = a.n_terms[k];
+    mie_series_block(x, a.m_re, a.m_im, N, a.n_start[k], s_a, s_b, s_rec, s_rec + MC_MAX_TERMS + 1, s_red, s_sums);
     if (tid == 0) {
-        double q_ext, q_sca, g;
-        mie_series(x, a.m_re, a.m_im, N, a.n_start[k], s_a, s_b, &q_ext, &q_sca, &g);
-        a.bins[4 * k + 0] = q_ext;
-        a.bins[4 * k + 1] = q_sca;
-        a.bins[4 * k + 2] = g;
+        a.bins[4 * k + 0] = s_sums[0];
+        a.bins[4 * k + 1] = s_sums[1];
+        a.bins[4 * k + 2] = s_sums[2];
         a.bins[4 * k + 3] = (double)N;
-        // c_k Q_sca,k P_k with P_k = 2 (|S1|^2 + |S2|^2) / (x^2 Q_sca,k): the Q_sca,k cancel.
-        s_w = a.c[k] * 2.0 / (x * x);
     }
-    __syncthreads();
-    const int na = a.n_angles;
-    const double dth = M_PI / (double)(na - 1);
-    for (int j = tid; j < na; j += kThreads)
-        a.rows[(uint64_t)k * na + j] = s_w * mie_intensity((double)j * dth, N, s_a, s_b);
+    prepare_angular(N, s_a, s_b, s_rcp);
+    // c_k Q_sca,k P_k with P_k = 2 (|S1|^2 + |S2|^2) / (x^2 Q_sca,k): the Q_sca,k cancel.
+    phase_grid(a.n_angles, N, a.c[k] * 2.0 / (x * x), s_a, s_b, s_rcp, a.rows + (uint64_t)k * a.n_angles, nullptr);
 }
 
 __global__ __launch_bounds__(kThreads) void mie_mix_kernel(PolyArgs a)
@@ -326,7 +434,7 @@ __global__ __launch_bounds__(kThreads) void mie_mix_kernel(PolyArgs a)
         for (int k = 0; k < a.n_bins; ++k) mix += a.rows[(uint64_t)k * na + j];
         const double P = mix * inv_sca;
         if (a.phase) a.phase[j] = P;
-        s_ang[j] = P * sin((double)j * dth);
+        s_ang[j] = P * sin_0_pi((double)j * dth);
     }
     __syncthreads();
     cdf_and_inverse(s_ang, s_part, &s_sca, na, a.n_cdf, a.inv_cdf, a.cdf);
