@@ -3,7 +3,8 @@ invariants: Beer-Lambert ballistic transmission (Eq. 1), exact per-photon
 energy balance under Eq. 16, a pure absorber, Fresnel identities, the
 orthonormal rotation basis, single-scatter statistics of the free path
 (Eq. 15), polar angle (inverse CDF / Eq. 11) and azimuth (uniform on
-[0, 2 pi)), the detector orientation, and resumability by photon range."""
+[0, 2 pi)), the detector orientation, resumability by photon range, and the
+adjoint's weight score against a common-random-number difference."""
 import math
 
 import numpy as np
@@ -240,6 +241,38 @@ def test_path_length_bounds_displacement(c1_table):
     assert np.all(r.rec("L") >= disp - 1e-9)
     ex = r.rec("cause") == 0
     assert np.all(r.rec("steps")[ex] >= r.rec("k")[ex] + 1)
+
+
+# ------------------------------------------------------- adjoint score
+
+def test_albedo_score_equals_common_random_number_difference(c1_table):
+    # The perturbation Monte Carlo score of the adjoint: at fixed mu_ext a
+    # detected photon's weight is w0 a^k (Eq. 16 applied k times), so
+    # d/da of any linear functional of the side image is sum g w k / a, and
+    # d/da = mu_ext (d/dmu_sca - d/dmu_abs) with the scores k/mu_sca - L and
+    # -L.  Walks at a +- delta with the same draws follow the same
+    # trajectories (the albedo only scales weights), so their central
+    # difference must equal that score sum to O(delta^2 k^2).
+    w = W.TINY.replace(tau=4.0, n_photons=6000)
+    base = owalk.Walk(w, c1_table).run(records=True)
+    delta = 5e-5                                   # albedo 0.9999 +- delta stays at or below 1
+    up = owalk.Walk(w.replace(albedo=w.albedo + delta), c1_table).run(records=True)
+    dn = owalk.Walk(w.replace(albedo=w.albedo - delta), c1_table).run(records=True)
+    for r in (up, dn):
+        np.testing.assert_array_equal(r.irec, base.irec)
+    g = np.random.default_rng(3).normal(size=base.side.shape)
+    fd = (np.sum(g * up.side) - np.sum(g * dn.side)) / (2 * delta)
+    sel = (base.rec("face") == 1) & (base.rec("cause") == 0)
+    n = w.side_px
+    rows = np.clip(np.floor(base.rec("py")[sel] / w.size_mm[1] * n).astype(int), 0, n - 1)
+    cols = np.clip(np.floor(base.rec("pz")[sel] / w.size_mm[2] * n).astype(int), 0, n - 1)
+    score = np.sum(g[rows, cols] * base.rec("w")[sel] * base.rec("k")[sel]) / w.albedo
+    mu_t = w.tau / w.size_mm[2]
+    mu_s, L = w.albedo * mu_t, base.rec("L")[sel]
+    by_coefficients = mu_t * np.sum(g[rows, cols] * base.rec("w")[sel] * ((base.rec("k")[sel] / mu_s - L) + L))
+    assert sel.sum() > 200
+    assert fd == pytest.approx(score, rel=1e-4)
+    assert by_coefficients == pytest.approx(score, rel=1e-12)
 
 
 # -------------------------------------------------------------- resume
