@@ -187,16 +187,16 @@ def test_corrected_l2_gradient_matches_crn_differences(mc, cuda_device):
 @pytest.mark.parametrize("exit_log", [False, True])
 def test_autograd_fits_optical_depth_to_a_lateral_image(mc, cuda_device, exit_log):
     """20 Adam steps on tau through torch.autograd (side_l2_loss), 1e7 photons
-    per evaluation, 128 x 128 lateral image, from tau = 4 towards the target
+    per evaluation, 512 x 512 lateral image, from tau = 4 towards the target
     made at tau = 4.5 with seed 99, with image exits tallied by atomics or
     through the exit log (one workspace shared by all walks).  Adam's step is
     nearly independent of the gradient's scale; betas (0.5, 0.9) and rate 0.1
     settle within 1e-3 of the optimum of a quadratic 0.5 away in 20 steps."""
     import torch
-    w = W.DIFF.replace(side_px=128, trans_px=128)
+    w = W.DIFF
     spec, *_ = mc.args_from_workload(w)
     table = mc.mie_table_build(spec, cuda_device)
-    target = gpu_run(W.DIFF_TARGET.replace(side_px=128, trans_px=128), table=table, sigma=False)["tally"].side
+    target = gpu_run(W.DIFF_TARGET, table=table, sigma=False)["tally"].side
     _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=mc.MC_EXIT_LOG if exit_log else 0)
     sim = mc.SideImage(med, src, geo, det, run, cuda_device)
     L = w.size_mm[2]

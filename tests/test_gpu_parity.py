@@ -148,14 +148,20 @@ def test_trajectory_parity_variants(mc, cuda_device, kw):
     assert image_within_3sigma(g["trans"], o.trans, o.trans_w2, w.n_photons, max_w=10.0).all()
 
 
-def test_full_size_sampled_trajectories(mc, cuda_device):
-    """Headline workload at full size, default launch shape: every 50 000th
-    photon is recorded and replayed one by one in the oracle."""
-    w = W.HEADLINE
+PAPER_SCALE = [(1.0, W.PHASE_MIE), (2.0, W.PHASE_MIE), (4.0, W.PHASE_MIE), (8.0, W.PHASE_MIE), (4.0, W.PHASE_HG)]
+
+
+@pytest.mark.parametrize("tau,phase", PAPER_SCALE, ids=lambda v: str(v))
+def test_full_size_sampled_trajectories(mc, cuda_device, tau, phase):
+    """Every paper-scale workload (tau 1, 2, 4, 8 with the Mie table and the
+    HG run with g = g_Mie; 1e8 photons, 16384-entry table, 512 x 512 images)
+    at full size in the default launch shape: every 50 000th photon is
+    recorded and replayed one by one in the oracle."""
+    w = W.paper_scale(tau, phase=phase)
     stride = 50_000
     g = gpu_run(w, records=True, record_stride=stride, sigma=False)
     ids = np.arange(0, w.n_photons, stride, dtype=np.uint64)
-    o = _oracle(w, ids=ids)
+    o = _oracle(w, ids=ids, g=None if phase == W.PHASE_MIE else mie.table_from_workload(w).g)
     ok = trajectory_match(g["rec"], oracle_rec(o), box=10.0)
     assert ok.mean() >= 0.999, ok.mean()
     s = g["scalars"]

@@ -129,10 +129,10 @@ def batch_instances(n: int = 256, seed: int = 2507) -> List[BatchInstance]:
             for a, b, c, e in zip(d, tau, alb, nph)]
 
 
-# Batched media share the cuvette, beam and detector of the parity workload
-# (4096-entry tables, 128 x 128 images); instance i draws Philox counter word
-# 1 = i.
-BATCH_BASE = Workload(name="batch", tau=1.0, n_cdf=4096, side_px=128, trans_px=128, n_photons=0)
+# Batched media share the cuvette and beam of the parity workload, with
+# 4096-entry tables and their own 256 x 256 lateral (and transmitted) images;
+# instance i draws Philox counter word 1 = i.
+BATCH_BASE = Workload(name="batch", tau=1.0, n_cdf=4096, side_px=256, trans_px=256, n_photons=0)
 
 
 def batch_workloads(n: int = 256, seed: int = 2507, photon_scale: float = 1.0) -> List[Workload]:
