@@ -379,9 +379,12 @@ int mc_autotune_batch(const mc_batch_item_t *items, uint32_t n_items, int32_t n_
  * out_grad[2] = sigma_sca out_grad[0] + sigma_abs out_grad[1], the derivative
  * with respect to the particle concentration c in 1/mm^3 (Eq. 17, with
  * mu_sca = c sigma_sca and mu_abs = mu_abs,medium + c sigma_abs; NaN when both
- * sigmas are 0).  The dot products run in one device workgroup (fixed order,
- * deterministic); the call waits for the stream.  Roulette's dependence on
- * the weight threshold is not differentiated.
+ * sigmas are 0).  The dot products run on the device in a fixed order
+ * (deterministic), with the tally's workspace beyond its scalar words as
+ * scratch (it holds mc_simulate's image copies, consumed by then; a walk
+ * sharing that workspace must not run concurrently).  The call waits for the
+ * stream.  Roulette's dependence on the weight threshold is not
+ * differentiated.
  */
 int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry, const mc_detector_t *detector,
             const mc_tally_t *tally, const double *dloss_dside, const double *d2loss_dside2,

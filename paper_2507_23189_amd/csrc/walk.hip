@@ -941,15 +941,19 @@ __global__ void philox_blocks_kernel(uint32_t k0, uint32_t k1, uint32_t instance
 }
 
 // sum_p g_p M_k[p], sum_p g_p M_L[p] and, with per-pixel h, sum_p h_p M2_k[p]
-// and sum_p h_p M2_L[p], in one workgroup (fixed order, deterministic); with a
-// uniform h instead, h times the image-wide second moments.
-__global__ __launch_bounds__(1024) void grad_dot(const double *g, const double *h, const double *wk,
-                                                 const double *wl, const double *w2k, const double *w2l,
-                                                 uint64_t n, double h_uniform, const double *scalars, double *out)
+// and sum_p h_p M2_L[p], in two passes with a fixed order (deterministic):
+// block b of grad_partial sums pixels b x 1024 + t + j x (gridDim x 1024) per
+// lane t, then over the block by a fixed tree, into part[4 b .. 4 b + 3];
+// grad_final adds the blocks' partials in block order.  With a uniform h
+// instead, h times the image-wide second moments.
+__global__ __launch_bounds__(1024) void grad_partial(const double *g, const double *h, const double *wk,
+                                                     const double *wl, const double *w2k, const double *w2l,
+                                                     uint64_t n, double *part)
 {
     __shared__ double s_red[4][1024];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         acc[0] = fma(g[i], wk[i], acc[0]);
         acc[1] = fma(g[i], wl[i], acc[1]);
         if (h) {
@@ -964,12 +968,18 @@ __global__ __launch_bounds__(1024) void grad_dot(const double *g, const double *
             for (int c = 0; c < 4; ++c) s_red[c][threadIdx.x] += s_red[c][threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x < 4) {
-        double v = s_red[threadIdx.x][0];
-        if (!h && threadIdx.x >= 2)
-            v = h_uniform != 0.0 ? h_uniform * scalars[threadIdx.x == 2 ? MC_S_SIDE_W2K : MC_S_SIDE_W2L] : 0.0;
-        out[threadIdx.x] = v;
-    }
+    if (threadIdx.x < 4) part[4 * (uint64_t)blockIdx.x + threadIdx.x] = s_red[threadIdx.x][0];
+}
+
+__global__ void grad_final(const double *part, uint32_t n_blocks, bool per_pixel_h, double h_uniform,
+                           const double *scalars, double *out)
+{
+    if (threadIdx.x >= 4) return;
+    double v = 0.0;
+    for (uint32_t b = 0; b < n_blocks; ++b) v += part[4 * (uint64_t)b + threadIdx.x];
+    if (!per_pixel_h && threadIdx.x >= 2)
+        v = h_uniform != 0.0 ? h_uniform * scalars[threadIdx.x == 2 ? MC_S_SIDE_W2K : MC_S_SIDE_W2L] : 0.0;
+    out[threadIdx.x] = v;
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -1566,17 +1576,25 @@ extern "C" int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry,
         return fail(MC_EINVAL, "mc_grad: d2loss_uniform must be finite");
     if (d2loss_dside2 && d2loss_uniform != 0.0)
         return fail(MC_EINVAL, "mc_grad: give either d2loss_dside2 or d2loss_uniform, not both");
-    if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < kWsScalarWords * 8)
+    if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < (kWsScalarWords + 4) * 8)
         return fail(MC_EINVAL, "mc_grad: workspace of at least %llu bytes required",
-                    (unsigned long long)(kWsScalarWords * 8));
+                    (unsigned long long)((kWsScalarWords + 4) * 8));
     const double mu_t = m.tau / geo.size_mm[2];
     const double mu_s = m.albedo * mu_t;
     hipStream_t st = (hipStream_t)stream;
     double *dots = (double *)t.workspace + 24;    // scalar words 24..27
     const uint64_t n = (uint64_t)det.side_nx * det.side_ny;
-    hipLaunchKernelGGL(grad_dot, dim3(1), dim3(1024), 0, st, dloss_dside, d2loss_dside2, (const double *)t.side_wk,
-                       (const double *)t.side_wl, (const double *)t.side_w2k, (const double *)t.side_w2l, n,
-                       d2loss_uniform, (const double *)t.scalars, dots);
+    // The blocks' partials go after the scalar words, where mc_simulate keeps
+    // its image copies (consumed by then): one block per 8192 pixels, at most
+    // 256, and no more than the workspace holds.
+    double *part = (double *)t.workspace + kWsScalarWords;
+    const uint64_t room = t.workspace_bytes / 8 - kWsScalarWords;
+    const uint32_t n_blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({256, (n + 8191) / 8192, room / 4}));
+    hipLaunchKernelGGL(grad_partial, dim3(n_blocks), dim3(1024), 0, st, dloss_dside, d2loss_dside2,
+                       (const double *)t.side_wk, (const double *)t.side_wl, (const double *)t.side_w2k,
+                       (const double *)t.side_w2l, n, part);
+    hipLaunchKernelGGL(grad_final, dim3(1), dim3(64), 0, st, (const double *)part, n_blocks,
+                       d2loss_dside2 != nullptr, d2loss_uniform, (const double *)t.scalars, dots);
     MC_HIP_CHECK(hipGetLastError());
     double d[4];
     MC_HIP_CHECK(hipMemcpyAsync(d, dots, sizeof d, hipMemcpyDeviceToHost, st));

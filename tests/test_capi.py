@@ -222,6 +222,11 @@ def test_mc_grad_validates():
     assert rc == mc.MC_EINVAL and b"not both" in mc.lib().mc_last_error()
     rc = g(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, None, float("inf"), out, None)
     assert rc == mc.MC_EINVAL
+    # the dot products' partials need the workspace past its 32 scalar words
+    tal.workspace_bytes = 32 * 8
+    rc = g(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, None, 0.0, out, None)
+    assert rc == mc.MC_EINVAL and b"workspace" in mc.lib().mc_last_error()
+    tal.workspace_bytes = mc.mc_workspace_bytes(det)
     med.tau = 0.0
     rc = g(C.byref(med), C.byref(geo), C.byref(det), C.byref(tal), 0x1000, None, 0.0, out, None)
     assert rc == mc.MC_EINVAL
