@@ -20,23 +20,27 @@
 //
 // Transport runs in FP32.  Weights are tallied in 64-bit fixed point
 // (weight * 2^32, rounded to nearest): integer sums do not depend on the order
-// in which photons finish, so results are bit-identical for any launch shape.
-// Exits go through a
-// per-block LDS tally cache: a direct-mapped table of pixel ids (claimed with
-// an LDS compare-and-swap, first come first served) whose FP64 sums are
-// flushed to the images once per block.  The pencil beam sends every
-// unscattered photon to the same transmitted pixel, and same-address global
-// atomics serialise across the chip, so without the cache that one pixel
-// bounds the whole launch.  Pixels that miss the cache (slot held by another
-// pixel) fall back to a global atomic into one of eight per-XCD copies of the
-// images in the caller's workspace (contention on the warm pixels around the
-// beam is then spread over eight addresses); a finalize pass sums the copies
-// and converts to the caller's images.  Exits are first queued per wave in
-// LDS and tallied 64 at a time by the whole wave, so the pixel arithmetic and
-// atomics run with full lanes instead of on the few lanes that exit in any
-// one step.  Scalar tallies use LDS atomics and lane accumulators, also
-// flushed once per block.  The kernel is specialised at compile time on the
-// phase function, the squared-weight tally and per-photon records.
+// in which photons finish, so results are bit-identical for any launch shape
+// and for either tally path.  Exits through the imaged faces are first queued
+// per wave in LDS and handled 64 at a time by the whole wave, so the pixel
+// arithmetic runs with full lanes instead of on the few lanes that exit in
+// any one step.  A flush then either
+//   * appends them to the exit log (MC_EXIT_LOG): each wave owns a fixed set
+//     of chunks in each of 64 key ranges and appends with one LDS add per
+//     exit; a second kernel (log_bin) sums each range in an LDS histogram and
+//     adds the sums into per-XCD copies of the images with plain stores; or
+//   * adds them into a per-block LDS tally cache (direct-mapped pixel ids
+//     claimed with an LDS compare-and-swap) whose sums go to the images once
+//     per block, with a global atomic into one of eight per-XCD copies of the
+//     images for the pixels that miss the cache.
+// On gfx950 every global image atomic is performed at the memory side, so the
+// log, which needs none, is the faster path.  Unscattered photons all leave
+// through one pixel with one weight and are only counted.  A finalize pass
+// sums the copies in integer arithmetic and converts to the caller's images.
+// Scalar tallies use LDS atomics and lane accumulators, flushed once per
+// block.  The kernel is specialised at compile time on the phase function,
+// the squared-weight tally, per-photon records, path moments, batching and
+// the exit log.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -174,11 +178,12 @@ constexpr int kOptSigma = 1, kOptRecord = 2, kOptMoments = 4, kOptBatch = 8, kOp
 // Exit log: image exits appended as (key << 32 | weight bits) to chunks of
 // kLogChunk entries.  Keys fall into kLogBuckets ranges; in each range's
 // region every wave of the launch owns log_chunks chunks, which it fills in
-// turn (no claim, no global atomic).  Keys go to ranges by groups of eight (one 64-byte line of a tally
-// copy): the group g is scrambled by p = g * kLogHashMul mod 2^bits (odd
-// multiplier, so a bijection), its top six bits pick the range and the rest,
-// with the key's place in its group, index the key within the range.  Bright
-// spots of an image thus spread evenly over the ranges.
+// turn (no claim, no global atomic).  Keys go to ranges by groups of eight
+// (one 64-byte line of a tally copy): the group g is scrambled by
+// p = g * kLogHashMul mod 2^bits (an odd multiplier, so a bijection), its top
+// six bits pick the range and the rest, with the key's place in its group,
+// index the key within the range.  Bright spots of an image thus spread
+// evenly over the ranges.
 constexpr uint32_t kLogChunk = 64;
 constexpr uint32_t kLogBuckets = 64;
 constexpr uint32_t kLogMaxChunks = 255;    // chunks per wave and range (an 8-bit cursor field)
