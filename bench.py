@@ -6,7 +6,8 @@ table build on the device (series, phase function, CDF, inverse table) and
 the photon walk of 1e8 photons through a 10 mm water cube holding 5 um
 polystyrene spheres at optical depth 4 (Philox seed 1234, 16384-entry inverse
 CDF, 512 x 512 side and transmitted images).  `value` is scatter events per
-second over the timed steps, inputs resident on the device.
+second over the timed steps, inputs resident on the device.  Image exits go
+through the exit log (MC_EXIT_LOG) unless --atomic-tally is given.
 
 The JSON line also carries
   roofline      the walk kernel's achieved issue rate from an operation census
