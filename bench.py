@@ -80,8 +80,8 @@ PEAK_SLOTS_PER_S = 256 * 64 * 2.4e9
 # what the same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0); valid only for the tally path and kernel sources it was
 # measured on (profiles/walk_tau4_counters.md).
-TRAFFIC = {"tally": "log", "sources_sha256": "f33c1d318c09c3c73128ffa949286d2567309dce8cf8c774e171a72b535b5c5a",
-           "fetch_kib": 398.4, "write_kib": 1825990.0, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"tally": "log", "sources_sha256": "eed80fb04f0405b441efce54caeeda4e81df6290ca3b780ff3141778ba4f008d",
+           "fetch_kib": 386.2, "write_kib": 1828495.0, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 
