@@ -131,18 +131,22 @@ __device__ __forceinline__ int pixel(float coord, float size, int n)
 }
 
 // Distance to the nearest wall along d and its axis (ties go to the lower
-// axis).  Per axis t = (L - p) / |d| moving up, p / |d| moving down; an axis
-// with d = 0 is never hit; t is clamped at 0 so a position that rounding left
-// a hair outside the box is taken back at once.
+// axis).  Per axis, with r = 1/d, the walls at L and at 0 lie (L - p) r and
+// -p r ahead; for p inside the box one of the two is negative, so the larger
+// is the wall the photon moves towards.  It is clamped at 0, so a position
+// that rounding left a hair outside the box is taken back at once.  An axis
+// with d = 0 gives r = inf and so t = inf: it is never hit (short of a
+// position exactly on one of its walls, where 0 x inf makes the far term NaN,
+// the maximum drops it and t is 0; the host keeps the source off that case).
+// No compare or select: three full-rate operations and one three-way maximum
+// per axis.
 __device__ __forceinline__ float wall_distance(float px, float py, float pz, float dx, float dy, float dz,
                                                float Lx, float Ly, float Lz, int &axis)
 {
-    float tx = (dx > 0.f ? Lx - px : px) * __builtin_amdgcn_rcpf(fabsf(dx));
-    float ty = (dy > 0.f ? Ly - py : py) * __builtin_amdgcn_rcpf(fabsf(dy));
-    float tz = (dz > 0.f ? Lz - pz : pz) * __builtin_amdgcn_rcpf(fabsf(dz));
-    tx = dx == 0.f ? __builtin_huge_valf() : fmaxf(tx, 0.f);
-    ty = dy == 0.f ? __builtin_huge_valf() : fmaxf(ty, 0.f);
-    tz = dz == 0.f ? __builtin_huge_valf() : fmaxf(tz, 0.f);
+    const float rx = __builtin_amdgcn_rcpf(dx), ry = __builtin_amdgcn_rcpf(dy), rz = __builtin_amdgcn_rcpf(dz);
+    const float tx = fmaxf(fmaxf((Lx - px) * rx, -px * rx), 0.f);
+    const float ty = fmaxf(fmaxf((Ly - py) * ry, -py * ry), 0.f);
+    const float tz = fmaxf(fmaxf((Lz - pz) * rz, -pz * rz), 0.f);
     float db = tx;
     axis = 0;
     if (ty < db) { db = ty; axis = 1; }
@@ -393,6 +397,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // otherwise these stay the launch's values).
     uint32_t l_slot = kEmpty, q_p = 0;
     float l_mu = a.neg_ln2_over_mu, l_alb = a.albedo, l_abs = a.absorb;
+    // FP32 operations with a scalar-register operand issue at half the rate
+    // of those whose operands are all vector registers; the constants of the
+    // step therefore live in vector registers (the empty asm hides that they
+    // are wave-uniform) where the kernel has eight to spare: not with path
+    // moments or batched media, which need those registers themselves.
+    float v_lx = a.size[0], v_ly = a.size[1], v_lz = a.size[2], v_n21 = a.n21, v_n12sq = a.n12sq;
+    if (!MOMENTS && !BATCH) {
+        asm volatile("" : "+v"(l_mu), "+v"(l_alb), "+v"(l_abs));
+        asm volatile("" : "+v"(v_lx), "+v"(v_ly), "+v"(v_lz), "+v"(v_n21), "+v"(v_n12sq));
+    }
     const float *l_tab = a.inv_cdf;
     uint32_t l_ctr = a.instance;
     // Batched: move the lane accumulators into the LDS scalars of its medium.
@@ -584,29 +598,29 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             ++step;
 
             // Nearest wall along the direction.
-            const float db = wall_distance(px, py, pz, dx, dy, dz, a.size[0], a.size[1], a.size[2], axis);
+            const float db = wall_distance(px, py, pz, dx, dy, dz, v_lx, v_ly, v_lz, axis);
 
             const bool hit = s >= db;
             const float t = hit ? db : s;
             px = fmaf(t, dx, px); py = fmaf(t, dy, py); pz = fmaf(t, dz, pz);
             L += t;
             if (hit) {
-                // Boundary: snap onto the wall, then reflect (u3 < R) or leave.
+                // Boundary: clamp into the box (a move that overshot the wall
+                // by rounding lands on it), then reflect (u3 < R) or leave.
                 // Written as selects so the wave runs it without branches.
                 const bool on_x = axis == 0, on_y = axis == 1, on_z = axis == 2;
                 const float da = on_x ? dx : (on_y ? dy : dz);
                 const bool pos_side = da > 0.f;
-                const float wall = pos_side ? (on_x ? a.size[0] : (on_y ? a.size[1] : a.size[2])) : 0.f;
-                px = on_x ? wall : px;
-                py = on_y ? wall : py;
-                pz = on_z ? wall : pz;
+                px = __builtin_amdgcn_fmed3f(px, 0.f, v_lx);
+                py = __builtin_amdgcn_fmed3f(py, 0.f, v_ly);
+                pz = __builtin_amdgcn_fmed3f(pz, 0.f, v_lz);
                 float R = 0.f;
                 if (!a.matched) {
                     const float ci = fabsf(da);
-                    const float st2 = a.n12sq * fmaf(-ci, ci, 1.f);
+                    const float st2 = v_n12sq * fmaf(-ci, ci, 1.f);
                     const float ct = __builtin_amdgcn_sqrtf(fmaxf(1.f - st2, 0.f));
-                    const float rs = (ci - a.n21 * ct) * __builtin_amdgcn_rcpf(ci + a.n21 * ct);
-                    const float rp = (a.n21 * ci - ct) * __builtin_amdgcn_rcpf(a.n21 * ci + ct);
+                    const float rs = (ci - v_n21 * ct) * __builtin_amdgcn_rcpf(ci + v_n21 * ct);
+                    const float rp = (v_n21 * ci - ct) * __builtin_amdgcn_rcpf(v_n21 * ci + ct);
                     R = st2 >= 1.f ? 1.f : 0.5f * fmaf(rs, rs, rp * rp);
                 }
                 const bool refl = u3 < R;
@@ -661,7 +675,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                     const float qx = fmaf(cp, e1x, sp * e2x), qy = fmaf(cp, e1y, sp * e2y),
                                 qz = fmaf(cp, e1z, sp * e2z);
                     const float nx = fmaf(ct, dx, st * qx), ny = fmaf(ct, dy, st * qy), nz = fmaf(ct, dz, st * qz);
-                    const float inv = __builtin_amdgcn_rsqf(fmaf(nx, nx, fmaf(ny, ny, nz * nz)));
+                    // |n|^2 is 1 up to rounding, so one Newton step of 1/sqrt from 1
+                    // (1.5 - |n|^2 / 2) renormalises to within 1e-13.
+                    const float inv = fmaf(-0.5f, fmaf(nx, nx, fmaf(ny, ny, nz * nz)), 1.5f);
                     dx = nx * inv; dy = ny * inv; dz = nz * inv;
                 }
             }
@@ -1031,6 +1047,17 @@ int check_geometry(const char *fn, const mc_geometry_t &geo)
     return MC_OK;
 }
 
+// Component i of the beam direction inside the medium (refracted at the
+// z = 0 face, Snell), as the walk gets it: FP32, a zero always +0.
+float entry_dir(const mc_source_t &src, const mc_geometry_t &geo, int i)
+{
+    const double dl = std::sqrt(src.dir[0] * src.dir[0] + src.dir[1] * src.dir[1] + src.dir[2] * src.dir[2]);
+    const double eta = geo.n_outside / geo.n_medium;
+    double d[3] = {eta * (src.dir[0] / dl), eta * (src.dir[1] / dl), 0.0};
+    d[2] = std::sqrt(std::max(0.0, 1.0 - d[0] * d[0] - d[1] * d[1]));
+    return (float)d[i] + 0.0f;
+}
+
 // Checks of the source, detector, tally buffers and run settings shared by
 // single and batched walks.
 int check_setup(const char *fn, const mc_source_t &src, const mc_geometry_t &geo, const mc_detector_t &det,
@@ -1048,6 +1075,14 @@ int check_setup(const char *fn, const mc_source_t &src, const mc_geometry_t &geo
     if (R > 0.0 && (src.pos_mm[0] - R < 0.0 || src.pos_mm[0] + R > geo.size_mm[0] || src.pos_mm[1] - R < 0.0 ||
                     src.pos_mm[1] + R > geo.size_mm[1]))
         return fail(MC_EINVAL, "%s: the beam disk must lie inside the z = 0 face", fn);
+    // A photon exactly on a side wall with no direction component across it
+    // would meet that wall at distance 0 (the walk's wall distance has no
+    // zero-component test): keep the entry points off the far side walls
+    // when the refracted beam runs parallel to them.
+    for (int i = 0; i < 2; ++i)
+        if (entry_dir(src, geo, i) == 0.f && (float)src.pos_mm[i] + (float)R >= (float)geo.size_mm[i])
+            return fail(MC_EINVAL, "%s: the beam must not run along the face %s = %g", fn, i ? "y" : "x",
+                        geo.size_mm[i]);
     if (R > 0.0 && rn.max_steps == 0xFFFFFFFFu)
         return fail(MC_EINVAL, "%s: a finite beam reserves step counter 2^32 - 1 (max_steps must be lower)", fn);
     if (!dims_ok(det)) return fail(MC_EINVAL, "%s: image dimensions must be >= 1", fn);
@@ -1090,9 +1125,6 @@ void fill_common(WalkArgs &a, const mc_source_t &src, const mc_geometry_t &geo, 
     a.n12sq = (float)((geo.n_medium / geo.n_outside) * (geo.n_medium / geo.n_outside));
     const double dl = std::sqrt(src.dir[0] * src.dir[0] + src.dir[1] * src.dir[1] + src.dir[2] * src.dir[2]);
     double din[3] = {src.dir[0] / dl, src.dir[1] / dl, src.dir[2] / dl};
-    const double eta = geo.n_outside / geo.n_medium;
-    double d0[3] = {eta * din[0], eta * din[1], 0.0};
-    d0[2] = std::sqrt(std::max(0.0, 1.0 - d0[0] * d0[0] - d0[1] * d0[1]));
     double R0 = 0.0;
     if (!a.matched) {
         const double n1 = geo.n_outside, n2 = geo.n_medium, ci = din[2];
@@ -1108,7 +1140,7 @@ void fill_common(WalkArgs &a, const mc_source_t &src, const mc_geometry_t &geo, 
     }
     for (int i = 0; i < 3; ++i) {
         a.pos0[i] = (float)src.pos_mm[i];
-        a.dir0[i] = (float)d0[i];
+        a.dir0[i] = entry_dir(src, geo, i);
     }
     a.w0 = (float)(1.0 - R0);
     a.beam_radius = (float)src.beam_radius_mm;

@@ -385,6 +385,31 @@ def test_finite_beam_validation():
     assert call() == mc.MC_EINVAL and b"reserves" in mc.lib().mc_last_error()
 
 
+def test_beam_along_a_far_side_face_is_rejected():
+    """A beam whose refracted direction has no x (or y) component may not
+    enter on the x = size (y = size) edge of the z = 0 face: the walk's wall
+    distance has no zero-component test and would meet that wall at once."""
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, med, src, geo, det, run = _valid_args()
+    tal = _tally_stub(det)
+
+    def call():
+        return mc.lib().mc_simulate(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                                    C.byref(tal), None)
+    src.dir[0], src.dir[1], src.dir[2] = 0.0, 0.0, 1.0
+    for axis in (0, 1):
+        src.pos_mm[0], src.pos_mm[1] = 5.0, 5.0
+        src.pos_mm[axis] = geo.size_mm[axis]
+        assert call() == mc.MC_EINVAL and b"must not run along" in mc.lib().mc_last_error()
+    src.pos_mm[0], src.pos_mm[1] = geo.size_mm[0], 5.0
+    src.dir[0] = 1e-50                                   # rounds to a zero FP32 component
+    assert call() == mc.MC_EINVAL and b"must not run along" in mc.lib().mc_last_error()
+    src.dir[0] = 0.0
+    src.pos_mm[0], src.beam_radius_mm = 5.0, 5.0         # the disk reaches x = size
+    assert call() == mc.MC_EINVAL and b"must not run along" in mc.lib().mc_last_error()
+
+
 def test_metrics_work_size_and_validation():
     import math
     import paper_2507_23189_amd as mc

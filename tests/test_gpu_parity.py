@@ -137,6 +137,7 @@ def test_tiny_workload_trajectories_and_images(mc, cuda_device, phase):
     dict(tau=3.0, n_photons=12345, side_px=3, trans_px=5, size_mm=(4.0, 7.0, 10.0),
          src_pos_mm=(1.0, 2.0, 0.0), src_dir=(0.3, -0.2, 0.9)),            # ragged, oblique beam
     dict(tau=8.0, max_steps=4, n_photons=5000),                            # step cap
+    dict(tau=2.0, n_photons=5000, src_pos_mm=(0.0, 0.0, 0.0), src_dir=(-0.0, 0.0, 1.0)),  # along an edge
 ])
 def test_trajectory_parity_variants(mc, cuda_device, kw):
     w = W.TINY.replace(**kw)
