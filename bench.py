@@ -12,9 +12,10 @@ through the exit log (MC_EXIT_LOG) unless --atomic-tally is given.
 The JSON line also carries
   roofline      the walk kernel's achieved issue rate from an operation census
                 of the method (counts of steps, interactions, boundary steps
-                and exits, each priced in FP32 VALU issue slots) over its
-                measured average duration (HIP events on the launch stream),
-                against the chip's FP32 VALU issue peak;
+                and exits, each priced in full-rate FP32 VALU issue slots by
+                instruction class) over its measured average duration (HIP
+                events on the launch stream), against the chip's FP32 VALU
+                peak (the published 157.3 TFLOP/s as fused multiply-adds);
   cpu_baseline  the FP64 oracle timed on this host on a bounded sample of the
                 same workload;
   adjoint       after the timed steps, the same walk run forward only
@@ -58,22 +59,45 @@ if ROOT not in sys.path:
 
 METRIC = "Mie MC scatter events/s (τ=4, 1e8 photons); fwd+adjoint vs fwd-only time"
 
-# Issue slots per unit of work, counted from the walk's arithmetic as the
-# fewest gfx950 VALU instructions that perform it (each FP32/INT32 operation,
-# transcendental, 32x32->64-bit product or three-input XOR is one slot: the
-# SQ counters show each such VALU instruction occupying one issue slot).
-#   step         Philox4x32-10 (20 products, 20 XOR3), four uniforms, free path,
-#                distances to the three walls and the nearest one, move   = 91
-#   interaction  weight update and roulette test, inverse-CDF lookup and
-#                interpolation, sin/cos of both angles, orthonormal basis,
-#                new direction and its renormalisation                     = 49
-#   boundary     wall component, snap, unpolarised Fresnel with TIR,
-#                reflect-or-leave                                          = 31
-#   exit         face total; for the imaged faces also pixel row/column
-#                (IEEE divide), pixel key and tally-cache slot            = 40 / 2
-CENSUS = {"step": 91, "interaction": 49, "boundary": 31, "imaged_exit": 40, "other_exit": 2}
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock at the 2.4 GHz peak engine clock.
-PEAK_SLOTS_PER_S = 256 * 64 * 2.4e9
+# Operation census: the fewest gfx950 VALU instructions that perform the
+# walk's arithmetic per unit of work, by issue class.  gfx950 issues a wave64
+# full-rate instruction (FP32 add/mul/fma, 32-bit integer add, and/or/xor,
+# move, all operands in vector registers) in 2 SIMD cycles, half-rate ones
+# (compares, selects, min/max/med3, shifts, conversions, 32x32-bit products
+# including v_mad_u64_u32, three-input bit operations) in 4, transcendentals
+# (rcp, sqrt, log, sin, cos) in 8; measured by issue_cost_probe.hip at 2.3-2.6,
+# 3.7-4.4 and 8.0-8.2 cycles.  A slot is one full-rate lane-instruction, so a
+# unit costs full + 2 half + 4 trans slots.
+#   step         Philox4x32-10 (20 products, 20 three-input XORs), the free-path
+#                uniform and its log, three wall distances (reciprocal, two
+#                products and a three-way maximum each), nearest wall (min3),
+#                hit test and step length, move, step count
+#   interaction  weight, absorption and event count, roulette test, two
+#                uniforms, inverse-CDF index, fraction and lerp, cos and
+#                sin of the polar angle, sin and cos of the azimuth, the
+#                orthonormal basis (Duff et al.), new direction, Newton
+#                renormalisation
+#   boundary     the reflection uniform, wall axis and its direction component,
+#                clamp onto the box, unpolarised Fresnel with TIR, reflect-or-
+#                leave, exit face and reflection count
+#   exit         imaged faces: pixel row and column (scale, floor, clamp), key,
+#                weight added; other faces: face total
+CENSUS = {"step": {"full": 17, "half": 47, "trans": 4},
+          "interaction": {"full": 41, "half": 7, "trans": 4},
+          "boundary": {"full": 14, "half": 18, "trans": 3},
+          "imaged_exit": {"full": 3, "half": 5, "trans": 0},
+          "other_exit": {"full": 2, "half": 0, "trans": 0}}
+SLOTS_PER_CLASS = {"full": 1, "half": 2, "trans": 4}
+
+
+def unit_slots(unit: str) -> int:
+    return sum(SLOTS_PER_CLASS[k] * n for k, n in CENSUS[unit].items())
+
+
+# MI355X: 256 CUs x 4 SIMDs x 32 full-rate FP32 lanes per clock at the
+# 2.4 GHz peak engine clock: the published 157.3 TFLOP/s FP32 vector rate
+# counted as fused multiply-adds.
+PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 
 # HBM traffic of one walk_kernel launch on this workload with the exit log,
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by
@@ -115,8 +139,9 @@ def census_slots(scal):
     exits = photons - scal[11] - scal[12]
     faces = scal[0:6]
     imaged = exits * (faces[1] + faces[5]) / max(faces.sum(), 1e-300)
-    return (CENSUS["step"] * steps + CENSUS["interaction"] * events + CENSUS["boundary"] * (steps - events)
-            + CENSUS["imaged_exit"] * imaged + CENSUS["other_exit"] * (exits - imaged))
+    return (unit_slots("step") * steps + unit_slots("interaction") * events
+            + unit_slots("boundary") * (steps - events)
+            + unit_slots("imaged_exit") * imaged + unit_slots("other_exit") * (exits - imaged))
 
 
 def cpu_baseline(w, target_s: float):

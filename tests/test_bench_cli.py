@@ -29,12 +29,22 @@ def test_census_prices_each_unit_of_work():
     s = np.zeros(20)
     s[14], s[9], s[10], s[11] = 6.0, 4.0, 2.0, 1.0
     s[5] = 0.9                                     # all exit weight through +z
-    c = bench.CENSUS
+    c = {u: bench.unit_slots(u) for u in bench.CENSUS}
     expect = 6 * c["step"] + 4 * c["interaction"] + 2 * c["boundary"] + 1 * c["imaged_exit"]
     assert bench.census_slots(s) == pytest.approx(expect)
     # The same exit through a face without an image costs the cheap exit.
     s[5], s[0] = 0.0, 0.9
     assert bench.census_slots(s) == pytest.approx(expect - c["imaged_exit"] + c["other_exit"])
+
+
+def test_census_classes_and_peak():
+    # Half-rate instructions take two full-rate slots, transcendentals four;
+    # a step is dominated by Philox's 20 products and 20 three-input XORs.
+    assert bench.SLOTS_PER_CLASS == {"full": 1, "half": 2, "trans": 4}
+    assert bench.CENSUS["step"]["half"] >= 40
+    assert bench.unit_slots("step") == 17 + 2 * 47 + 4 * 4
+    # The peak is the published FP32 vector rate in fused multiply-adds.
+    assert bench.PEAK_SLOTS_PER_S == pytest.approx(157.3e12 / 2, rel=1e-3)
 
 
 def test_traffic_record_applies_only_to_its_tally_path_and_sources(monkeypatch):
