@@ -85,6 +85,9 @@ struct WalkArgs {
     int cache_bits;           // log2 of the tally-cache slots (0: no cache)
     uint32_t n_side;          // pixels of the side image (cache key offset of the transmitted image)
     int side_nx, side_ny, trans_nx, trans_ny;
+    // Pixels per mm: side rows (y), side columns (z), transmitted rows (y),
+    // transmitted columns (x).
+    float pix_scale[4];
     unsigned long long *ws_scal;   // workspace: 16 fixed-point scalar sums, work counter at MC_S_RESERVED
     unsigned long long *ws_img;    // workspace: kCopies x n_pix fixed-point weight sums
     unsigned long long *ws_img2;   // workspace (MC_SIGMA): kCopies x n_pix squared-weight sums
@@ -123,10 +126,21 @@ __device__ __forceinline__ unsigned long long fix(float w)
 }
 
 // Pixel = floor(coord / size * n), clamped to the image (IEEE division, so a
-// coordinate on a pixel edge lands where the FP64 definition puts it).
+// coordinate on a pixel edge lands where the FP64 definition puts it).  Used
+// for the beam's unscattered exit pixel, where every such photon lands on
+// the same point.
 __device__ __forceinline__ int pixel(float coord, float size, int n)
 {
     const int i = (int)floorf(coord / size * (float)n);
+    return min(max(i, 0), n - 1);
+}
+
+// The same with one product by pixels per mm in place of the division, for
+// the exits of scattered photons: only at a coordinate exactly on a pixel
+// edge may the product round to the other side of it.
+__device__ __forceinline__ int pixel_scaled(float coord, float per_mm, int n)
+{
+    const int i = (int)floorf(coord * per_mm);
     return min(max(i, 0), n - 1);
 }
 
@@ -255,7 +269,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // are found here, by every thread, with the walk's own arithmetic; face -1
     // when the beam leaves through a face without an image (or through the
     // side image while its path moments are tallied).
-    int beam_face = -1;
+    int beam_face = -2;   // -2: no face (it matches no photon's face, which is -1 or up)
     {
         int ax;
         const float db = wall_distance(a.pos0[0], a.pos0[1], a.pos0[2], a.dir0[0], a.dir0[1], a.dir0[2],
@@ -263,7 +277,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         const float bx = fmaf(db, a.dir0[0], a.pos0[0]), by = fmaf(db, a.dir0[1], a.pos0[1]);
         const float bz = fmaf(db, a.dir0[2], a.pos0[2]);
         const float da = ax == 0 ? a.dir0[0] : (ax == 1 ? a.dir0[1] : a.dir0[2]);
-        int face = -1;
+        int face = -2;
         uint32_t key = 0;
         if (da > 0.f && (ax == 0 || ax == 2) && !(MOMENTS && ax == 0) && !(a.beam_radius > 0.f)) {
             face = 2 * ax + 1;
@@ -307,10 +321,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             const bool side = wb >> 31;
             wf = __uint_as_float(wb & 0x7FFFFFFFu);
             const uint32_t key_base = BATCH ? __float_as_uint(q_s[lane]) * a.n_pix_inst : 0u;
-            key = key_base +
-                  (side ? (uint32_t)(pixel(y, a.size[1], a.side_ny) * a.side_nx + pixel(b, a.size[2], a.side_nx))
-                        : a.n_side + (uint32_t)(pixel(y, a.size[1], a.trans_ny) * a.trans_nx +
-                                                pixel(b, a.size[0], a.trans_nx)));
+            const float per_row = side ? a.pix_scale[0] : a.pix_scale[2];
+            const float per_col = side ? a.pix_scale[1] : a.pix_scale[3];
+            const int n_row = side ? a.side_ny : a.trans_ny, n_col = side ? a.side_nx : a.trans_nx;
+            key = key_base + (side ? 0u : a.n_side) +
+                  (uint32_t)(pixel_scaled(y, per_row, n_row) * n_col + pixel_scaled(b, per_col, n_col));
         }
         if (act) {
             wq = fix(wf);
@@ -400,10 +415,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // FP32 operations with a scalar-register operand issue at half the rate
     // of those whose operands are all vector registers; the constants of the
     // step therefore live in vector registers (the empty asm hides that they
-    // are wave-uniform) where the kernel has eight to spare: not with path
-    // moments or batched media, which need those registers themselves.
+    // are wave-uniform; batched media keep theirs per lane anyway), except
+    // with both path moments and squared-weight images, whose tallies need
+    // those registers.
     float v_lx = a.size[0], v_ly = a.size[1], v_lz = a.size[2], v_n21 = a.n21, v_n12sq = a.n12sq;
-    if (!MOMENTS && !BATCH) {
+    if (!(MOMENTS && SIGMA)) {
         asm volatile("" : "+v"(l_mu), "+v"(l_alb), "+v"(l_abs));
         asm volatile("" : "+v"(v_lx), "+v"(v_ly), "+v"(v_lz), "+v"(v_n21), "+v"(v_n12sq));
     }
@@ -427,6 +443,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // lanes at once: when at least refill_min lanes are free, or none is still
     // walking.  Few lanes finish in any one step, so doing that work every
     // step would run it with most lanes masked off.
+    // An ended photon's face is its exit face (0..5) exactly when it left
+    // through a wall (cause 0); roulette kills and the step cap leave it -1.
+    // A photon that ends on its first step through the beam's own exit face
+    // is an unscattered first-step exit (no interaction can end a photon at
+    // step 1 with a face).
     bool pending = false;
     int cause = 0, face = -1, axis = 0;
 
@@ -437,13 +458,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             if (pending) {
                 const uint32_t scal_at = BATCH ? l_slot * kBatchScal : 0u;
                 // Faces +x and +z are totalled from their images when finalizing.
-                if (cause == 0 && face != 1 && face != 5) atomicAdd(&s_scal[scal_at + MC_S_FACE + face], fix(w));
+                if (face >= 0 && (face | 4) != 5) atomicAdd(&s_scal[scal_at + MC_S_FACE + face], fix(w));
                 if (MOMENTS && cause == 0 && face == 1) {
                     // Path moments of the side image (perturbation Monte Carlo):
                     // first order per pixel, second order summed over the image
                     // in lane registers (per pixel as well when asked for).
-                    const uint32_t key = (uint32_t)(pixel(py, a.size[1], a.side_ny) * a.side_nx +
-                                                    pixel(pz, a.size[2], a.side_nx));
+                    const uint32_t key = (uint32_t)(pixel_scaled(py, a.pix_scale[0], a.side_ny) * a.side_nx +
+                                                    pixel_scaled(pz, a.pix_scale[1], a.side_nx));
                     const double wd = (double)w, wk = wd * (double)k, wl = wd * (double)L;
                     atomicAdd(a.side_wk + key, wk);
                     atomicAdd(a.side_wl + key, wl);
@@ -490,9 +511,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 }
             }
             // ---- queue exits through the imaged faces (+x side, +z transmitted) ----
-            const bool ballistic = pending && cause == 0 && k == 0 && step == 1 && face == beam_face;
+            const bool ballistic = pending && step == 1 && face == beam_face;
             acc_ball += ballistic ? 1u : 0u;
-            const bool to_img = pending && cause == 0 && (face == 1 || face == 5) && !ballistic;
+            const bool to_img = pending && (face | 4) == 5 && !ballistic;
             const uint64_t m = __ballot(to_img);
             if (m) {
                 const uint32_t n_push = __popcll(m);
@@ -1153,6 +1174,10 @@ void fill_common(WalkArgs &a, const mc_source_t &src, const mc_geometry_t &geo, 
     a.flags = det.flags;
     a.side_nx = det.side_nx; a.side_ny = det.side_ny;
     a.trans_nx = det.trans_nx; a.trans_ny = det.trans_ny;
+    a.pix_scale[0] = (float)(det.side_ny / geo.size_mm[1]);
+    a.pix_scale[1] = (float)(det.side_nx / geo.size_mm[2]);
+    a.pix_scale[2] = (float)(det.trans_ny / geo.size_mm[1]);
+    a.pix_scale[3] = (float)(det.trans_nx / geo.size_mm[0]);
     a.n_side = (uint32_t)((uint64_t)det.side_nx * det.side_ny);
     a.n_pix_inst = (uint32_t)((uint64_t)det.side_nx * det.side_ny + (uint64_t)det.trans_nx * det.trans_ny);
 }

@@ -228,7 +228,8 @@ def test_fixed_point_tallies_are_exact_sums_of_record_weights(mc, cuda_device):
     """MC_FIX64 tallies hold, per pixel and per face, the sum of each exit
     weight rounded to nearest (ties to even) at 2^32 per unit, bit for bit:
     recomputed here from the per-photon records, with the pixel of each exit
-    from its recorded position by the same FP32 floor(coord / size * n)."""
+    from its recorded position by the same FP32 floor(coord * (n / size)),
+    n / size rounded once to FP32 as the library does."""
     w = W.TINY.replace(tau=3.0, n_photons=30000, side_px=97, trans_px=131)
     f = gpu_run(w, records=True, fix64=True)
     r = f["rec"]
@@ -242,8 +243,8 @@ def test_fixed_point_tallies_are_exact_sums_of_record_weights(mc, cuda_device):
     for face, img, row_c, col_c, col_size, n in ((1, "side", "py", "pz", w.size_mm[2], w.side_px),
                                                  (5, "trans", "py", "px", w.size_mm[0], w.trans_px)):
         sel = out & (r["face"] == face)
-        row = np.floor(r[row_c][sel].astype(f32) / f32(w.size_mm[1]) * f32(n)).astype(np.int64).clip(0, n - 1)
-        col = np.floor(r[col_c][sel].astype(f32) / f32(col_size) * f32(n)).astype(np.int64).clip(0, n - 1)
+        row = np.floor(r[row_c][sel].astype(f32) * f32(n / w.size_mm[1])).astype(np.int64).clip(0, n - 1)
+        col = np.floor(r[col_c][sel].astype(f32) * f32(n / col_size)).astype(np.int64).clip(0, n - 1)
         for name, vals in ((img, q(wf[sel])), (img + "_w2", q(wf[sel] * wf[sel]))):
             expect = np.zeros(n * n, dtype=np.int64)
             np.add.at(expect, row * n + col, vals)
