@@ -195,7 +195,7 @@ typedef struct {
     double albedo;         /* mu_sca / mu_ext in [0, 1]; mu_abs = (1 - albedo) mu_ext */
     int32_t phase;         /* MC_PHASE_MIE or MC_PHASE_HG */
     int32_t n_cdf;         /* MIE: entries of inv_cdf, 2..MC_MAX_N_CDF */
-    const float *inv_cdf;  /* MIE: device inverse table as written by mie_table_build */
+    const float *inv_cdf;  /* MIE: device inverse table as written by mie_table_build (values in [0, 2]) */
     double g;              /* HG: asymmetry in (-1, 1) */
     double sigma_sca_mm2;  /* particle cross-sections (Eq. 14), used only by mc_grad for the */
     double sigma_abs_mm2;  /* concentration derivative; 0 and 0 make that derivative NaN */
@@ -327,7 +327,7 @@ int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_g
 typedef struct {
     double tau;            /* optical depth along z (Eq. 1), >= 0 */
     double albedo;         /* mu_sca / mu_ext, in [0, 1] */
-    const float *inv_cdf;  /* DEVICE inverse table of v = 1 - cos(theta), n_cdf floats (Sec. 2.6) */
+    const float *inv_cdf;  /* DEVICE inverse table of v = 1 - cos(theta) in [0, 2], n_cdf floats (Sec. 2.6) */
     uint64_t n_photons;    /* photons of this medium, ids 0 .. n_photons - 1 (0 allowed) */
     uint32_t instance;     /* Philox counter word 1 of its photons */
     uint32_t reserved;     /* set to 0 */

@@ -391,7 +391,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 
     unsigned long long *work = a.ws_scal + MC_S_RESERVED;
     const float tab_scale = (float)(a.n_cdf - 1);
-    const int tab_last = a.n_cdf - 2;
 
     // Wave-uniform id range: next id and ids left in the claimed chunk.
     uint64_t q_next = 0;
@@ -639,7 +638,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 if (!a.matched) {
                     const float ci = fabsf(da);
                     const float st2 = v_n12sq * fmaf(-ci, ci, 1.f);
-                    const float ct = __builtin_amdgcn_sqrtf(fmaxf(1.f - st2, 0.f));
+                    // 1 - st2 > 0 wherever R uses ct; under TIR the select drops it.
+                    const float ct = __builtin_amdgcn_sqrtf(1.f - st2);
                     const float rs = (ci - v_n21 * ct) * __builtin_amdgcn_rcpf(ci + v_n21 * ct);
                     const float rp = (v_n21 * ci - ct) * __builtin_amdgcn_rcpf(v_n21 * ci + ct);
                     R = st2 >= 1.f ? 1.f : 0.5f * fmaf(rs, rs, rp * rp);
@@ -672,8 +672,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 if (!ended) {
                     float v;
                     if (PHASE == MC_PHASE_MIE) {
+                        // u1 <= 1 - 2^-24, so u1 (n - 1) rounds below n - 1 (exact when
+                        // n - 1 is a power of two, else more than half an ulp short of
+                        // it): i <= n - 2 and entry i + 1 exists.
                         const float tt = u1 * tab_scale;
-                        const int i = min((int)tt, tab_last);
+                        const int i = (int)tt;
                         const float f = tt - (float)i;
                         const float t0 = GLOBAL_TABLE ? l_tab[i] : s_table[i];
                         const float t1 = GLOBAL_TABLE ? l_tab[i + 1] : s_table[i + 1];
@@ -684,7 +687,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                         v = a.hg_d * u1 * fmaf(a.hg_c, rD, a.hg_d) * rD;
                     }
                     const float ct = 1.f - v;
-                    const float st = __builtin_amdgcn_sqrtf(fmaxf(v * (2.f - v), 0.f));
+                    // A table value lies in [0, 2], and so does a rounded point between
+                    // two of them: v (2 - v) >= 0.  The HG formula can overshoot 2.
+                    const float st = __builtin_amdgcn_sqrtf(PHASE == MC_PHASE_MIE ? v * (2.f - v)
+                                                                                  : fmaxf(v * (2.f - v), 0.f));
                     const float cp = __builtin_amdgcn_cosf(u2);        // cos(2 pi u2)
                     const float sp = __builtin_amdgcn_sinf(u2);        // sin(2 pi u2)
                     // Orthonormal basis around d (Duff et al. 2017).
