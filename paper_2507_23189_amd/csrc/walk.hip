@@ -117,12 +117,22 @@ constexpr double kFix = 4294967296.0;      // fixed-point scale 2^32 per unit we
 // part of w and its fraction are exact in FP32, and the fraction times 2^32
 // is an exact FP32 value below 2^32, so two FP32 conversions give the same
 // integer as llrint((double)w * 2^32) with no FP64 arithmetic (an even
-// multiple of 2^32 does not change the tie-breaking parity).
+// multiple of 2^32 does not change the tie-breaking parity).  No fused
+// multiply-add may absorb w's own rounding: a squared weight passed as w * w
+// is the rounded FP32 product.
 __device__ __forceinline__ unsigned long long fix(float w)
 {
+#pragma clang fp contract(off)
     const float hi = truncf(w);
     const float lo = rintf((w - hi) * 4294967296.f);
     return ((unsigned long long)(uint32_t)hi << 32) + (unsigned long long)(uint32_t)lo;
+}
+
+// The same for 0 <= w < 1 (every weight of the walk unless roulette is set
+// to raise weights above 1): the integer part is 0 and w * 2^32 < 2^32.
+__device__ __forceinline__ unsigned long long fix_below_one(float w)
+{
+    return (unsigned long long)(uint32_t)rintf(w * 4294967296.f);
 }
 
 // Pixel = floor(coord / size * n), clamped to the image (IEEE division, so a
@@ -327,7 +337,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             key = key_base + (side ? 0u : a.n_side) +
                   (uint32_t)(pixel_scaled(y, per_row, n_row) * n_col + pixel_scaled(b, per_col, n_col));
         }
-        if (act) {
+        if (act && !LOG) {
             wq = fix(wf);
             wq2 = SIGMA ? fix(wf * wf) : 0ull;
         }
@@ -362,8 +372,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 }
             }
             if (direct) {
-                atomicAdd(my_img + key, wq);
-                if (SIGMA) atomicAdd(my_img2 + key, wq2);
+                atomicAdd(my_img + key, fix(wf));
+                if (SIGMA) atomicAdd(my_img2 + key, fix(wf * wf));
             }
             const uint64_t took = __ballot(direct);
             if (took && lane == 0) atomicAdd(a.ws_scal + kWsLogFallback, (unsigned long long)__popcll(took));
@@ -457,7 +467,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             if (pending) {
                 const uint32_t scal_at = BATCH ? l_slot * kBatchScal : 0u;
                 // Faces +x and +z are totalled from their images when finalizing.
-                if (face >= 0 && (face | 4) != 5) atomicAdd(&s_scal[scal_at + MC_S_FACE + face], fix(w));
+                const bool below_one = __ballot(w >= 1.f || A >= 1.f) == 0;   // wave-uniform
+                if (face >= 0 && (face | 4) != 5)
+                    atomicAdd(&s_scal[scal_at + MC_S_FACE + face], below_one ? fix_below_one(w) : fix(w));
                 if (MOMENTS && cause == 0 && face == 1) {
                     // Path moments of the side image (perturbation Monte Carlo):
                     // first order per pixel, second order summed over the image
@@ -475,7 +487,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                         atomicAdd(a.side_w2l + key, wd * wl);
                     }
                 }
-                acc_abs += fix(A);
+                acc_abs += below_one ? fix_below_one(A) : fix(A);
                 acc_events += k;
                 acc_steps += step;
                 ++acc_photons;

@@ -224,13 +224,17 @@ def test_full_chip_launches_are_bit_identical(mc, cuda_device):
             np.testing.assert_array_equal(a[k], other[k], err_msg=k)
 
 
-def test_fixed_point_tallies_are_exact_sums_of_record_weights(mc, cuda_device):
+@pytest.mark.parametrize("kw", [dict(), dict(albedo=0.8, roulette_w=0.5, roulette_p=0.2)],
+                         ids=["default", "weights_above_one"])
+def test_fixed_point_tallies_are_exact_sums_of_record_weights(mc, cuda_device, kw):
     """MC_FIX64 tallies hold, per pixel and per face, the sum of each exit
     weight rounded to nearest (ties to even) at 2^32 per unit, bit for bit:
     recomputed here from the per-photon records, with the pixel of each exit
     from its recorded position by the same FP32 floor(coord * (n / size)),
-    n / size rounded once to FP32 as the library does."""
-    w = W.TINY.replace(tau=3.0, n_photons=30000, side_px=97, trans_px=131)
+    n / size rounded once to FP32 as the library does.  The second case sets
+    roulette to raise weights to up to 2.5, past the walk's shortcut for
+    weights below 1."""
+    w = W.TINY.replace(tau=3.0, n_photons=30000, side_px=97, trans_px=131, **kw)
     f = gpu_run(w, records=True, fix64=True)
     r = f["rec"]
     f32 = np.float32
