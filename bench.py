@@ -104,8 +104,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # what the same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
 # WRITE_SIZE x 1.0); valid only for the tally path and kernel sources it was
 # measured on (profiles/walk_tau4_counters.md).
-TRAFFIC = {"tally": "log", "sources_sha256": "9160b4249f2a327a61a382648a45193d38f5be27836b327b3e1cd9786ad89712",
-           "fetch_kib": 385.5, "write_kib": 1812920.0, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"tally": "log", "sources_sha256": "527af57dcc4ce54e489649577e2c369ee76b8f4b0ce13a91e14fe2e9c31d49b8",
+           "fetch_kib": 376.2, "write_kib": 1806443.0, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 
