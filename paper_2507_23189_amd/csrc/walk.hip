@@ -18,6 +18,14 @@
 // Henyey-Greenstein (Eq. 11), with azimuth 2 pi u2, built in the orthonormal
 // basis of Duff et al. 2017 around the old direction.
 //
+// The kernel is bound by VALU issue.  On gfx950 a wave64 FP32 add, multiply
+// or fma whose operands are all vector registers issues in 2 cycles, while
+// compares, selects, min/max, conversions, shifts, 32-bit products and any
+// FP32 operation with a scalar-register operand take 4 and transcendentals
+// 8.  The step is written for that: its FP32 constants sit in vector
+// registers, the wall distances need neither compares nor selects, and
+// guards the arithmetic already ensures are left out.
+//
 // Transport runs in FP32.  Weights are tallied in 64-bit fixed point
 // (weight * 2^32, rounded to nearest): integer sums do not depend on the order
 // in which photons finish, so results are bit-identical for any launch shape
@@ -454,9 +462,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // step would run it with most lanes masked off.
     // An ended photon's face is its exit face (0..5) exactly when it left
     // through a wall (cause 0); roulette kills and the step cap leave it -1.
-    // A photon that ends on its first step through the beam's own exit face
-    // is an unscattered first-step exit (no interaction can end a photon at
-    // step 1 with a face).
+    // A photon that leaves on its first step met a wall before any
+    // interaction, so leaving through the beam's own exit face at step 1
+    // makes it an unscattered first-step exit.
     bool pending = false;
     int cause = 0, face = -1, axis = 0;
 
