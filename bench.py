@@ -102,22 +102,32 @@ PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # HBM traffic of one walk_kernel launch on this workload with the exit log,
 # from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) scaled by
 # what the same counters read for a 256 MiB device copy (FETCH_SIZE x 2.0,
-# WRITE_SIZE x 1.0); valid only for the tally path and kernel sources it was
-# measured on (profiles/walk_tau4_counters.md).
-TRAFFIC = {"tally": "log", "sources_sha256": "527af57dcc4ce54e489649577e2c369ee76b8f4b0ce13a91e14fe2e9c31d49b8",
+# WRITE_SIZE x 1.0); valid only for the tally path and kernel code it was
+# measured on (profiles/walk_tau4_counters.md): the digest covers the walk
+# sources without comments and whitespace, so a comment edit keeps it.
+TRAFFIC = {"tally": "log", "sources_sha256": "3e69df0390fe0065899182b9caef7406ce087f093e717c06394fd53f2a101058",
            "fetch_kib": 376.2, "write_kib": 1806443.0, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 
+def code_digest(text: str) -> str:
+    """SHA-256 of C++ source text with its comments and all whitespace removed."""
+    import hashlib
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return hashlib.sha256(re.sub(r"\s+", "", text).encode()).hexdigest()
+
+
+def walk_sources_digest() -> str:
+    return code_digest("".join(open(os.path.join(ROOT, f)).read() for f in WALK_SOURCES))
+
+
 def measured_traffic(args):
     """Bytes per launch if the walk kernel is the one the counters were taken on, else None."""
-    import hashlib
     if args.atomic_tally != (TRAFFIC["tally"] == "atomic"):
         return None
-    h = hashlib.sha256()
-    for f in WALK_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest() != TRAFFIC["sources_sha256"]:
+    if walk_sources_digest() != TRAFFIC["sources_sha256"]:
         return None
     return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] + TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
 

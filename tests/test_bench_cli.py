@@ -51,14 +51,18 @@ def test_traffic_record_applies_only_to_its_tally_path_and_sources(monkeypatch):
     log_args = types.SimpleNamespace(atomic_tally=False)
     atomic_args = types.SimpleNamespace(atomic_tally=True)
     rec = dict(bench.TRAFFIC)
-    import hashlib
-    h = hashlib.sha256()
-    for f in bench.WALK_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    rec["sources_sha256"] = h.hexdigest()
+    rec["sources_sha256"] = bench.walk_sources_digest()
     monkeypatch.setattr(bench, "TRAFFIC", rec)
     v = bench.measured_traffic(log_args if rec["tally"] == "log" else atomic_args)
     assert v == pytest.approx(1024.0 * (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"]))
     assert bench.measured_traffic(atomic_args if rec["tally"] == "log" else log_args) is None
     monkeypatch.setattr(bench, "TRAFFIC", dict(rec, sources_sha256="0" * 64))
     assert bench.measured_traffic(log_args) is None and bench.measured_traffic(atomic_args) is None
+
+
+def test_code_digest_ignores_comments_and_whitespace_only():
+    base = "int f(int a) {\n    return a + 1;   // one more\n}\n/* note */\n"
+    same = "int f(int a) { return a + 1; }  // edited comment\n/* another\n note */"
+    changed = "int f(int a) {\n    return a + 2;   // one more\n}\n"
+    assert bench.code_digest(base) == bench.code_digest(same)
+    assert bench.code_digest(base) != bench.code_digest(changed)
