@@ -210,7 +210,9 @@ typedef struct {
                               on the disk of this radius around pos_mm (Sec. 4.1), drawn from each
                               photon's Philox block at the reserved step counter 2^32 - 1 (radius
                               R sqrt(u0), azimuth 2 pi u1); the disk must lie inside the z = 0 face
-                              and max_steps must then be below 2^32 - 1 */
+                              and max_steps must then be below 2^32 - 1.  A beam whose refracted
+                              direction has no x (y) component must not reach the x = size
+                              (y = size) edge of the face: MC_EINVAL */
 } mc_source_t;
 
 /* Cuboid cuvette (Sec. 4.3) with one refractive-index step at every wall. */
@@ -222,11 +224,14 @@ typedef struct {
 
 /* Detector images: side view on the +x face (rows y, columns z) and the
  * transmitted image on the +z face (rows y, columns x); pixel index =
- * floor(coord / size * n), clamped to n - 1 (Sec. 4.3, Sec. 5.2). */
+ * floor(coord / size * n), clamped to n - 1 (Sec. 4.3, Sec. 5.2), evaluated
+ * in FP32 as floor(coord * (n / size)) with n / size rounded once (an exit
+ * exactly on a pixel edge may fall on either side of it). */
 typedef struct {
     int32_t side_nx, side_ny;     /* columns (z) and rows (y) of the side image, >= 1 */
     int32_t trans_nx, trans_ny;   /* columns (x) and rows (y) of the transmitted image, >= 1 */
-    uint32_t flags;               /* MC_ACCUMULATE | MC_SIGMA | MC_RECORD */
+    uint32_t flags;               /* MC_ACCUMULATE, MC_SIGMA, MC_RECORD, MC_FIX64, MC_MOMENTS,
+                                     MC_MOMENTS_PIXEL2, MC_EXIT_LOG */
 } mc_detector_t;
 
 /* Photon budget, random streams, termination and launch shape. */
