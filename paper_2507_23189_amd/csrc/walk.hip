@@ -433,13 +433,21 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // of those whose operands are all vector registers; the constants of the
     // step therefore live in vector registers (the empty asm hides that they
     // are wave-uniform; batched media keep theirs per lane anyway), except
-    // with both path moments and squared-weight images, whose tallies need
-    // those registers.
+    // with path moments together with squared-weight images or records,
+    // whose tallies need those registers.
     float v_lx = a.size[0], v_ly = a.size[1], v_lz = a.size[2], v_n21 = a.n21, v_n12sq = a.n12sq;
-    if (!(MOMENTS && SIGMA)) {
+    if (!(MOMENTS && (SIGMA || RECORD))) {
         asm volatile("" : "+v"(l_mu), "+v"(l_alb), "+v"(l_abs));
         asm volatile("" : "+v"(v_lx), "+v"(v_ly), "+v"(v_lz), "+v"(v_n21), "+v"(v_n12sq));
     }
+    // A new photon's starting state, likewise in vector registers where there
+    // is room (a refill then copies at full rate instead of from scalar
+    // registers, and seven scalar registers fewer need spilling).
+    constexpr bool INIT_V = !MOMENTS && !BATCH;
+    float i_px = a.pos0[0], i_py = a.pos0[1], i_pz = a.pos0[2], i_dx = a.dir0[0], i_dy = a.dir0[1];
+    float i_dz = a.dir0[2], i_w = a.w0;
+    if (INIT_V)
+        asm volatile("" : "+v"(i_px), "+v"(i_py), "+v"(i_pz), "+v"(i_dx), "+v"(i_dy), "+v"(i_dz), "+v"(i_w));
     const float *l_tab = a.inv_cdf;
     uint32_t l_ctr = a.instance;
     // Batched: move the lane accumulators into the LDS scalars of its medium.
@@ -601,7 +609,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                     }
                 }
                 alive = true;
-                px = a.pos0[0]; py = a.pos0[1]; pz = a.pos0[2];
+                px = INIT_V ? i_px : a.pos0[0];
+                py = INIT_V ? i_py : a.pos0[1];
+                pz = INIT_V ? i_pz : a.pos0[2];
                 if (a.beam_radius > 0.f) {
                     // Finite beam: entry point uniform on the disk, from the
                     // photon's Philox block at the reserved step counter.
@@ -612,8 +622,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                     px = fmaf(rho, __builtin_amdgcn_cosf(u1), px);    // cos(2 pi u1)
                     py = fmaf(rho, __builtin_amdgcn_sinf(u1), py);    // sin(2 pi u1)
                 }
-                dx = a.dir0[0]; dy = a.dir0[1]; dz = a.dir0[2];
-                w = a.w0; L = 0.f; A = 0.f; k = 0; step = 0;
+                dx = INIT_V ? i_dx : a.dir0[0];
+                dy = INIT_V ? i_dy : a.dir0[1];
+                dz = INIT_V ? i_dz : a.dir0[2];
+                w = INIT_V ? i_w : a.w0;
+                L = 0.f; A = 0.f; k = 0; step = 0;
             }
             const uint32_t took = min((uint32_t)__popcll(need), q_rem);
             q_next += took;
