@@ -105,8 +105,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # WRITE_SIZE x 1.0); valid only for the tally path and kernel code it was
 # measured on (profiles/walk_tau4_counters.md): the digest covers the walk
 # sources without comments and whitespace, so a comment edit keeps it.
-TRAFFIC = {"tally": "log", "sources_sha256": "3e69df0390fe0065899182b9caef7406ce087f093e717c06394fd53f2a101058",
-           "fetch_kib": 376.2, "write_kib": 1806443.0, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"tally": "log", "sources_sha256": "0dd8c6bbf79c8f13cec6aa19ce48c1391efe4d1510dcee2ad9dfb460369bb38e",
+           "fetch_kib": 377.3, "write_kib": 1798653.0, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 
