@@ -155,7 +155,10 @@ def inverse_table(theta: np.ndarray, F: np.ndarray, n_cdf: int) -> np.ndarray:
 
     For each u the first grid index j with F_j >= u is found by binary search;
     theta(u) interpolates linearly between theta_{j-1} and theta_j; the table
-    stores v = 1 - cos(theta(u))."""
+    stores v = 1 - cos(theta(u)), evaluated as 2 sin^2(theta/2), the same
+    quantity without the cancellation of 1 - cos at small angles (at
+    x ~ 940 the first entries have theta ~ 1e-6, where 1 - cos(theta) in
+    FP64 keeps three significant digits)."""
     v = np.zeros(n_cdf)
     for i in range(n_cdf):
         u = i / (n_cdf - 1)
@@ -164,7 +167,7 @@ def inverse_table(theta: np.ndarray, F: np.ndarray, n_cdf: int) -> np.ndarray:
             th = theta[0]
         else:
             th = theta[j - 1] + (u - F[j - 1]) / (F[j] - F[j - 1]) * (theta[j] - theta[j - 1])
-        v[i] = 1.0 - math.cos(th)
+        v[i] = 2.0 * math.sin(0.5 * th) ** 2
     return v
 
 

@@ -60,6 +60,7 @@ TABLE_CASES = [
     dict(d=0.5, m_re=1.59, m_im=0.0, n_med=1.33, lam=532.0, na=1801, nc=4096),      # x ~ 3.9
     dict(d=10.0, m_re=1.59, m_im=0.0, n_med=1.33, lam=532.0, na=1801, nc=2),        # x ~ 78.5, smallest table
     dict(d=0.02, m_re=1.5, m_im=0.1, n_med=1.0, lam=532.0, na=3, nc=5),             # Rayleigh, smallest grid
+    dict(d=120.0, m_re=1.59, m_im=0.0, n_med=1.33, lam=532.0, na=3001, nc=16384),   # x ~ 942: 984 of the 1024 terms
 ]
 
 
@@ -85,8 +86,15 @@ def test_mie_table_parity(mc, cuda_device, case):
     for name in ("q_ext", "q_sca", "g", "sigma_ext_mm2"):
         assert getattr(t, name) == pytest.approx(getattr(o, name), rel=1e-11, abs=1e-300)
     assert t.q_abs == pytest.approx(o.q_abs, abs=1e-11 * o.q_ext)
-    np.testing.assert_allclose(t.phase.cpu().numpy(), o.P, rtol=1e-10, atol=1e-14 * o.P.max())
-    np.testing.assert_allclose(t.cdf.cpu().numpy(), o.F, rtol=0, atol=1e-13)
+    gP = t.phase.cpu().numpy()
+    np.testing.assert_allclose(gP, o.P, rtol=1e-10, atol=1e-14 * o.P.max())
+    # The CDF is a normalised sum of P with positive weights, so a relative
+    # error eps in every P moves it by at most 2 eps; the sums' own rounding
+    # stays below 1e-13.  At small x eps is ~1e-15; near the 1024-term limit
+    # the series' conditioning leaves P agreeing to ~1e-13.
+    pos = o.P > 1e-300
+    eps_p = float(np.max(np.abs(gP[pos] - o.P[pos]) / o.P[pos]))
+    np.testing.assert_allclose(t.cdf.cpu().numpy(), o.F, rtol=0, atol=1e-13 + 2.0 * eps_p)
     inv = t.inv_cdf.cpu().numpy()
     ref32 = o.v.astype(np.float32)
     ulp = np.spacing(np.abs(ref32)).astype(np.float64)
