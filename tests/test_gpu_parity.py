@@ -146,6 +146,8 @@ def test_tiny_workload_trajectories_and_images(mc, cuda_device, phase):
          src_pos_mm=(1.0, 2.0, 0.0), src_dir=(0.3, -0.2, 0.9)),            # ragged, oblique beam
     dict(tau=8.0, max_steps=4, n_photons=5000),                            # step cap
     dict(tau=2.0, n_photons=5000, src_pos_mm=(0.0, 0.0, 0.0), src_dir=(-0.0, 0.0, 1.0)),  # along an edge
+    dict(tau=0.0, n_photons=5000, src_dir=(0.2, 0.1, 0.97)),              # no medium: walls only
+    dict(tau=3.0, albedo=1.0, n_photons=10000),                           # no absorption
 ])
 def test_trajectory_parity_variants(mc, cuda_device, kw):
     w = W.TINY.replace(**kw)
