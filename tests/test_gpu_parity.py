@@ -137,6 +137,17 @@ def test_tiny_workload_trajectories_and_images(mc, cuda_device, phase):
     assert image_within_3sigma(g["side_w2"], o.side_w2, o.side_w2, w.n_photons).all()
 
 
+@pytest.mark.parametrize("g", [-0.5, 0.0, 0.99])
+def test_hg_trajectories_across_asymmetry(mc, cuda_device, g):
+    """Eq. 11 sampling at back-scattering, isotropic and strongly forward g."""
+    w = W.TINY.replace(phase=W.PHASE_HG, tau=3.0, n_photons=20000)
+    gr = gpu_run(w, records=True, g=g)
+    o = _oracle(w, g=g)
+    ok = trajectory_match(gr["rec"], oracle_rec(o), box=10.0)
+    assert ok.mean() >= 0.999, (g, ok.mean())
+    assert image_within_3sigma(gr["trans"], o.trans, o.trans_w2, w.n_photons).all()
+
+
 @pytest.mark.parametrize("kw", [
     dict(tau=4.0, n_cdf=16384, side_px=512, trans_px=512, n_photons=20000),
     dict(tau=8.0, n_photons=20000, albedo=0.9),
