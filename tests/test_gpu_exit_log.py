@@ -84,6 +84,19 @@ def test_log_equals_atomic_path(mc, cuda_device, table, case):
     _same(a, b)
 
 
+def test_log_with_finite_beam_and_heavy_weights(mc, cuda_device, table):
+    """The analysis workload's 1.25 mm beam (no first-step counting, so the
+    beam's unscattered exits go through the log too) and roulette settings
+    that raise weights above 1: the log still equals the atomic path."""
+    w = W.analysis_workload(8.0).replace(roulette_w=0.5, roulette_p=0.2, albedo=0.98)
+    flags = mc.MC_FIX64 | mc.MC_SIGMA
+    n = 1_000_000
+    a = _run(mc, cuda_device, w, table, flags, n_photons=n)
+    b = _run(mc, cuda_device, w, table, flags | mc.MC_EXIT_LOG, n_photons=n)
+    assert a["scalars"][10] == n and a["trans"].sum() > 0
+    _same(a, b)
+
+
 @pytest.mark.parametrize("shape", [(37, 23, 61, 19), (1, 1, 1, 1), (5, 300, 700, 3), (512, 512, 1024, 1024)])
 def test_log_ragged_shapes(mc, cuda_device, table, shape):
     """Image sizes whose key count is not a multiple of 512, a single pixel
