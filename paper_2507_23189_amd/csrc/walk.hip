@@ -1115,7 +1115,8 @@ float entry_dir(const mc_source_t &src, const mc_geometry_t &geo, int i)
     const double eta = geo.n_outside / geo.n_medium;
     double d[3] = {eta * (src.dir[0] / dl), eta * (src.dir[1] / dl), 0.0};
     d[2] = std::sqrt(std::max(0.0, 1.0 - d[0] * d[0] - d[1] * d[1]));
-    return (float)d[i] + 0.0f;
+    const float f = (float)d[i];
+    return f == 0.f ? 0.f : f;   // -0 (or an underflow to it) becomes +0
 }
 
 // Checks of the source, detector, tally buffers and run settings shared by
