@@ -241,8 +241,16 @@ constexpr int kWsBallistic = 19;           // workspace word (per medium) of tha
 constexpr int kWsBeamKey = 20;             // workspace word (first medium): beam exit key + 1, or 0
 constexpr int kWsLogFallback = 21;         // workspace word: exits added directly because the log was full
 
+// Waves per SIMD a walk kernel is built for: eight (64 vector registers
+// each), or six (80 each) with path moments, whose tallies would otherwise
+// leave no registers for the step's constants (measured: six waves with the
+// constants beat eight without by 7 %, while the plain walk loses 3 % at six).
+template <int OPT>
+constexpr int walk_waves_per_simd() { return (OPT & 4) ? 6 : 8; }
+
 template <int PHASE, int OPT>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void walk_kernel(WalkArgs a)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(walk_waves_per_simd<OPT>())))
+void walk_kernel(WalkArgs a)
 {
     constexpr bool SIGMA = OPT & kOptSigma, RECORD = OPT & kOptRecord, MOMENTS = OPT & kOptMoments;
     constexpr bool BATCH = OPT & kOptBatch, LOG = OPT & kOptLog;
@@ -432,18 +440,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // FP32 operations with a scalar-register operand issue at half the rate
     // of those whose operands are all vector registers; the constants of the
     // step therefore live in vector registers (the empty asm hides that they
-    // are wave-uniform; batched media keep theirs per lane anyway), except
-    // with path moments together with squared-weight images or records,
-    // whose tallies need those registers.
+    // are wave-uniform; batched media keep theirs per lane anyway).
     float v_lx = a.size[0], v_ly = a.size[1], v_lz = a.size[2], v_n21 = a.n21, v_n12sq = a.n12sq;
-    if (!(MOMENTS && (SIGMA || RECORD))) {
-        asm volatile("" : "+v"(l_mu), "+v"(l_alb), "+v"(l_abs));
-        asm volatile("" : "+v"(v_lx), "+v"(v_ly), "+v"(v_lz), "+v"(v_n21), "+v"(v_n12sq));
-    }
-    // A new photon's starting state, likewise in vector registers where there
-    // is room (a refill then copies at full rate instead of from scalar
-    // registers, and seven scalar registers fewer need spilling).
-    constexpr bool INIT_V = !MOMENTS && !BATCH;
+    asm volatile("" : "+v"(l_mu), "+v"(l_alb), "+v"(l_abs));
+    asm volatile("" : "+v"(v_lx), "+v"(v_ly), "+v"(v_lz), "+v"(v_n21), "+v"(v_n12sq));
+    // A new photon's starting state, likewise in vector registers (a refill
+    // then copies at full rate instead of from scalar registers, and seven
+    // scalar registers fewer need spilling); not for batched media, whose
+    // kernels have no registers to spare and whose photons start the same.
+    constexpr bool INIT_V = !BATCH;
     float i_px = a.pos0[0], i_py = a.pos0[1], i_pz = a.pos0[2], i_dx = a.dir0[0], i_dy = a.dir0[1];
     float i_dz = a.dir0[2], i_w = a.w0;
     if (INIT_V)
@@ -1266,11 +1271,13 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     const bool use_log = (det.flags & MC_EXIT_LOG) != 0;
     const uint64_t ws_words = batch ? workspace_words(det, n_inst) : workspace_words(det);
 
-    // ---- launch shape: 1024-lane blocks, two per CU (32 waves), each with
+    // ---- launch shape: 1024-lane blocks (768 with path moments), two per CU, each with
     // the table (single medium), the scalar words, the per-wave exit queues and
     // as large a tally cache as fits in half the CU's 160 KB LDS (with the exit
     // log: the log cursors and no cache) ----
-    const int block = rn.block_size ? rn.block_size : 1024;
+    // Path-moment kernels are built for six waves per SIMD: 768-lane blocks,
+    // two per CU.
+    const int block = rn.block_size ? rn.block_size : ((det.flags & MC_MOMENTS) ? 768 : 1024);
     const size_t table_bytes = batch ? 0 : (size_t)((a.n_cdf + 3) & ~3) * sizeof(float);
     const size_t scal_bytes = (batch ? (size_t)n_inst * kBatchScal : MC_N_SCALARS) * sizeof(double);
     const size_t queue_arrays = batch ? 4 : 3;
