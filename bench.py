@@ -105,7 +105,7 @@ PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # WRITE_SIZE x 1.0); valid only for the tally path and kernel code it was
 # measured on (profiles/walk_tau4_counters.md): the digest covers the walk
 # sources without comments and whitespace, so a comment edit keeps it.
-TRAFFIC = {"tally": "log", "sources_sha256": "d7c849a586999adf0c0931907138d11d52031e5fac1723656130e65eafb3a201",
+TRAFFIC = {"tally": "log", "sources_sha256": "1bd222ac92adf83877fca51ca05569852e0c9e28722ef522ea358f8633ba19cb",
            "fetch_kib": 377.3, "write_kib": 1798653.0, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
