@@ -32,8 +32,12 @@ __global__ __launch_bounds__(1024) void probe(uint32_t *out, int iters, float fa
     uint32_t u[8];
     double d[8];
     uint64_t q[8], m[8];
+    float y[8], z[8], t[8], v[8];   // independent chains beside x and u (mixed probes)
+    uint32_t u2[8];
     for (int c = 0; c < 8; ++c) {
         x[c] = 1.0f + (float)(threadIdx.x + c) * 1e-4f;
+        y[c] = z[c] = t[c] = v[c] = x[c];
+        u2[c] = gid * 40503u + c;
         u[c] = gid * 2654435761u + c;
         d[c] = 1.0 + (double)(threadIdx.x + c) * 1e-4;
         q[c] = gid + c;
@@ -70,16 +74,28 @@ __global__ __launch_bounds__(1024) void probe(uint32_t *out, int iters, float fa
             if (OP == 20) CHAINS("v_log_f32 %0, %0" : "+v"(x[c]))
             if (OP == 21) CHAINS("v_sin_f32 %0, %0" : "+v"(x[c]))
             if (OP == 22) CHAINS("v_fma_f64 %0, %0, %1, %2" : "+v"(d[c]) : "v"(da), "v"(db))
+            // Mixed groups: does a transcendental overlap independent full-
+            // or half-rate work, or do the costs add?
+            if (OP == 23) CHAINS("v_rcp_f32 %0, %0\n\tv_fma_f32 %1, %1, %2, %3"
+                                 : "+v"(x[c]), "+v"(y[c]) : "v"(fa), "v"(fb))
+            if (OP == 24) CHAINS("v_rcp_f32 %0, %0\n\tv_fma_f32 %1, %1, %5, %6\n\tv_fma_f32 %2, %2, %5, %6\n\t"
+                                 "v_fma_f32 %3, %3, %5, %6\n\tv_fma_f32 %4, %4, %5, %6"
+                                 : "+v"(x[c]), "+v"(y[c]), "+v"(z[c]), "+v"(t[c]), "+v"(v[c]) : "v"(fa), "v"(fb))
+            if (OP == 25) CHAINS("v_rcp_f32 %0, %0\n\tv_mul_hi_u32 %1, %1, %3\n\tv_mul_hi_u32 %2, %2, %3"
+                                 : "+v"(x[c]), "+v"(u[c]), "+v"(u2[c]) : "v"(ua))
+            if (OP == 26) CHAINS("v_mul_hi_u32 %0, %0, %3\n\tv_fma_f32 %1, %1, %4, %5\n\tv_fma_f32 %2, %2, %4, %5"
+                                 : "+v"(u[c]), "+v"(y[c]), "+v"(z[c]) : "v"(ua), "v"(fa), "v"(fb))
         }
     }
     uint32_t s = 0;
     for (int c = 0; c < 8; ++c)
-        s += __float_as_uint(x[c]) + u[c] + (uint32_t)__double_as_longlong(d[c]) + (uint32_t)q[c] + (uint32_t)m[c];
+        s += __float_as_uint(x[c]) + u[c] + (uint32_t)__double_as_longlong(d[c]) + (uint32_t)q[c] + (uint32_t)m[c] +
+             __float_as_uint(y[c]) + __float_as_uint(z[c]) + __float_as_uint(t[c]) + __float_as_uint(v[c]) + u2[c];
     out[gid] = s;
 }
 
 template <int OP>
-void run(const char *name, uint32_t *out, int blocks, int iters)
+void run(const char *name, uint32_t *out, int blocks, int iters, int per_chain = 1)
 {
     hipEvent_t e0, e1;
     CHECK(hipEventCreate(&e0));
@@ -97,9 +113,14 @@ void run(const char *name, uint32_t *out, int blocks, int iters)
         CHECK(hipEventElapsedTime(&ms, e0, e1));
         if (ms < best) best = ms;
     }
-    // 16 waves per workgroup, 128 instructions per wave and iteration, 1024 SIMDs.
+    // 16 waves per workgroup, 128 chain steps per wave and iteration (each
+    // of per_chain instructions), 1024 SIMDs.
     const double per_simd = (double)blocks * 16 * iters * 128 / 1024.0;
-    std::printf("%-34s %7.3f ms  %5.2f cycles per wave64 instruction\n", name, best, best * 1e-3 * 2.4e9 / per_simd);
+    const double cyc = best * 1e-3 * 2.4e9 / per_simd;
+    if (per_chain == 1)
+        std::printf("%-34s %7.3f ms  %5.2f cycles per wave64 instruction\n", name, best, cyc);
+    else
+        std::printf("%-34s %7.3f ms  %5.2f cycles per group of %d\n", name, best, cyc, per_chain);
     std::fflush(stdout);
     CHECK(hipEventDestroy(e0));
     CHECK(hipEventDestroy(e1));
@@ -139,6 +160,10 @@ int main()
     run<20>("v_log_f32", out, blocks, it / 2);
     run<21>("v_sin_f32", out, blocks, it / 2);
     run<22>("v_fma_f64", out, blocks, it);
+    run<23>("mixed: rcp + fma", out, blocks, it / 2, 2);
+    run<24>("mixed: rcp + 4 fma", out, blocks, it / 2, 5);
+    run<25>("mixed: rcp + 2 mul_hi_u32", out, blocks, it / 2, 3);
+    run<26>("mixed: mul_hi_u32 + 2 fma", out, blocks, it / 2, 3);
     run<0>("v_fma_f32 (VGPR operands, again)", out, blocks, it);
     CHECK(hipFree(out));
     return 0;
