@@ -85,6 +85,14 @@ __global__ __launch_bounds__(1024) void probe(uint32_t *out, int iters, float fa
                                  : "+v"(x[c]), "+v"(u[c]), "+v"(u2[c]) : "v"(ua))
             if (OP == 26) CHAINS("v_mul_hi_u32 %0, %0, %3\n\tv_fma_f32 %1, %1, %4, %5\n\tv_fma_f32 %2, %2, %4, %5"
                                  : "+v"(u[c]), "+v"(y[c]), "+v"(z[c]) : "v"(ua), "v"(fa), "v"(fb))
+            // The group of probe 24 in another order: the eight chains' rcp
+            // back to back, then their 32 fma.
+            if (OP == 27) {
+                CHAINS("v_rcp_f32 %0, %0" : "+v"(x[c]))
+                CHAINS("v_fma_f32 %0, %0, %4, %5\n\tv_fma_f32 %1, %1, %4, %5\n\tv_fma_f32 %2, %2, %4, %5\n\t"
+                       "v_fma_f32 %3, %3, %4, %5"
+                       : "+v"(y[c]), "+v"(z[c]), "+v"(t[c]), "+v"(v[c]) : "v"(fa), "v"(fb))
+            }
         }
     }
     uint32_t s = 0;
@@ -164,6 +172,7 @@ int main()
     run<24>("mixed: rcp + 4 fma", out, blocks, it / 2, 5);
     run<25>("mixed: rcp + 2 mul_hi_u32", out, blocks, it / 2, 3);
     run<26>("mixed: mul_hi_u32 + 2 fma", out, blocks, it / 2, 3);
+    run<27>("mixed: 8 rcp, then 32 fma", out, blocks, it / 2, 5);
     run<0>("v_fma_f32 (VGPR operands, again)", out, blocks, it);
     CHECK(hipFree(out));
     return 0;
