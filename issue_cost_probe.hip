@@ -85,6 +85,10 @@ __global__ __launch_bounds__(1024) void probe(uint32_t *out, int iters, float fa
                                  : "+v"(x[c]), "+v"(u[c]), "+v"(u2[c]) : "v"(ua))
             if (OP == 26) CHAINS("v_mul_hi_u32 %0, %0, %3\n\tv_fma_f32 %1, %1, %4, %5\n\tv_fma_f32 %2, %2, %4, %5"
                                  : "+v"(u[c]), "+v"(y[c]), "+v"(z[c]) : "v"(ua), "v"(fa), "v"(fb))
+            // Constant operands: a 32-bit literal (v_fmamk_f32 x * K + y) and an
+            // inline constant (0.5).
+            if (OP == 28) CHAINS("v_fmamk_f32 %0, %0, 0x3f800001, %1" : "+v"(x[c]) : "v"(fb))
+            if (OP == 29) CHAINS("v_fma_f32 %0, %0, %1, 0.5" : "+v"(x[c]) : "v"(fa))
             // The group of probe 24 in another order: the eight chains' rcp
             // back to back, then their 32 fma.
             if (OP == 27) {
@@ -173,6 +177,8 @@ int main()
     run<25>("mixed: rcp + 2 mul_hi_u32", out, blocks, it / 2, 3);
     run<26>("mixed: mul_hi_u32 + 2 fma", out, blocks, it / 2, 3);
     run<27>("mixed: 8 rcp, then 32 fma", out, blocks, it / 2, 5);
+    run<28>("v_fmamk_f32 (32-bit literal)", out, blocks, it);
+    run<29>("v_fma_f32 (inline constant 0.5)", out, blocks, it);
     run<0>("v_fma_f32 (VGPR operands, again)", out, blocks, it);
     CHECK(hipFree(out));
     return 0;
