@@ -167,6 +167,49 @@ def _ptr(t) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _require(t, name: str, dtypes, *, numel=None, min_numel=None, shape=None, optional=False):
+    """Refuse, before any library call, a buffer the kernels would read or
+    write out of bounds: it must be a contiguous tensor of one of `dtypes`
+    with the stated element count or shape.  Raises ValueError; returns the
+    tensor (None for an absent optional one).  Where it lives is checked
+    afterwards, for all buffers of a call at once, by _on_one_gpu."""
+    import torch
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor, got {type(t).__name__}")
+    if not isinstance(dtypes, (tuple, list)):
+        dtypes = (dtypes,)
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} must have dtype {' or '.join(str(d) for d in dtypes)}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements, got {t.numel()}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name} must hold at least {min_numel} elements, got {t.numel()}")
+    return t
+
+
+def _on_one_gpu(**named):
+    """Every given tensor (None skipped) lives on the same GPU; returns it."""
+    dev = None
+    for name, t in named.items():
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be on a GPU, got {t.device}")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError(f"{name} is on {t.device}, other buffers of the call on {dev}")
+    return dev
+
+
 @dataclass
 class MieTable:
     """Host scalars and device tensors written by mie_table_build."""
@@ -243,6 +286,9 @@ def mie_table_enqueue(spec: MieSpec, device="cuda", *, inv_cdf=None, result=None
     dev = torch.device(device)
     inv = inv_cdf if inv_cdf is not None else torch.empty(max(int(spec.n_cdf), 1), dtype=torch.float32, device=dev)
     res = result if result is not None else torch.empty(4, dtype=torch.float64, device=dev)
+    _require(inv, "inv_cdf", torch.float32, min_numel=max(int(spec.n_cdf), 1))
+    _require(res, "result", torch.float64, min_numel=4)
+    _on_one_gpu(inv_cdf=inv, result=res)
     t = _MieTableC()
     t.inv_cdf, t.result = _ptr(inv), _ptr(res)
     with torch.cuda.device(dev):
@@ -336,6 +382,43 @@ class Tally:
             t.trans_w2 = torch.empty_like(t.trans)
         return t
 
+    def validate(self, det: Detector, n_items: Optional[int] = None, *, grad: bool = False, **extra):
+        """Check every buffer the library will touch against `det` (and
+        n_items media for a batched launch) before a call: dtypes, shapes and
+        contiguity first, then that they (and the tensors in `extra`, already
+        checked by the caller) share one GPU.  Raises ValueError; returns the
+        device."""
+        import torch
+        lead = () if n_items is None else (int(n_items),)
+        img_t = torch.int64 if det.flags & MC_FIX64 else torch.float64
+        side_shape = lead + (det.side_ny, det.side_nx)
+        trans_shape = lead + (det.trans_ny, det.trans_nx)
+        used = {}
+        if not grad:
+            used["tally.side"] = _require(self.side, "tally.side", img_t, shape=side_shape)
+            used["tally.trans"] = _require(self.trans, "tally.trans", img_t, shape=trans_shape)
+        used["tally.scalars"] = _require(self.scalars, "tally.scalars", torch.float64,
+                                         numel=MC_N_SCALARS * (1 if n_items is None else n_items))
+        used["tally.workspace"] = _require(self.workspace, "tally.workspace", torch.int64)
+        if (det.flags & MC_SIGMA) and not grad:
+            used["tally.side_w2"] = _require(self.side_w2, "tally.side_w2", img_t, shape=side_shape)
+            used["tally.trans_w2"] = _require(self.trans_w2, "tally.trans_w2", img_t, shape=trans_shape)
+        if det.flags & MC_MOMENTS or grad:
+            for name in ("side_wk", "side_wl"):
+                used[f"tally.{name}"] = _require(getattr(self, name), f"tally.{name}", torch.float64,
+                                                 shape=side_shape)
+        if det.flags & MC_MOMENTS_PIXEL2 or (grad and self.side_w2k is not None):
+            for name in ("side_w2k", "side_w2l"):
+                used[f"tally.{name}"] = _require(getattr(self, name), f"tally.{name}", torch.float64,
+                                                 shape=side_shape)
+        if (det.flags & MC_RECORD) and not grad and (self.rec_i is not None or self.rec_f is not None):
+            ri = _require(self.rec_i, "tally.rec_i", torch.int32)
+            if ri.dim() != 2 or ri.shape[0] != MC_REC_I_N:
+                raise ValueError(f"tally.rec_i must have shape ({MC_REC_I_N}, rows)")
+            used["tally.rec_i"] = ri
+            used["tally.rec_f"] = _require(self.rec_f, "tally.rec_f", torch.float32, shape=(MC_REC_F_N, ri.shape[1]))
+        return _on_one_gpu(**used, **extra)
+
     def _c(self) -> _TallyC:
         c = _TallyC()
         c.side, c.trans, c.scalars = _ptr(self.side), _ptr(self.trans), _ptr(self.scalars)
@@ -352,6 +435,7 @@ class Tally:
 def mc_simulate(medium: Medium, source: Source, geometry: Geometry, detector: Detector, run: Run,
                 tally: Tally, stream=None) -> None:
     """Enqueue the photon walk on the stream (asynchronous)."""
+    tally.validate(detector)
     tc = tally._c()
     _check(lib().mc_simulate(C.byref(medium), C.byref(source), C.byref(geometry), C.byref(detector),
                              C.byref(run), C.byref(tc), _stream(stream)))
@@ -365,6 +449,11 @@ def mc_grad(medium: Medium, geometry: Geometry, detector: Detector, tally: Tally
     derivative for the self-correlation correction: per pixel
     (`d2loss_dside2`, device tensor, needs MC_MOMENTS_PIXEL2) or one value for
     every pixel (`d2loss_uniform`).  Waits for the stream."""
+    import torch
+    n = detector.side_ny * detector.side_nx
+    g = _require(dloss_dside, "dloss_dside", torch.float64, numel=n)
+    h = _require(d2loss_dside2, "d2loss_dside2", torch.float64, numel=n, optional=True)
+    tally.validate(detector, grad=True, dloss_dside=g, d2loss_dside2=h)
     out = (C.c_double * 3)()
     tc = tally._c()
     _check(lib().mc_grad(C.byref(medium), C.byref(geometry), C.byref(detector), C.byref(tc),
@@ -384,6 +473,7 @@ def mc_simulate_batch(items, n_cdf: int, source: Source, geometry: Geometry, det
     """Enqueue the batched walk of `items` (a sequence of BatchItem, one per
     medium; outputs item-major in `tally`, see Tally.alloc_batch)."""
     arr = _batch_items(items)
+    tally.validate(detector, len(items))
     tc = tally._c()
     _check(lib().mc_simulate_batch(arr, len(items), int(n_cdf), C.byref(source), C.byref(geometry),
                                    C.byref(detector), C.byref(run), C.byref(tc), _stream(stream)))
@@ -395,6 +485,7 @@ def mc_autotune_batch(items, n_cdf: int, source: Source, geometry: Geometry, det
     batch; returns (block_size, chunk, best_ms, {(block, chunk): ms}).  The
     tally is overwritten.  Waits for the stream."""
     arr = _batch_items(items)
+    tally.validate(detector, len(items))
     tc = tally._c()
     blk, chk, best = C.c_int32(), C.c_uint32(), C.c_double()
     cand = (C.c_double * (len(AUTOTUNE_BLOCKS) * len(AUTOTUNE_CHUNKS)))()
@@ -412,6 +503,12 @@ def image_metrics(a, b, c=None, *, cx=None, cy=None, r_max=None, profiles=False,
     radial centre defaults to the image centre and r_max to half the shorter
     side.  Waits for the stream."""
     import torch
+    if not isinstance(a, torch.Tensor) or a.dim() != 2:
+        raise ValueError("a must be a 2-D torch tensor")
+    _require(a, "a", torch.float64)
+    _require(b, "b", torch.float64, shape=a.shape)
+    _require(c, "c", torch.float64, shape=a.shape, optional=True)
+    _on_one_gpu(a=a, b=b, c=c)
     ny, nx = (int(v) for v in a.shape)
     rad = Radial(nx / 2.0 if cx is None else cx, ny / 2.0 if cy is None else cy,
                  min(nx, ny) / 2.0 if r_max is None else r_max)
@@ -433,6 +530,10 @@ def image_metrics(a, b, c=None, *, cx=None, cy=None, r_max=None, profiles=False,
 
 def mc_philox_blocks(seed: int, instance: int, ids, step0: int, n_steps: int, out, stream=None) -> None:
     """Fill `out` (uint32 viewed as int32, len(ids) * n_steps * 4) with the walk's Philox words."""
+    import torch
+    _require(ids, "ids", (torch.int64, torch.uint64))
+    _require(out, "out", (torch.int32, torch.uint32), min_numel=int(ids.numel()) * int(n_steps) * 4)
+    _on_one_gpu(ids=ids, out=out)
     _check(lib().mc_philox_blocks(seed, instance, _ptr(ids), int(ids.numel()), step0, n_steps, _ptr(out),
                                   _stream(stream)))
 

@@ -428,3 +428,130 @@ def test_metrics_work_size_and_validation():
     assert L.mc_image_metrics(0x1000, 0x1000, None, 128, 128, C.byref(rad), None, 0x1000, nb - 8, out, None) \
         == mc.MC_EINVAL
     assert b"work" in L.mc_last_error()
+
+
+# ---- the Python binding refuses buffers the kernels would overrun, before any library call ----
+
+def _no_library(monkeypatch):
+    import paper_2507_23189_amd._capi as cap
+
+    def boom():
+        raise AssertionError("the library was called")
+    monkeypatch.setattr(cap, "lib", boom)
+    return cap
+
+
+def _cpu_tally(det, **kw):
+    """Tally-shaped CPU tensors (the device check comes after dtype and shape)."""
+    import torch
+    import paper_2507_23189_amd as mc
+    t = mc.Tally(torch.zeros((det.side_ny, det.side_nx), dtype=torch.float64),
+                 torch.zeros((det.trans_ny, det.trans_nx), dtype=torch.float64),
+                 torch.zeros(mc.MC_N_SCALARS, dtype=torch.float64), torch.zeros(64, dtype=torch.int64))
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+@pytest.mark.parametrize("case", ["dloss_dtype", "dloss_size", "dloss_strided", "d2loss_size", "cpu"])
+def test_mc_grad_refuses_bad_loss_buffers(monkeypatch, case):
+    import torch
+    import paper_2507_23189_amd as mc
+    cap = _no_library(monkeypatch)
+    _, med, _, geo, det, _ = _valid_args()
+    det.flags |= mc.MC_MOMENTS
+    n = (det.side_ny, det.side_nx)
+    tal = _cpu_tally(det, side_wk=torch.zeros(n, dtype=torch.float64), side_wl=torch.zeros(n, dtype=torch.float64))
+    g = torch.zeros(n, dtype=torch.float64)
+    h = None
+    if case == "dloss_dtype":
+        g = g.float()
+    elif case == "dloss_size":
+        g = g[:-1]
+    elif case == "dloss_strided":
+        g = torch.zeros((n[1], n[0]), dtype=torch.float64).t()
+    elif case == "d2loss_size":
+        h = torch.zeros(3, dtype=torch.float64)
+    with pytest.raises(ValueError) as e:
+        cap.mc_grad(med, geo, det, tal, g, h)
+    assert ("GPU" in str(e.value)) == (case == "cpu"), e.value
+
+
+@pytest.mark.parametrize("case", ["side_dtype", "side_shape", "scalars", "sigma_missing", "moments_missing",
+                                  "rec_shape", "workspace_dtype", "cpu"])
+def test_mc_simulate_refuses_bad_tally(monkeypatch, case):
+    import torch
+    import paper_2507_23189_amd as mc
+    cap = _no_library(monkeypatch)
+    _, med, src, geo, det, run = _valid_args()
+    tal = _cpu_tally(det)
+    if case == "side_dtype":
+        tal.side = tal.side.float()
+    elif case == "side_shape":
+        tal.side = torch.zeros((det.side_ny, det.side_nx + 1), dtype=torch.float64)
+    elif case == "scalars":
+        tal.scalars = torch.zeros(5, dtype=torch.float64)
+    elif case == "sigma_missing":
+        det.flags |= mc.MC_SIGMA
+    elif case == "moments_missing":
+        det.flags |= mc.MC_MOMENTS
+    elif case == "rec_shape":
+        det.flags |= mc.MC_RECORD
+        tal.rec_i = torch.zeros((mc._capi.MC_REC_I_N, 10), dtype=torch.int32)
+        tal.rec_f = torch.zeros((mc._capi.MC_REC_F_N, 9), dtype=torch.float32)
+    elif case == "workspace_dtype":
+        tal.workspace = torch.zeros(64, dtype=torch.float64)
+    with pytest.raises(ValueError) as e:
+        cap.mc_simulate(med, src, geo, det, run, tal)
+    assert ("GPU" in str(e.value)) == (case == "cpu"), e.value
+
+
+@pytest.mark.parametrize("case", ["inv_short", "inv_dtype", "result_short", "cpu"])
+def test_mie_table_enqueue_refuses_bad_buffers(monkeypatch, case):
+    import torch
+    cap = _no_library(monkeypatch)
+    spec = _valid_args()[0]
+    inv = torch.zeros(spec.n_cdf, dtype=torch.float32)
+    res = torch.zeros(4, dtype=torch.float64)
+    if case == "inv_short":
+        inv = inv[:-1]
+    elif case == "inv_dtype":
+        inv = inv.double()
+    elif case == "result_short":
+        res = res[:3]
+    with pytest.raises(ValueError) as e:
+        cap.mie_table_enqueue(spec, "cpu", inv_cdf=inv, result=res)
+    assert ("GPU" in str(e.value)) == (case == "cpu"), e.value
+
+
+@pytest.mark.parametrize("case", ["b_shape", "c_dtype", "a_dtype", "cpu"])
+def test_image_metrics_refuses_bad_images(monkeypatch, case):
+    import torch
+    cap = _no_library(monkeypatch)
+    a = torch.zeros((8, 8), dtype=torch.float64)
+    b = torch.zeros((8, 8), dtype=torch.float64)
+    c = None
+    if case == "b_shape":
+        b = torch.zeros((8, 9), dtype=torch.float64)
+    elif case == "c_dtype":
+        c = torch.zeros((8, 8), dtype=torch.float32)
+    elif case == "a_dtype":
+        a = a.float()
+    with pytest.raises(ValueError) as e:
+        cap.image_metrics(a, b, c)
+    assert ("GPU" in str(e.value)) == (case == "cpu"), e.value
+
+
+@pytest.mark.parametrize("case", ["out_short", "ids_dtype", "cpu"])
+def test_philox_blocks_refuses_bad_buffers(monkeypatch, case):
+    import torch
+    cap = _no_library(monkeypatch)
+    ids = torch.arange(4, dtype=torch.int64)
+    out = torch.zeros(4 * 3 * 4, dtype=torch.int32)
+    if case == "out_short":
+        out = out[:-1]
+    elif case == "ids_dtype":
+        ids = ids.int()
+    with pytest.raises(ValueError) as e:
+        cap.mc_philox_blocks(1234, 0, ids, 0, 3, out)
+    assert ("GPU" in str(e.value)) == (case == "cpu"), e.value
