@@ -41,8 +41,11 @@ def n_terms(x: float) -> int:
     return int(round(x + 4.0 * x ** (1.0 / 3.0) + 2.0))
 
 
-def mie_coefficients(x: float, m: complex):
+def mie_coefficients(x: float, m: complex, n_max: int | None = None):
     """a_n, b_n for n = 1..N (Eqs. 7-8), by the Bohren-Huffman recurrence (Sec. 2.5).
+
+    N is n_terms(x) unless n_max is given (used to check that the terms the
+    truncation drops are negligible).
 
     D_n(mx) = psi_n'(mx)/psi_n(mx) by downward recurrence from D = 0 at
     n_start = ceil(max(N, |mx|)) + 16 + ceil(8 |mx|^(1/3)) (the start error
@@ -55,7 +58,7 @@ def mie_coefficients(x: float, m: complex):
       a_n = [(D_n/m + n/x) psi_n - psi_{n-1}] / [(D_n/m + n/x) xi_n - xi_{n-1}]
       b_n = [(m D_n + n/x) psi_n - psi_{n-1}] / [(m D_n + n/x) xi_n - xi_{n-1}]
     """
-    N = n_terms(x)
+    N = n_terms(x) if n_max is None else int(n_max)
     mx = m * x
     n_start = int(math.ceil(max(N, abs(mx)))) + 16 + int(math.ceil(8.0 * abs(mx) ** (1.0 / 3.0)))
     D = np.zeros(n_start + 1, dtype=np.complex128)

@@ -89,12 +89,11 @@ def test_mie_table_parity(mc, cuda_device, case):
     gP = t.phase.cpu().numpy()
     np.testing.assert_allclose(gP, o.P, rtol=1e-10, atol=1e-14 * o.P.max())
     # The CDF is a normalised sum of P with positive weights, so a relative
-    # error eps in every P moves it by at most 2 eps; the sums' own rounding
-    # stays below 1e-13.  At small x eps is ~1e-15; near the 1024-term limit
-    # the series' conditioning leaves P agreeing to ~1e-13.
-    pos = o.P > 1e-300
-    eps_p = float(np.max(np.abs(gP[pos] - o.P[pos]) / o.P[pos]))
-    np.testing.assert_allclose(t.cdf.cpu().numpy(), o.F, rtol=0, atol=1e-13 + 2.0 * eps_p)
+    # error eps in every P moves it by at most 2 eps, plus the sums' own
+    # rounding (below 1e-13).  P agrees to ~1e-15 at small x and to ~1e-13
+    # near the 1024-term limit (the series' conditioning), so a fixed 1e-12
+    # holds for every case.
+    np.testing.assert_allclose(t.cdf.cpu().numpy(), o.F, rtol=0, atol=1e-12)
     inv = t.inv_cdf.cpu().numpy()
     ref32 = o.v.astype(np.float32)
     ulp = np.spacing(np.abs(ref32)).astype(np.float64)

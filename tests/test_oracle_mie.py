@@ -160,3 +160,19 @@ def test_printed_paper_values_loosely():
     assert t.q_abs > 0                      # the printed index absorbs a little
     # Eq. 14: sigma = Q pi d^2 / 4, micrometres squared to mm^2.
     assert q_paper * math.pi * (5e-3) ** 2 / 4 == pytest.approx(sig_paper, rel=2e-3)
+
+
+@pytest.mark.parametrize("diameter_um", [532e-3 / (math.pi * 1.33), 5.0, 10.0, 120.0])   # x = 1, 39.27, 78.5, 942
+def test_series_truncation_has_converged(diameter_um):
+    """The truncation N = round(x + 4 x^(1/3) + 2) drops only negligible terms:
+    twenty more terms change Q_ext, Q_sca and g by less than 1e-12 (relative
+    for the efficiencies).  Dropping the x^(1/3) term, for instance, changes
+    them by 2e-9 at x = 1 and by 0.06 at x = 39.27."""
+    x = mie.size_parameter(diameter_um, 532.0, 1.33)
+    m = mie.relative_index(1.59, 0.0, 1.33)
+    N = mie.n_terms(x)
+    q_ext, q_sca, _, g = mie.efficiencies(x, *mie.mie_coefficients(x, m))
+    q_ext2, q_sca2, _, g2 = mie.efficiencies(x, *mie.mie_coefficients(x, m, N + 20))
+    assert abs(q_ext - q_ext2) <= 1e-12 * q_ext2
+    assert abs(q_sca - q_sca2) <= 1e-12 * q_sca2
+    assert abs(g - g2) <= 1e-12
