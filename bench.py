@@ -65,7 +65,7 @@ METRIC = "Mie MC scatter events/s (τ=4, 1e8 photons); fwd+adjoint vs fwd-only t
 # move, all operands in vector registers) in 2 SIMD cycles, half-rate ones
 # (compares, selects, min/max/med3, shifts, conversions, 32x32-bit products
 # including v_mad_u64_u32, three-input bit operations) in 4, transcendentals
-# (rcp, sqrt, log, sin, cos) in 8; measured by issue_cost_probe.hip at 2.3-2.6,
+# (rcp, sqrt, log, sin, cos) in 8; measured by bench/issue_cost_probe.hip at 2.3-2.6,
 # 3.7-4.4 and 8.0-8.2 cycles.  A slot is one full-rate lane-instruction, so a
 # unit costs full + 2 half + 4 trans slots.
 #   step         Philox4x32-10 (20 products, 20 three-input XORs), the free-path

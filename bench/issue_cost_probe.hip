@@ -7,7 +7,7 @@
 //
 // Build and run (one GPU):
 //   hipcc --offload-arch=gfx950 -O3 -Xclang -target-feature -Xclang -packed-fp32-ops \
-//       issue_cost_probe.hip -o /tmp/issue_cost_probe && /tmp/issue_cost_probe
+//       bench/issue_cost_probe.hip -o /tmp/issue_cost_probe && /tmp/issue_cost_probe
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstdio>
