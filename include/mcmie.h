@@ -189,17 +189,42 @@ int mc_lognormal_bins(double median_um, double sigma_ln, int32_t n_bins, double 
 
 /* -------------------------------------------------------------- the walk */
 
-/* Medium filling the cuboid (Eq. 1, Eq. 16). */
+/* How a medium's coefficients are given (mc_medium_t.input). */
+#define MC_MEDIUM_TAU 0            /* optical depth along z and albedo (Eq. 1, Eq. 16) */
+#define MC_MEDIUM_MU 1             /* scattering and absorption coefficients (Sec. 3.1.1) */
+#define MC_MEDIUM_CONCENTRATION 2  /* particle concentration and cross-sections (Eq. 14, Eq. 17) */
+
+/* Medium filling the cuboid.  The walk needs the extinction coefficient
+ * mu_ext = mu_sca + mu_abs (free paths, Eq. 15) and the albedo
+ * mu_sca / mu_ext (weight update, Eq. 16); `input` says which fields give
+ * them:
+ *   MC_MEDIUM_TAU            mu_ext = tau / size_z (Eq. 1, the optical depth
+ *                            taken along the beam axis) and the albedo given,
+ *                            or, with albedo < 0, the particles' own albedo
+ *                            Q_sca / Q_ext = sigma_sca / (sigma_sca + sigma_abs);
+ *   MC_MEDIUM_MU             mu_sca and mu_abs as given;
+ *   MC_MEDIUM_CONCENTRATION  mu_sca = c sigma_sca and
+ *                            mu_abs = c sigma_abs + mu_abs_host (Eq. 17 with
+ *                            the cross-sections of Eq. 14), c in 1/mm^3.
+ * mc_medium_coefficients returns the coefficients the library derives.
+ * With mu_ext = 0 no photon interacts (the albedo is then taken as 1). */
 typedef struct {
-    double tau;            /* optical depth along z: mu_ext = tau / size_z (Eq. 1), >= 0 */
-    double albedo;         /* mu_sca / mu_ext in [0, 1]; mu_abs = (1 - albedo) mu_ext */
+    int32_t input;         /* MC_MEDIUM_TAU, MC_MEDIUM_MU or MC_MEDIUM_CONCENTRATION */
     int32_t phase;         /* MC_PHASE_MIE or MC_PHASE_HG */
+    double tau;            /* TAU: optical depth along z, >= 0 */
+    double albedo;         /* TAU: mu_sca / mu_ext in [0, 1]; < 0: sigma_sca / (sigma_sca + sigma_abs) */
+    double mu_sca, mu_abs; /* MU: coefficients in 1/mm, >= 0 */
+    double concentration_per_mm3;   /* CONCENTRATION: particles per mm^3, >= 0 */
+    double mu_abs_host;    /* CONCENTRATION: absorption of the host medium in 1/mm, >= 0 */
     int32_t n_cdf;         /* MIE: entries of inv_cdf, 2..MC_MAX_N_CDF */
+    int32_t reserved;      /* set to 0 */
     const float *inv_cdf;  /* MIE: device inverse table as written by mie_table_build (values in [0, 2]) */
     double g;              /* HG: asymmetry in (-1, 1) */
-    double sigma_sca_mm2;  /* particle cross-sections (Eq. 14), used only by mc_grad for the */
-    double sigma_abs_mm2;  /* concentration derivative; 0 and 0 make that derivative NaN */
+    double sigma_sca_mm2;  /* particle cross-sections (Eq. 14, e.g. mie_table_t.sigma_sca_mm2): used by */
+    double sigma_abs_mm2;  /* CONCENTRATION, by TAU with albedo < 0 and by mc_grad for the concentration
+                              derivative (0 and 0 make that derivative NaN) */
 } mc_medium_t;
+
 
 /* Collimated beam entering the z = 0 face (Sec. 3.1.3: parallel beam, all
  * photons with the same initial direction), a pencil or a disk. */
@@ -221,6 +246,14 @@ typedef struct {
     double n_medium;       /* index inside (> 0) */
     double n_outside;      /* index outside (> 0); equal to n_medium means no Fresnel term */
 } mc_geometry_t;
+
+/*
+ * Host only: the coefficients the walk takes from `medium` in `geometry`
+ * (Eq. 1, Eq. 16, Eq. 17): out[0] = mu_sca, out[1] = mu_abs, out[2] = mu_ext
+ * (1/mm) and out[3] = albedo, in FP64 (the walk rounds mu_ext and the albedo
+ * to FP32).  MC_EINVAL for a medium mc_simulate would reject.
+ */
+int mc_medium_coefficients(const mc_medium_t *medium, const mc_geometry_t *geometry, double out[4]);
 
 /* Detector images: side view on the +x face (rows y, columns z) and the
  * transmitted image on the +z face (rows y, columns x); pixel index =

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libmcmie.so")
 
 MC_OK, MC_EINVAL, MC_EDEVICE, MC_ENOMEM, MC_EUNSUPPORTED = 0, -1, -2, -3, -4
 MC_PHASE_MIE, MC_PHASE_HG = 0, 1
+MC_MEDIUM_TAU, MC_MEDIUM_MU, MC_MEDIUM_CONCENTRATION = 0, 1, 2
 MC_ACCUMULATE, MC_SIGMA, MC_RECORD, MC_FIX64, MC_MOMENTS, MC_MOMENTS_PIXEL2 = 1, 2, 4, 8, 16, 32
 MC_EXIT_LOG = 64
 MC_N_SCALARS = 20
@@ -56,7 +57,11 @@ class Radial(C.Structure):
 
 
 class Medium(C.Structure):
-    _fields_ = [("tau", C.c_double), ("albedo", C.c_double), ("phase", C.c_int32), ("n_cdf", C.c_int32),
+    """mc_medium_t: `input` selects tau + albedo, mu_sca + mu_abs, or a
+    particle concentration with the cross-sections (MC_MEDIUM_*)."""
+    _fields_ = [("input", C.c_int32), ("phase", C.c_int32), ("tau", C.c_double), ("albedo", C.c_double),
+                ("mu_sca", C.c_double), ("mu_abs", C.c_double), ("concentration_per_mm3", C.c_double),
+                ("mu_abs_host", C.c_double), ("n_cdf", C.c_int32), ("reserved", C.c_int32),
                 ("inv_cdf", C.c_void_p), ("g", C.c_double), ("sigma_sca_mm2", C.c_double),
                 ("sigma_abs_mm2", C.c_double)]
 
@@ -131,6 +136,7 @@ def lib():
         L.mc_metrics_work_bytes.restype = C.c_uint64
         L.mc_image_metrics.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Radial),
                                        C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_double), C.c_void_p]
+        L.mc_medium_coefficients.argtypes = [C.POINTER(Medium), C.POINTER(Geometry), C.POINTER(C.c_double)]
         L.mc_workspace_bytes.argtypes = [C.POINTER(Detector)]
         L.mc_workspace_bytes.restype = C.c_uint64
         L.mc_workspace_bytes_batch.argtypes = [C.POINTER(Detector), C.c_uint32]
@@ -146,7 +152,7 @@ def lib():
         L.mc_version.restype = C.c_int
         for f in ("mie_table_build", "mie_table_enqueue", "mc_simulate", "mc_grad", "mc_philox_blocks",
                   "mc_simulate_batch", "mc_autotune_batch", "mie_table_build_poly", "mc_lognormal_bins",
-                  "mc_image_metrics"):
+                  "mc_image_metrics", "mc_medium_coefficients"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -295,6 +301,14 @@ def mie_table_enqueue(spec: MieSpec, device="cuda", *, inv_cdf=None, result=None
         _check(lib().mie_table_enqueue(C.byref(spec), C.byref(t), _stream(stream)))
     return MieTable(t.x, complex(t.m_rel_re, t.m_rel_im), t.q_ext, t.q_sca, t.q_abs, t.g, t.sigma_ext_mm2,
                     t.sigma_sca_mm2, t.sigma_abs_mm2, t.n_terms, inv, result=res)
+
+
+def mc_medium_coefficients(medium: Medium, geometry: Geometry) -> dict:
+    """The coefficients the walk derives from `medium` (host only):
+    mu_sca, mu_abs, mu_ext in 1/mm and the albedo."""
+    out = (C.c_double * 4)()
+    _check(lib().mc_medium_coefficients(C.byref(medium), C.byref(geometry), out))
+    return dict(mu_sca=out[0], mu_abs=out[1], mu_ext=out[2], albedo=out[3])
 
 
 def mc_workspace_bytes(det: Detector) -> int:

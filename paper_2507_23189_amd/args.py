@@ -2,7 +2,7 @@
 the C-ABI argument structs.  Pure marshalling: no arithmetic of the method."""
 from __future__ import annotations
 
-from ._capi import MC_PHASE_MIE, BatchItem, Detector, Geometry, Medium, MieSpec, Run, Source
+from ._capi import MC_MEDIUM_TAU, MC_PHASE_MIE, BatchItem, Detector, Geometry, Medium, MieSpec, Run, Source
 
 
 def args_from_workload(w, table=None, *, g=None, flags=0, record_stride=1, block_size=0, grid_blocks=0,
@@ -13,7 +13,8 @@ def args_from_workload(w, table=None, *, g=None, flags=0, record_stride=1, block
     p = w.particle
     spec = MieSpec(n_medium=p.n_medium, m_re=p.m_re, m_im=p.m_im, diameter_um=p.diameter_um,
                    wavelength_nm=p.wavelength_nm, n_angles=w.n_angles, n_cdf=w.n_cdf)
-    med = Medium(tau=w.tau, albedo=w.albedo, phase=w.phase, n_cdf=w.n_cdf if w.phase == MC_PHASE_MIE else 0,
+    med = Medium(input=MC_MEDIUM_TAU, tau=w.tau, albedo=w.albedo, phase=w.phase,
+                 n_cdf=w.n_cdf if w.phase == MC_PHASE_MIE else 0,
                  inv_cdf=(table.inv_cdf.data_ptr() if (table is not None and w.phase == MC_PHASE_MIE) else None),
                  g=(g if g is not None else (table.g if table is not None else 0.0)),
                  sigma_sca_mm2=(table.sigma_sca_mm2 if table is not None else 0.0) or 0.0,

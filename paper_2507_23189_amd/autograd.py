@@ -16,9 +16,7 @@ side_l2_loss(mu_sca, mu_abs, target, sim)
 """
 from __future__ import annotations
 
-import math
-
-from ._capi import (MC_EXIT_LOG, MC_MOMENTS, MC_S_SIDE_W2, Detector, Geometry, Medium, Run, Source, Tally, mc_grad,
+from ._capi import (MC_EXIT_LOG, MC_MEDIUM_MU, MC_MOMENTS, MC_S_SIDE_W2, Detector, Geometry, Medium, Run, Source, Tally, mc_grad,
                     mc_simulate)
 
 
@@ -37,15 +35,14 @@ class SideImage:
         self._workspace = None
 
     def medium_for(self, mu_sca: float, mu_abs: float) -> Medium:
-        """Eq. 1 and Eq. 16: tau = (mu_sca + mu_abs) L_z, albedo = mu_sca / mu_ext."""
-        if not (mu_sca > 0.0 and mu_abs >= 0.0 and math.isfinite(mu_sca + mu_abs)):
-            raise ValueError("need mu_sca > 0 and mu_abs >= 0")
+        """The fixed medium with its coefficients given directly (MC_MEDIUM_MU):
+        the library derives mu_ext and the albedo."""
         m = Medium()
         for f, _ in Medium._fields_:
             setattr(m, f, getattr(self.medium, f))
-        mu_t = mu_sca + mu_abs
-        m.tau = mu_t * self.geometry.size_mm[2]
-        m.albedo = mu_sca / mu_t
+        m.input = MC_MEDIUM_MU
+        m.mu_sca = mu_sca
+        m.mu_abs = mu_abs
         return m
 
     def run_walk(self, mu_sca: float, mu_abs: float):

@@ -1228,12 +1228,63 @@ void fill_common(WalkArgs &a, const mc_source_t &src, const mc_geometry_t &geo, 
 }
 
 // Per-medium coefficients (Eq. 1 and Eq. 16): s = log2(u0) * neg_ln2_over_mu.
-void fill_medium(float &neg_ln2_over_mu, float &albedo, float &absorb, double tau, double alb, double size_z)
+void fill_medium(float &neg_ln2_over_mu, float &albedo, float &absorb, double mu_t, double alb)
 {
-    const double mu_t = tau / size_z;
     neg_ln2_over_mu = mu_t > 0.0 ? (float)(-M_LN2 / mu_t) : -__builtin_huge_valf();
     albedo = (float)alb;
     absorb = (float)(1.0 - alb);
+}
+
+// A medium's coefficients in 1/mm from the form the caller gave them in.
+struct MediumCoef {
+    double mu_sca, mu_abs, mu_ext, albedo;
+};
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+// Eq. 1 (optical depth along the beam axis), Eq. 16 (albedo) or Eq. 17
+// (concentration times the cross-sections of Eq. 14), validated.  The optical
+// depth form keeps mu_ext = tau / size_z and the given albedo exactly, the
+// others form mu_ext as the sum and the albedo as the quotient.
+int medium_coefficients(const char *fn, const mc_medium_t &m, double size_z, MediumCoef &c)
+{
+    const bool sig_ok = finite_nonneg(m.sigma_sca_mm2) && finite_nonneg(m.sigma_abs_mm2);
+    if (m.input == MC_MEDIUM_TAU) {
+        if (!finite_nonneg(m.tau)) return fail(MC_EINVAL, "%s: tau must be finite and >= 0", fn);
+        double alb = m.albedo;
+        if (alb < 0.0) {
+            if (!sig_ok || !(m.sigma_sca_mm2 + m.sigma_abs_mm2 > 0.0))
+                return fail(MC_EINVAL, "%s: albedo < 0 takes sigma_sca / (sigma_sca + sigma_abs), which needs "
+                                       "cross-sections >= 0 with a positive sum", fn);
+            alb = m.sigma_sca_mm2 / (m.sigma_sca_mm2 + m.sigma_abs_mm2);
+        } else if (!(alb <= 1.0)) {
+            return fail(MC_EINVAL, "%s: albedo must be in [0, 1] (or < 0 to derive it)", fn);
+        }
+        c.mu_ext = m.tau / size_z;
+        c.albedo = alb;
+        c.mu_sca = alb * c.mu_ext;
+        c.mu_abs = (1.0 - alb) * c.mu_ext;
+        return MC_OK;
+    }
+    if (m.input == MC_MEDIUM_MU) {
+        if (!finite_nonneg(m.mu_sca) || !finite_nonneg(m.mu_abs))
+            return fail(MC_EINVAL, "%s: mu_sca and mu_abs must be finite and >= 0", fn);
+        c.mu_sca = m.mu_sca;
+        c.mu_abs = m.mu_abs;
+    } else if (m.input == MC_MEDIUM_CONCENTRATION) {
+        if (!finite_nonneg(m.concentration_per_mm3) || !sig_ok || !finite_nonneg(m.mu_abs_host))
+            return fail(MC_EINVAL, "%s: concentration, cross-sections and mu_abs_host must be finite and >= 0", fn);
+        c.mu_sca = m.concentration_per_mm3 * m.sigma_sca_mm2;
+        c.mu_abs = m.concentration_per_mm3 * m.sigma_abs_mm2 + m.mu_abs_host;
+        if (!std::isfinite(c.mu_sca) || !std::isfinite(c.mu_abs))
+            return fail(MC_EINVAL, "%s: the coefficients overflow", fn);
+    } else {
+        return fail(MC_EINVAL, "%s: unknown medium input %d", fn, m.input);
+    }
+    c.mu_ext = c.mu_sca + c.mu_abs;
+    if (!std::isfinite(c.mu_ext)) return fail(MC_EINVAL, "%s: the coefficients overflow", fn);
+    c.albedo = c.mu_ext > 0.0 ? c.mu_sca / c.mu_ext : 1.0;
+    return MC_OK;
 }
 
 // A batched launch's schedule is written into the workspace by small kernels
@@ -1456,7 +1507,7 @@ int prepare_batch(const char *fn, const mc_batch_item_t *items, uint32_t n_items
         if (photon_scale < 1.0 && n > 0) n = std::max<uint64_t>(1, (uint64_t)std::llround((double)n * photon_scale));
         if (int rc = check_overflow(fn, n, det, rn)) return rc;
         BatchInst b{};
-        fill_medium(b.neg_ln2_over_mu, b.albedo, b.absorb, it.tau, it.albedo, geo.size_mm[2]);
+        fill_medium(b.neg_ln2_over_mu, b.albedo, b.absorb, it.tau / geo.size_mm[2], it.albedo);
         b.inv_cdf = it.inv_cdf;
         b.n_photons = n;
         b.counter = it.instance;
@@ -1504,8 +1555,8 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
 
     // ---- parameter checks (Sec. 3.1.1) ----
     if (int rc = check_geometry(fn, geo)) return rc;
-    if (!(m.tau >= 0.0) || !std::isfinite(m.tau)) return fail(MC_EINVAL, "mc_simulate: tau must be >= 0");
-    if (!(m.albedo >= 0.0 && m.albedo <= 1.0)) return fail(MC_EINVAL, "mc_simulate: albedo must be in [0, 1]");
+    MediumCoef coef{};
+    if (int rc = medium_coefficients(fn, m, geo.size_mm[2], coef)) return rc;
     if (m.phase == MC_PHASE_MIE) {
         if (m.n_cdf < 2 || m.n_cdf > MC_MAX_N_CDF)
             return fail(MC_EINVAL, "mc_simulate: n_cdf %d outside 2..%d", m.n_cdf, MC_MAX_N_CDF);
@@ -1537,7 +1588,7 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
 
     WalkArgs a{};
     fill_common(a, *source, geo, det, rn);
-    fill_medium(a.neg_ln2_over_mu, a.albedo, a.absorb, m.tau, m.albedo, geo.size_mm[2]);
+    fill_medium(a.neg_ln2_over_mu, a.albedo, a.absorb, coef.mu_ext, coef.albedo);
     a.phase = m.phase;
     a.n_cdf = m.phase == MC_PHASE_MIE ? m.n_cdf : 0;
     a.inv_cdf = m.inv_cdf;
@@ -1556,6 +1607,21 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     a.rec_rows = (det.flags & MC_RECORD) ? t.rec_rows : 0;
     a.record_stride = rn.record_stride >= 1 ? rn.record_stride : 1;
     return launch_walk(a, det, rn, t, m.phase, 1, rn.n_photons, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int mc_medium_coefficients(const mc_medium_t *medium, const mc_geometry_t *geometry, double out[4])
+{
+    using namespace mcmie;
+    clear_error();
+    if (!medium || !geometry || !out) return fail(MC_EINVAL, "mc_medium_coefficients: null argument");
+    if (int rc = check_geometry("mc_medium_coefficients", *geometry)) return rc;
+    MediumCoef c{};
+    if (int rc = medium_coefficients("mc_medium_coefficients", *medium, geometry->size_mm[2], c)) return rc;
+    out[0] = c.mu_sca;
+    out[1] = c.mu_abs;
+    out[2] = c.mu_ext;
+    out[3] = c.albedo;
+    return MC_OK;
 }
 
 extern "C" uint64_t mc_workspace_bytes(const mc_detector_t *detector)
@@ -1674,8 +1740,10 @@ extern "C" int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry,
     const mc_geometry_t geo = *geometry;
     const mc_detector_t det = *detector;
     const mc_tally_t t = *tally;
-    if (!finite_pos(geo.size_mm[2]) || !(m.tau > 0.0) || !std::isfinite(m.tau) || !(m.albedo > 0.0 && m.albedo <= 1.0))
-        return fail(MC_EINVAL, "mc_grad: needs tau > 0, albedo in (0, 1] and size_mm[2] > 0");
+    if (!finite_pos(geo.size_mm[2])) return fail(MC_EINVAL, "mc_grad: size_mm[2] must be > 0");
+    MediumCoef coef{};
+    if (int rc = medium_coefficients("mc_grad", m, geo.size_mm[2], coef)) return rc;
+    if (!(coef.mu_sca > 0.0)) return fail(MC_EINVAL, "mc_grad: needs mu_sca > 0");
     if (det.side_nx < 1 || det.side_ny < 1) return fail(MC_EINVAL, "mc_grad: side image dimensions must be >= 1");
     if (!t.side_wk || !t.side_wl || !t.scalars)
         return fail(MC_EINVAL, "mc_grad: the tally has no moment images (MC_MOMENTS)");
@@ -1688,8 +1756,7 @@ extern "C" int mc_grad(const mc_medium_t *medium, const mc_geometry_t *geometry,
     if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < (kWsScalarWords + 4) * 8)
         return fail(MC_EINVAL, "mc_grad: workspace of at least %llu bytes required",
                     (unsigned long long)((kWsScalarWords + 4) * 8));
-    const double mu_t = m.tau / geo.size_mm[2];
-    const double mu_s = m.albedo * mu_t;
+    const double mu_s = coef.mu_sca;
     hipStream_t st = (hipStream_t)stream;
     double *dots = (double *)t.workspace + 24;    // scalar words 24..27
     const uint64_t n = (uint64_t)det.side_nx * det.side_ny;

@@ -555,3 +555,66 @@ def test_philox_blocks_refuses_bad_buffers(monkeypatch, case):
     with pytest.raises(ValueError) as e:
         cap.mc_philox_blocks(1234, 0, ids, 0, 3, out)
     assert ("GPU" in str(e.value)) == (case == "cpu"), e.value
+
+
+# ---- medium input forms (Eq. 1, Eq. 16, Eq. 17) ----
+
+def _medium(**kw):
+    import paper_2507_23189_amd as mc
+    m = mc.Medium(phase=mc.MC_PHASE_HG, g=0.5)
+    for k, v in kw.items():
+        setattr(m, k, v)
+    return m
+
+
+def _geometry(lz=10.0):
+    import paper_2507_23189_amd as mc
+    geo = mc.Geometry()
+    geo.size_mm[0], geo.size_mm[1], geo.size_mm[2] = 10.0, 10.0, lz
+    geo.n_medium = geo.n_outside = 1.33
+    return geo
+
+
+def test_medium_coefficients_from_each_form():
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    geo = _geometry(lz=8.0)
+    # Optical depth along z (Eq. 1) and albedo (Eq. 16).
+    c = mc.mc_medium_coefficients(_medium(input=mc.MC_MEDIUM_TAU, tau=4.0, albedo=0.75), geo)
+    assert c == dict(mu_sca=0.375, mu_abs=0.125, mu_ext=0.5, albedo=0.75)
+    # The particles' own albedo Q_sca / Q_ext when albedo < 0.
+    c = mc.mc_medium_coefficients(_medium(input=mc.MC_MEDIUM_TAU, tau=2.0, albedo=-1.0, sigma_sca_mm2=3e-5,
+                                          sigma_abs_mm2=1e-5), geo)
+    assert c["albedo"] == 0.75 and c["mu_ext"] == 0.25
+    # Coefficients given directly.
+    c = mc.mc_medium_coefficients(_medium(input=mc.MC_MEDIUM_MU, mu_sca=0.375, mu_abs=0.125), geo)
+    assert c == dict(mu_sca=0.375, mu_abs=0.125, mu_ext=0.5, albedo=0.75)
+    # Concentration (Eq. 17): mu_sca = c sigma_sca, mu_abs = c sigma_abs + host absorption.
+    c = mc.mc_medium_coefficients(_medium(input=mc.MC_MEDIUM_CONCENTRATION, concentration_per_mm3=2048.0,
+                                          sigma_sca_mm2=2.0 ** -12, sigma_abs_mm2=2.0 ** -14, mu_abs_host=0.0625),
+                                  geo)
+    assert c == dict(mu_sca=0.5, mu_abs=0.1875, mu_ext=0.6875, albedo=0.5 / 0.6875)
+    # No scatterers: nothing interacts, the albedo is taken as 1.
+    c = mc.mc_medium_coefficients(_medium(input=mc.MC_MEDIUM_MU, mu_sca=0.0, mu_abs=0.0), geo)
+    assert c["mu_ext"] == 0.0 and c["albedo"] == 1.0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(input=3), dict(input=0, tau=-1.0), dict(input=0, tau=1.0, albedo=1.5), dict(input=0, tau=1.0, albedo=float("nan")),
+    dict(input=0, tau=1.0, albedo=-1.0), dict(input=1, mu_sca=-0.1), dict(input=1, mu_sca=0.1, mu_abs=float("inf")),
+    dict(input=2, concentration_per_mm3=-1.0, sigma_sca_mm2=1e-5), dict(input=2, concentration_per_mm3=1.0,
+                                                                       sigma_sca_mm2=1e-5, mu_abs_host=-0.1),
+    dict(input=2, concentration_per_mm3=1e300, sigma_sca_mm2=1e300),
+])
+def test_medium_forms_reject_invalid_values(kw):
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    with pytest.raises(mc.McError) as e:
+        mc.mc_medium_coefficients(_medium(**kw), _geometry())
+    assert e.value.code == mc.MC_EINVAL
+    # mc_simulate rejects the same medium before any device work.
+    spec, med, src, geo, det, run = _valid_args()
+    m = _medium(**kw)
+    tal = _tally_stub(det)
+    rc = mc.lib().mc_simulate(C.byref(m), C.byref(src), C.byref(geo), C.byref(det), C.byref(run), C.byref(tal), None)
+    assert rc == mc.MC_EINVAL

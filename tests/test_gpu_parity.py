@@ -309,3 +309,38 @@ def test_gpu_physics_pins(mc, cuda_device):
     gh = gpu_run(wh, records=True, g=0.8668)
     mu = gh["rec"]["dz"]
     assert abs(mu.mean() - 0.8668) <= 4 * mu.std() / math.sqrt(len(mu))
+
+
+def test_medium_forms_give_the_same_walk(mc, cuda_device):
+    """The optical-depth, coefficient and concentration forms of one medium
+    (Eq. 1, Eq. 16, Eq. 17) give the same FP32 walk constants and hence the
+    same tallies, bit for bit."""
+    torch = _torch()
+    w = W.TINY.replace(n_photons=20000, tau=2.0, albedo=0.75)
+    spec, *_ = mc.args_from_workload(w)
+    table = mc.mie_table_build(spec, cuda_device)
+    _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=mc.MC_FIX64)
+    lz = geo.size_mm[2]
+    mu_ext = w.tau / lz
+    forms = [med]
+    m_mu = mc.Medium.from_buffer_copy(med)
+    m_mu.input, m_mu.mu_sca, m_mu.mu_abs = mc.MC_MEDIUM_MU, 0.75 * mu_ext, 0.25 * mu_ext
+    forms.append(m_mu)
+    m_c = mc.Medium.from_buffer_copy(med)
+    m_c.input, m_c.concentration_per_mm3 = mc.MC_MEDIUM_CONCENTRATION, 1.0e4
+    m_c.sigma_sca_mm2, m_c.sigma_abs_mm2, m_c.mu_abs_host = 0.75 * mu_ext / 1.0e4, 0.0, 0.25 * mu_ext
+    forms.append(m_c)
+    consts = set()
+    for m in forms:
+        c = mc.mc_medium_coefficients(m, geo)
+        consts.add((np.float32(-math.log(2.0) / c["mu_ext"]), np.float32(c["albedo"]), np.float32(1.0 - c["albedo"])))
+    assert len(consts) == 1, consts
+    outs = []
+    for m in forms:
+        t = mc.Tally.alloc(det, cuda_device, fix64=True)
+        mc.mc_simulate(m, src, geo, det, run, t)
+        torch.cuda.synchronize()
+        outs.append(t)
+    for t in outs[1:]:
+        assert torch.equal(t.side, outs[0].side) and torch.equal(t.trans, outs[0].trans)
+        assert torch.equal(t.scalars, outs[0].scalars)
