@@ -16,8 +16,20 @@ The JSON line also carries
                 instruction class) over its measured average duration (HIP
                 events on the launch stream), against the chip's FP32 VALU
                 peak (the published 157.3 TFLOP/s as fused multiply-adds);
-  cpu_baseline  the FP64 oracle timed on this host on a bounded sample of the
-                same workload;
+  cpu_baseline  the FP64 oracle timed on this host: one thread on a leading
+                sample of the workload and every thread of the CPU share on
+                the whole workload (or a bounded leading part), with the CPU
+                model and core counts;
+  tally_error   per workload, the GPU path against the FP64 oracle at matched
+                seeds: largest |difference| per image bin in units of the bin's
+                Monte Carlo sigma, relative L2 norm of the image difference,
+                bins beyond 3 sigma, the energy-balance residual of each side,
+                and for the differentiation workload the path-moment images and
+                a gradient (--no-tally-error skips it; both come from the
+                oracle leg, which --no-cpu-baseline skips);
+  sweep         the paper-scale workload at optical depths 1, 2 and 8 and the
+                HG run at 4: scatter events/s and census fraction of each
+                (--no-sweep skips it);
   adjoint       after the timed steps, the same walk run forward only
                 (mc_simulate, then a stream wait) and forward + adjoint
                 (mc_simulate with the path-moment tallies, then mc_grad for
@@ -76,7 +88,12 @@ METRIC = "Mie MC scatter events/s (τ=4, 1e8 photons); fwd+adjoint vs fwd-only t
 #                uniforms, inverse-CDF index, fraction and lerp, cos and
 #                sin of the polar angle, sin and cos of the azimuth, the
 #                orthonormal basis (Duff et al.), new direction, Newton
-#                renormalisation
+#                renormalisation; with Henyey-Greenstein (Eq. 11) the table
+#                index, fraction and lerp (4 full, 2 half: product, two
+#                conversions, fraction, difference, fma) give way to the
+#                closed-form inverse and a clamp of v (4 full, 1 half,
+#                1 transcendental: fma, reciprocal, product, fma, product,
+#                maximum)
 #   boundary     the reflection uniform, wall axis and its direction component,
 #                clamp onto the box, unpolarised Fresnel with TIR, reflect-or-
 #                leave, exit face and reflection count
@@ -84,6 +101,7 @@ METRIC = "Mie MC scatter events/s (τ=4, 1e8 photons); fwd+adjoint vs fwd-only t
 #                weight added; other faces: face total
 CENSUS = {"step": {"full": 17, "half": 47, "trans": 4},
           "interaction": {"full": 41, "half": 7, "trans": 4},
+          "interaction_hg": {"full": 41, "half": 6, "trans": 5},
           "boundary": {"full": 14, "half": 18, "trans": 3},
           "imaged_exit": {"full": 3, "half": 5, "trans": 0},
           "other_exit": {"full": 2, "half": 0, "trans": 0}}
@@ -141,7 +159,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def census_slots(scal):
+def census_slots(scal, hg=False):
     """Algorithmic issue slots of one launch from its scalar tallies.  The
     imaged share of exits is taken from the exit weights (every exit weight
     is w0 * albedo^k, equal to 1e-3 at albedo 0.9999)."""
@@ -149,29 +167,218 @@ def census_slots(scal):
     exits = photons - scal[11] - scal[12]
     faces = scal[0:6]
     imaged = exits * (faces[1] + faces[5]) / max(faces.sum(), 1e-300)
-    return (unit_slots("step") * steps + unit_slots("interaction") * events
+    return (unit_slots("step") * steps + unit_slots("interaction_hg" if hg else "interaction") * events
             + unit_slots("boundary") * (steps - events)
             + unit_slots("imaged_exit") * imaged + unit_slots("other_exit") * (exits - imaged))
 
 
-def cpu_baseline(w, target_s: float):
-    """FP64 oracle on host threads over photons 0..n-1 of the same workload."""
-    from oracle import walk as owalk
-    threads = max(1, min(os.cpu_count() or 1, 16))
-    wk = owalk.Walk(w)
-    n = 1_000_000
-    res = wk.run(n_photons=n, threads=threads)
-    if res.seconds < 0.5 * target_s:           # scale the sample to about target_s
-        n = int(min(w.n_photons, n * target_s / max(res.seconds, 1e-3)))
-        res = wk.run(n_photons=n, threads=threads)
-    ev = res.scalars[9]
+def host_cpu():
+    """CPU model, logical CPUs, CPUs this process may run on, and the share of
+    them the benchmark uses: OMP_NUM_THREADS when set (a GPU machine allots each
+    GPU a fixed share of its host cores), else every CPU in the affinity set."""
     try:
-        cpu = open("/proc/cpuinfo").read().split("model name")[1].split("\n")[0].strip(" :\t")
+        model = open("/proc/cpuinfo").read().split("model name")[1].split("\n")[0].strip(" :\t")
     except Exception:
-        cpu = "unknown"
-    return {"value": ev / res.seconds, "unit": "scatter events/s", "cores": threads, "kind": "oracle",
-            "sample": f"photons 0..{n - 1} of the same workload (same seed and draws), FP64 C oracle, "
-                      f"{threads} host threads, {res.seconds:.1f} s, {ev:.3e} events; host CPU: {cpu}"}
+        model = "unknown"
+    total = os.cpu_count() or 1
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else total
+    share = int(os.environ.get("OMP_NUM_THREADS") or affinity)
+    return model, total, affinity, max(1, min(affinity, share))
+
+
+def cpu_baseline(w, target_s: float, gpu_value: float):
+    """FP64 oracle on the host: one thread on a leading sample of the workload,
+    then every thread of the CPU share on the whole workload (or on as much
+    of it as fits in about target_s), both on the same seed and draws."""
+    from oracle import walk as owalk
+    model, total, affinity, threads = host_cpu()
+    wk = owalk.Walk(w)
+    n1 = 250_000
+    r1 = wk.run(n_photons=n1, threads=1, chunks=1)
+    if r1.seconds < 0.15 * target_s:
+        n1 = int(min(w.n_photons, n1 * 0.15 * target_s / max(r1.seconds, 1e-3)))
+        r1 = wk.run(n_photons=n1, threads=1, chunks=1)
+    one = r1.scalars[9] / r1.seconds
+    n = int(min(w.n_photons, one * threads * target_s / max(r1.scalars[9] / n1, 1e-9)))
+    res = wk.run(n_photons=n, threads=threads)
+    ev = res.scalars[9]
+    allc = ev / res.seconds
+    return {"value": allc, "unit": "scatter events/s", "cores": threads, "kind": "oracle",
+            "sample": f"photons 0..{n - 1} of the same workload (same seed and draws), FP64 C oracle on "
+                      f"{threads} host threads, {res.seconds:.1f} s, {ev:.3e} events; one thread on photons "
+                      f"0..{n1 - 1}, {r1.seconds:.1f} s",
+            "cpu_model": model, "cores_total": total, "cores_affinity": affinity,
+            "one_core": {"value": one, "photons": n1, "seconds": r1.seconds},
+            "all_cores": {"value": allc, "threads": threads, "photons": n, "seconds": res.seconds},
+            "gpu_over_all_cores": gpu_value / allc, "gpu_over_one_core": gpu_value / one}
+
+
+def _image_error(g, o, o_w2, n, max_w=1.0):
+    """GPU image g against the oracle's o at matched seeds: largest |g - o| in
+    units of the bin's Monte Carlo sigma (sigma^2 = sum w^2 - (sum w)^2 / N,
+    from the oracle), the relative L2 norm of g - o, bins beyond 3 sigma, and
+    bins the oracle leaves empty where the GPU holds more than 3 photon weights."""
+    import numpy as np
+    sig = np.sqrt(np.maximum(o_w2 - o * o / n, 0.0))
+    d = np.abs(g - o)
+    m = sig > 0
+    return {"max_dev_over_sigma": float((d[m] / sig[m]).max()) if m.any() else 0.0,
+            "rel_l2": float(np.linalg.norm(g - o) / max(float(np.linalg.norm(o)), 1e-300)),
+            "bins_beyond_3sigma": int(np.sum(m & (d > 3.0 * sig))),
+            "empty_oracle_bins_over_3w": int(np.sum(~m & (d > 3.0 * max_w)))}
+
+
+def _energy_residual(s, n, w0):
+    """Energy bookkeeping (Eq. 16): the weight that left, was absorbed or was
+    capped, less roulette's net change, over the weight that entered, minus 1."""
+    return float((float(s[0:6].sum()) + s[6] + s[8] - s[7]) / (n * w0) - 1.0)
+
+
+def tally_error(mc, W, dev, args):
+    """Tally error of the benchmarked GPU path against the FP64 oracle at
+    matched seeds (same photon ids, Philox draws and tables' definitions), per
+    workload: the parity workload in full, the paper-scale optical depths and
+    the HG run, the differentiation workload (images, path-moment images and a
+    gradient), three batched media and the heavy polydisperse workload, each
+    on its leading photons."""
+    import numpy as np
+    import torch
+    from oracle import mie as omie
+    from oracle import walk as owalk
+    from oracle import poly as opoly
+    lg = tally_flags(mc, args)
+    sub = 1_000_000
+    rows = []
+
+    def compare(label, w, g, o, fix=False):
+        scale = 2.0 ** -32 if fix else 1.0
+        gs = np.asarray(g["scalars"], dtype=np.float64)
+        w0 = 1.0 - owalk.fresnel(w.src_dir[2], w.n_outside, w.particle.n_medium)
+        maxw = max(1.0, w.roulette_w / w.roulette_p)
+        row = {"config": label, "workload": w.name, "photons": w.n_photons,
+               "side": _image_error(g["side"] * scale, o.side, o.side_w2, w.n_photons, maxw),
+               "trans": _image_error(g["trans"] * scale, o.trans, o.trans_w2, w.n_photons, maxw),
+               "energy_residual": {"gpu": _energy_residual(gs, w.n_photons, w0),
+                                   "oracle": _energy_residual(o.scalars, w.n_photons, w0)},
+               "events_rel_diff": float(abs(gs[9] - o.scalars[9]) / max(o.scalars[9], 1.0)),
+               "absorbed_rel_diff": float(abs(gs[6] - o.scalars[6]) / max(abs(o.scalars[6]), 1e-300))}
+        rows.append(row)
+        return row
+
+    def gpu(w, table, flags, g=None, moments=False, fix=False):
+        _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g, flags=flags)
+        t = mc.Tally.alloc(det, dev, moments=moments, fix64=fix, log_photons=w.n_photons)
+        mc.mc_simulate(med, src, geo, det, run, t)
+        torch.cuda.synchronize()
+        return dict(side=t.side.cpu().numpy().astype(np.float64), trans=t.trans.cpu().numpy().astype(np.float64),
+                    scalars=t.scalars.cpu().numpy(), tally=t, med=med, geo=geo, det=det)
+
+    # The parity workload in full.
+    w = W.TINY
+    tab = mc.mie_table_build(mc.args_from_workload(w)[0], dev)
+    compare("parity tau=1 1e5", w, gpu(w, tab, lg), owalk.Walk(w).run())
+    # Paper scale: each optical depth and the HG run, leading 1e6 photons.
+    for tau in W.PAPER_TAUS:
+        w = W.paper_scale(tau).replace(n_photons=sub)
+        tab = mc.mie_table_build(mc.args_from_workload(w)[0], dev)
+        compare(f"paper tau={tau:g} mie", w, gpu(w, tab, lg), owalk.Walk(w).run())
+    w = W.paper_scale(4.0, phase=W.PHASE_HG).replace(n_photons=sub)
+    tab = mc.mie_table_build(mc.args_from_workload(w)[0], dev)
+    compare("paper tau=4 hg", w, gpu(w, tab, lg, g=tab.g),
+            owalk.Walk(w, g=omie.table_from_workload(w).g).run())
+    # Differentiation workload: images, path moments and the gradient of a
+    # fixed random linear loss against the oracle's per-photon records.
+    w = W.DIFF.replace(n_photons=sub)
+    tab = mc.mie_table_build(mc.args_from_workload(w)[0], dev)
+    g = gpu(w, tab, lg | mc.MC_MOMENTS, moments=True)
+    o = owalk.Walk(w).run(records=True)
+    row = compare("differentiation tau=4", w, g, o)
+    n = w.side_px
+    sel = (o.rec("face") == 1) & (o.rec("cause") == 0)
+    r_ = np.clip(np.floor(o.rec("py")[sel] / w.size_mm[1] * n).astype(int), 0, n - 1)
+    c_ = np.clip(np.floor(o.rec("pz")[sel] / w.size_mm[2] * n).astype(int), 0, n - 1)
+    wk = np.zeros((n, n)); wl = np.zeros((n, n))
+    np.add.at(wk, (r_, c_), o.rec("w")[sel] * o.rec("k")[sel])
+    np.add.at(wl, (r_, c_), o.rec("w")[sel] * o.rec("L")[sel])
+    gk, gl = g["tally"].side_wk.cpu().numpy(), g["tally"].side_wl.cpu().numpy()
+    row["moments_rel_l2"] = {"sum_wk": float(np.linalg.norm(gk - wk) / np.linalg.norm(wk)),
+                             "sum_wl": float(np.linalg.norm(gl - wl) / np.linalg.norm(wl))}
+    gimg = np.random.default_rng(5).normal(size=(n, n))
+    d_ms, d_ma, _ = mc.mc_grad(g["med"], g["geo"], g["det"], g["tally"], torch.tensor(gimg, device=dev))
+    mu_s = w.albedo * w.tau / w.size_mm[2]
+    term_s = gimg[r_, c_] * o.rec("w")[sel] * (o.rec("k")[sel] / mu_s - o.rec("L")[sel])
+    term_a = -gimg[r_, c_] * o.rec("w")[sel] * o.rec("L")[sel]
+    row["gradient_rel_diff"] = {"mu_sca": float(abs(d_ms - term_s.sum()) / np.abs(term_s).sum()),
+                                "mu_abs": float(abs(d_ma - term_a.sum()) / np.abs(term_a).sum()),
+                                "what": "|GPU - oracle| / sum of |per-photon terms| for a fixed random "
+                                        "dLoss/dI (numpy seed 5)"}
+    # Three batched media: the smallest, middle and largest particles.
+    ws = W.batch_workloads(256)
+    order = sorted(range(len(ws)), key=lambda i: ws[i].particle.diameter_um)
+    pick = [ws[order[0]], ws[order[len(ws) // 2]], ws[order[-1]]]
+    pick = [x.replace(n_photons=min(x.n_photons, sub)) for x in pick]
+    tabs = [mc.mie_table_build(mc.args_from_workload(x)[0], dev) for x in pick]
+    _, _, src, geo, det, run = mc.args_from_workload(pick[0])
+    tb = mc.Tally.alloc_batch(det, len(pick), dev)
+    mc.mc_simulate_batch([mc.batch_item(x, t) for x, t in zip(pick, tabs)], pick[0].n_cdf, src, geo, det, run, tb)
+    torch.cuda.synchronize()
+    for i, x in enumerate(pick):
+        gi = dict(side=tb.side[i].cpu().numpy(), trans=tb.trans[i].cpu().numpy(), scalars=tb.scalars[i].cpu().numpy())
+        compare(f"batch medium {x.instance} d={x.particle.diameter_um:.2f}um tau={x.tau:.2f} "
+                f"albedo={x.albedo:.4f}", x, gi, owalk.Walk(x).run())
+    # Heavy polydisperse workload, leading 1e6 photons, int64 images.
+    w = W.HEAVY.replace(n_photons=sub)
+    tab = mc.table_for_workload(w, dev)
+    compare("heavy polydisperse tau=16", w, gpu(w, tab, lg | mc.MC_FIX64, fix=True),
+            owalk.Walk(w, opoly.poly_table_from_workload(w)).run(), fix=True)
+    return rows
+
+
+def oracle_leg(mc, W, w, dev, args, gpu_value):
+    """The part of the benchmark that runs the oracle: its timing on the host
+    and the tally error of the GPU path against it."""
+    log("bench: timing the oracle on the host")
+    base = cpu_baseline(w, args.cpu_seconds, gpu_value)
+    err = None
+    if not args.no_tally_error:
+        log("bench: tally error against the oracle")
+        t0 = time.perf_counter()
+        err = tally_error(mc, W, dev, args)
+        log(f"bench: tally error done in {time.perf_counter() - t0:.1f} s")
+    return base, err
+
+
+def sweep_timing(mc, W, dev, args):
+    """The paper-scale workload at its other optical depths and the HG run on
+    the headline's seeds: scatter events/s and the census fraction of each,
+    mc_simulate timed with HIP events on the launch stream."""
+    import torch
+    out = []
+    stream = torch.cuda.current_stream()
+    for tau, phase in [(t, W.PHASE_MIE) for t in W.PAPER_TAUS if t != 4.0] + [(4.0, W.PHASE_HG)]:
+        w = W.paper_scale(tau, phase=phase)
+        table = mc.mie_table_build(mc.args_from_workload(w)[0], dev)
+        g = table.g if phase == W.PHASE_HG else None
+        _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g, flags=tally_flags(mc, args))
+        t = mc.Tally.alloc(det, dev, log_photons=w.n_photons)
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        for _ in range(3):
+            mc.mc_simulate(med, src, geo, det, run, t)
+        ms = []
+        for _ in range(max(3, args.steps // 2)):
+            ev[0].record(stream)
+            mc.mc_simulate(med, src, geo, det, run, t)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        s = t.scalars.cpu().numpy()
+        kernel_s = sum(ms) / len(ms) * 1e-3
+        slots = census_slots(s, phase == W.PHASE_HG)
+        out.append({"workload": w.name, "tau": tau, "phase": "mie" if phase == W.PHASE_MIE else "hg",
+                    "photons": w.n_photons, "events_per_photon": float(s[9] / s[10]),
+                    "steps_per_photon": float(s[14] / s[10]), "mc_simulate_ms": kernel_s * 1e3,
+                    "events_per_s": float(s[9]) / kernel_s, "frac": slots / kernel_s / PEAK_SLOTS_PER_S})
+    return out
 
 
 def adjoint_timing(mc, w, dev, args):
@@ -367,6 +574,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-heavy", action="store_true")
     ap.add_argument("--no-analysis", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the other optical depths and the HG run")
+    ap.add_argument("--no-tally-error", action="store_true", help="skip the tally error against the oracle")
     ap.add_argument("--atomic-tally", action="store_true",
                     help="tally image exits with global atomics instead of the exit log")
     args = ap.parse_args()
@@ -439,6 +648,8 @@ def main():
     log("bench: heavy timing done")
     analysis = None if args.no_analysis else analysis_timing(mc, W, dev, args)
     log("bench: analysis done")
+    sweep = None if args.no_sweep else sweep_timing(mc, W, dev, args)
+    log("bench: optical-depth sweep done")
 
     scal = [t.scalars.cpu().numpy() for t in tallies[args.warmup:]]
     events = float(sum(s[9] for s in scal))
@@ -483,10 +694,13 @@ def main():
         "batch": batch,
         "heavy": heavy,
         "analysis": analysis,
+        "sweep": sweep,
     }
     if not args.no_cpu_baseline:
-        log("bench: timing the oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        base, err = oracle_leg(mc, W, w, dev, args, out["value"])
+        out["cpu_baseline"] = base
+        if not args.no_tally_error:
+            out["tally_error"] = err
     print(json.dumps(out), flush=True)
 
 
