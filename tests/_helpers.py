@@ -77,3 +77,28 @@ def image_within_3sigma(img_g, img_o, w2_o, n_photons, max_w=1.0):
     tol = 3.0 * np.sqrt(var)
     tol = np.where(img_o == 0.0, 3.0 * max_w, tol)
     return np.abs(img_g - img_o) <= tol + 1e-9 * np.abs(img_o)
+
+
+def unmatched_totals(rec, bad):
+    """Per-face exit weight, absorbed weight and scatter events of the
+    photons flagged in `bad`, from one side's per-photon records: subtracted
+    from that side's scalar tallies, they leave the sums over the photons
+    both sides walked alike."""
+    out = np.zeros(10)
+    exited = bad & (rec["cause"] == 0)
+    for f in range(6):
+        out[f] = np.sum(rec["w"][exited & (rec["face"] == f)], dtype=np.float64)
+    out[6] = np.sum(rec["A"][bad], dtype=np.float64)
+    out[9] = np.sum(rec["k"][bad].astype(np.float64))
+    return out
+
+
+def assert_matched_scalars(g_scal, g_rec, o_scal, o_rec, ok, rtol=1e-4):
+    """Scalar tallies restricted to trajectory-matched photons: face totals
+    and absorbed weight agree to rtol (FP32 transport against FP64), scatter
+    events exactly (matched photons have the same k)."""
+    gs = np.asarray(g_scal[:10], dtype=np.float64) - unmatched_totals(g_rec, ~ok)
+    os_ = np.asarray(o_scal[:10], dtype=np.float64) - unmatched_totals(o_rec, ~ok)
+    for i in list(range(7)):
+        assert abs(gs[i] - os_[i]) <= rtol * abs(os_[i]) + 1e-9, (i, gs[i], os_[i])
+    assert gs[9] == os_[9], (gs[9], os_[9])

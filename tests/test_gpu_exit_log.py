@@ -170,11 +170,22 @@ def test_log_against_oracle(mc, cuda_device):
 def test_log_full_size_launch(mc, cuda_device, table):
     """The full tau = 4 launch of 1e8 photons (512 x 512 images) in the
     launch configuration the benchmark times: the log path equals the atomic
-    path bit for bit, and nearly every exit went through the log."""
+    path, and the record-writing kernel whose sampled trajectories the parity
+    tests replay in the oracle, bit for bit; nearly every exit went through
+    the log."""
+    import torch
     w = W.paper_scale(4.0)
     a = _run(mc, cuda_device, w, table, mc.MC_FIX64, n_photons=w.n_photons)
     b = _run(mc, cuda_device, w, table, mc.MC_FIX64 | mc.MC_EXIT_LOG, n_photons=w.n_photons)
     _same(a, b)
+    stride = 50_000
+    _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=mc.MC_FIX64 | mc.MC_RECORD,
+                                                       record_stride=stride)
+    t = mc.Tally.alloc(det, cuda_device, fix64=True, record_rows=w.n_photons // stride)
+    mc.mc_simulate(med, src, geo, det, run, t)
+    torch.cuda.synchronize()
+    _same(b, {k: getattr(t, k).cpu().numpy() for k in ("side", "trans", "scalars")})
+    assert int(t.rec_i[0].ge(0).sum()) > 0
     assert a["scalars"][10] == w.n_photons
     # Waves that take more than their share of photons can run out of chunks
     # in a range; those few exits are added directly.

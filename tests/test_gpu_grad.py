@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from _helpers import gpu_run
+from _helpers import FREC, IREC, gpu_run, oracle_rec, trajectory_match
 from oracle import walk as owalk
 
 pytestmark = pytest.mark.gpu
@@ -70,6 +70,35 @@ def test_moments_and_gradient_match_oracle(mc, cuda_device):
     scale_a = np.sqrt(np.sum((gp * r.rec("w")[sel] * r.rec("L")[sel]) ** 2))
     assert abs(d_ms - o_ms) <= 0.05 * scale_s
     assert abs(d_ma - o_ma) <= 0.05 * scale_a
+    # Over the photons both sides walked alike (same trajectory to 1e-4 and
+    # the same side pixel), the gradient agrees to 1e-4 of the sum of its
+    # terms' sizes: the library's value less the GPU records' terms of the
+    # other photons against the oracle's terms of the matched ones.
+    ri, rf = tal.rec_i.cpu().numpy(), tal.rec_f.cpu().numpy().astype(np.float64)
+    grec = {k: ri[i] for i, k in enumerate(IREC)}
+    grec.update({k: rf[i] for i, k in enumerate(FREC)})
+    orec = oracle_rec(r)
+    n = w.side_px
+    f32 = np.float32
+    g_side = (grec["face"] == 1) & (grec["cause"] == 0)
+    o_side = (orec["face"] == 1) & (orec["cause"] == 0)
+    g_pix = (np.floor(grec["py"].astype(f32) * f32(n / w.size_mm[1])).astype(np.int64).clip(0, n - 1) * n
+             + np.floor(grec["pz"].astype(f32) * f32(n / w.size_mm[2])).astype(np.int64).clip(0, n - 1))
+    o_pix = (np.floor(orec["py"] / w.size_mm[1] * n).astype(np.int64).clip(0, n - 1) * n
+             + np.floor(orec["pz"] / w.size_mm[2] * n).astype(np.int64).clip(0, n - 1))
+    ok = trajectory_match(grec, orec, box=10.0) & (g_side == o_side) & (~g_side | (g_pix == o_pix))
+    assert ok.mean() >= 0.999
+    gflat = gimg.reshape(-1)
+
+    def terms(rec, side, pix, sel):
+        m = side & sel
+        gp, wv = gflat[pix[m]], rec["w"][m]
+        return gp * wv * (rec["k"][m] / mu_s - rec["L"][m]), -gp * wv * rec["L"][m]
+
+    gs_bad, ga_bad = terms(grec, g_side, g_pix, ~ok)
+    os_ok, oa_ok = terms(orec, o_side, o_pix, ok)
+    assert abs((d_ms - gs_bad.sum()) - os_ok.sum()) <= 1e-4 * np.abs(os_ok).sum()
+    assert abs((d_ma - ga_bad.sum()) - oa_ok.sum()) <= 1e-4 * np.abs(oa_ok).sum()
     assert d_c == pytest.approx(table.sigma_sca_mm2 * d_ms + table.sigma_abs_mm2 * d_ma, rel=1e-12)
     # Second-order moments, per pixel (MC_MOMENTS_PIXEL2) and summed over the
     # image (scalars), and the self-correlation correction (h = 2).
