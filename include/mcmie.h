@@ -342,6 +342,28 @@ int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_g
                 void *stream);
 
 /*
+ * mc_simulate for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments and results as mc_simulate, except that
+ * tally->workspace and tally->workspace_bytes are ignored: the images are
+ * tallied in one fixed-point copy (instead of eight per-XCD copies) held in a
+ * device array of MC_NOALLOC_SCRATCH_BYTES that the library keeps on every
+ * GPU it runs on until the process ends.  The call allocates nothing (no
+ * hipMalloc, no hipFree, no allocating library routine); the caller still
+ * owns the images, scalars, records and moment buffers.
+ * Limits: side + transmitted pixels at most 2^21 (2^20 with MC_SIGMA), and no
+ * MC_EXIT_LOG (the log needs a caller workspace): MC_EINVAL otherwise.
+ * The array is cleared by the call's own fill kernel on `stream` (no memset),
+ * and every call on one GPU shares it: calls that overlap in time on one GPU
+ * (other streams, other threads) race and give wrong tallies.  With MC_FIX64
+ * the results equal mc_simulate's bit for bit.  Asynchronous.
+ */
+#define MC_NOALLOC_SCRATCH_BYTES 16777472ull   /* 8 * (32 + 2^21) */
+int mc_simulate_noalloc(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
+                        const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,
+                        void *stream);
+
+/*
  * Batched launch: many media in one persistent kernel.  Every item is a
  * medium in the same cuvette, with the same source, detector and run
  * settings, the Mie phase function (its own device inverse table of n_cdf

@@ -17,7 +17,7 @@ from ._capi import (MC_ACCUMULATE, MC_EDEVICE, MC_EINVAL, MC_ENOMEM, MC_EUNSUPPO
                     mc_autotune_batch, mc_workspace_bytes_batch, MiePoly, MC_MAX_BINS, mie_table_build_poly,
                     mc_lognormal_bins, Radial, MC_METRICS_N, MC_MAX_ANNULI, image_metrics,
                     mie_table_enqueue, MC_MEDIUM_TAU, MC_MEDIUM_MU, MC_MEDIUM_CONCENTRATION,
-                    mc_medium_coefficients)
+                    mc_medium_coefficients, mc_simulate_noalloc, MC_NOALLOC_SCRATCH_BYTES)
 from .args import args_from_workload, batch_item, table_for_workload
 from .autograd import SideImage, side_image, side_l2_loss
 

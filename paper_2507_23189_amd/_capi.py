@@ -17,6 +17,7 @@ MC_PHASE_MIE, MC_PHASE_HG = 0, 1
 MC_MEDIUM_TAU, MC_MEDIUM_MU, MC_MEDIUM_CONCENTRATION = 0, 1, 2
 MC_ACCUMULATE, MC_SIGMA, MC_RECORD, MC_FIX64, MC_MOMENTS, MC_MOMENTS_PIXEL2 = 1, 2, 4, 8, 16, 32
 MC_EXIT_LOG = 64
+MC_NOALLOC_SCRATCH_BYTES = 8 * (32 + (1 << 21))
 MC_N_SCALARS = 20
 MC_S_FACE, MC_S_ABSORBED, MC_S_ROULETTE_NET, MC_S_CAPPED_W, MC_S_EVENTS = 0, 6, 7, 8, 9
 MC_S_PHOTONS, MC_S_ROULETTE_KILLS, MC_S_CAPPED, MC_S_REFLECTIONS, MC_S_STEPS, MC_S_RESERVED = 10, 11, 12, 13, 14, 15
@@ -122,6 +123,8 @@ def lib():
         L.mie_table_enqueue.argtypes = [C.POINTER(MieSpec), C.POINTER(_MieTableC), C.c_void_p]
         L.mc_simulate.argtypes = [C.POINTER(Medium), C.POINTER(Source), C.POINTER(Geometry),
                                   C.POINTER(Detector), C.POINTER(Run), C.POINTER(_TallyC), C.c_void_p]
+        L.mc_simulate_noalloc.argtypes = [C.POINTER(Medium), C.POINTER(Source), C.POINTER(Geometry),
+                                          C.POINTER(Detector), C.POINTER(Run), C.POINTER(_TallyC), C.c_void_p]
         L.mc_grad.argtypes = [C.POINTER(Medium), C.POINTER(Geometry), C.POINTER(Detector), C.POINTER(_TallyC),
                               C.c_void_p, C.c_void_p, C.c_double, C.POINTER(C.c_double), C.c_void_p]
         L.mc_philox_blocks.argtypes = [C.c_uint64, C.c_uint32, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
@@ -150,7 +153,7 @@ def lib():
                                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]
         L.mc_last_error.restype = C.c_char_p
         L.mc_version.restype = C.c_int
-        for f in ("mie_table_build", "mie_table_enqueue", "mc_simulate", "mc_grad", "mc_philox_blocks",
+        for f in ("mie_table_build", "mie_table_enqueue", "mc_simulate", "mc_simulate_noalloc", "mc_grad", "mc_philox_blocks",
                   "mc_simulate_batch", "mc_autotune_batch", "mie_table_build_poly", "mc_lognormal_bins",
                   "mc_image_metrics", "mc_medium_coefficients"):
             getattr(L, f).restype = C.c_int
@@ -396,7 +399,8 @@ class Tally:
             t.trans_w2 = torch.empty_like(t.trans)
         return t
 
-    def validate(self, det: Detector, n_items: Optional[int] = None, *, grad: bool = False, **extra):
+    def validate(self, det: Detector, n_items: Optional[int] = None, *, grad: bool = False,
+                 need_workspace: bool = True, **extra):
         """Check every buffer the library will touch against `det` (and
         n_items media for a batched launch) before a call: dtypes, shapes and
         contiguity first, then that they (and the tensors in `extra`, already
@@ -413,7 +417,8 @@ class Tally:
             used["tally.trans"] = _require(self.trans, "tally.trans", img_t, shape=trans_shape)
         used["tally.scalars"] = _require(self.scalars, "tally.scalars", torch.float64,
                                          numel=MC_N_SCALARS * (1 if n_items is None else n_items))
-        used["tally.workspace"] = _require(self.workspace, "tally.workspace", torch.int64)
+        if need_workspace:
+            used["tally.workspace"] = _require(self.workspace, "tally.workspace", torch.int64)
         if (det.flags & MC_SIGMA) and not grad:
             used["tally.side_w2"] = _require(self.side_w2, "tally.side_w2", img_t, shape=side_shape)
             used["tally.trans_w2"] = _require(self.trans_w2, "tally.trans_w2", img_t, shape=trans_shape)
@@ -453,6 +458,19 @@ def mc_simulate(medium: Medium, source: Source, geometry: Geometry, detector: De
     tc = tally._c()
     _check(lib().mc_simulate(C.byref(medium), C.byref(source), C.byref(geometry), C.byref(detector),
                              C.byref(run), C.byref(tc), _stream(stream)))
+
+
+def mc_simulate_noalloc(medium: Medium, source: Source, geometry: Geometry, detector: Detector, run: Run,
+                        tally: Tally, stream=None) -> None:
+    """mc_simulate with the library's own device scratch in place of a
+    workspace (tally.workspace may be None): allocates nothing.  At most 2^21
+    image pixels (2^20 with MC_SIGMA), no MC_EXIT_LOG; calls overlapping on
+    one GPU race."""
+    tally.validate(detector, need_workspace=False)
+    tc = tally._c()
+    tc.workspace, tc.workspace_bytes = None, 0
+    _check(lib().mc_simulate_noalloc(C.byref(medium), C.byref(source), C.byref(geometry), C.byref(detector),
+                                     C.byref(run), C.byref(tc), _stream(stream)))
 
 
 def mc_grad(medium: Medium, geometry: Geometry, detector: Detector, tally: Tally, dloss_dside,

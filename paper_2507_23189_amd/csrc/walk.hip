@@ -54,10 +54,18 @@
 #include <cmath>
 #include <cstdint>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
 #include "philox.hpp"
+
+// Device scratch of mc_simulate_noalloc: the scalar words and one fixed-point
+// copy of the images (and squared-weight images), for callers that cannot
+// allocate a workspace.  Every GPU the library runs on holds its own copy
+// until the process ends.
+constexpr unsigned long long kNoAllocWords = 32 + (1ull << 21);
+static __device__ __align__(256) unsigned long long scratch[kNoAllocWords];
 
 namespace mcmie {
 namespace {
@@ -100,6 +108,7 @@ struct WalkArgs {
     unsigned long long *ws_img;    // workspace: kCopies x n_pix fixed-point weight sums
     unsigned long long *ws_img2;   // workspace (MC_SIGMA): kCopies x n_pix squared-weight sums
     uint64_t n_pix;
+    uint32_t copy_mask;       // image copy of a wave: XCC_ID & copy_mask (kCopies - 1, or 0 for one copy)
     int32_t *rec_i;
     float *rec_f;
     double *side_wk, *side_wl;     // MC_MOMENTS: per side pixel, sum w k and sum w L
@@ -236,6 +245,8 @@ __device__ __forceinline__ uint32_t log_index(uint32_t key, uint32_t bits)
 }
 constexpr int kBatchScal = 16;             // LDS scalar words per medium in a batched launch
 constexpr uint64_t kWsScalarWords = 32;    // workspace scalar words per medium
+static_assert(kNoAllocWords == kWsScalarWords + (1ull << 21) && kNoAllocWords * 8 == MC_NOALLOC_SCRATCH_BYTES,
+              "scratch holds the scalar words and 2^21 image words");
 constexpr int kLdsBallistic = 15;          // LDS scalar word (per medium) counting first-step exits
 constexpr int kWsBallistic = 19;           // workspace word (per medium) of that count
 constexpr int kWsBeamKey = 20;             // workspace word (first medium): beam exit key + 1, or 0
@@ -319,7 +330,7 @@ void walk_kernel(WalkArgs a)
     __syncthreads();
 
     const int lane = __lane_id();
-    const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) % kCopies;   // hwreg(HW_REG_XCC_ID, 0, 4)
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20) & a.copy_mask;   // hwreg(HW_REG_XCC_ID, 0, 4)
     unsigned long long *my_img = a.ws_img + (uint64_t)xcc * a.n_pix;
     unsigned long long *my_img2 = SIGMA ? a.ws_img2 + (uint64_t)xcc * a.n_pix : nullptr;
     float *q_y = s_queue + (threadIdx.x >> 6) * (kQueueArrays * kQueue);
@@ -929,7 +940,7 @@ __global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, c
     }
 }
 
-// Sum the per-XCD fixed-point copies of every pixel (integer adds, so the
+// Sum the n_copies fixed-point copies of every pixel (integer adds, so the
 // order is immaterial) and add them to the caller's images, as int64 (FIX) or
 // converted to double.  Weight sums of the +x and +z images also give those
 // faces' totals.
@@ -941,7 +952,7 @@ __global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, c
 // Unscattered first-step exits were only counted (workspace word kWsBallistic
 // of each medium); the beam pixel (word kWsBeamKey) gets count x ball_w.
 template <bool FIX>
-__global__ __launch_bounds__(256) void finalize_images(const unsigned long long *copies, uint64_t n_total,
+__global__ __launch_bounds__(256) void finalize_images(const unsigned long long *copies, int n_copies, uint64_t n_total,
                                                        uint64_t n_pix, uint32_t n_side, void *side, void *trans,
                                                        unsigned long long *face_side, unsigned long long *face_trans,
                                                        uint64_t face_stride, const unsigned long long *ws_scal,
@@ -960,8 +971,7 @@ __global__ __launch_bounds__(256) void finalize_images(const unsigned long long 
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pix;
          i += (uint64_t)gridDim.x * blockDim.x) {
         unsigned long long v = 0ull;
-#pragma unroll
-        for (int c = 0; c < kCopies; ++c) v += copies[(uint64_t)c * n_total + key0 + i];
+        for (int c = 0; c < n_copies; ++c) v += copies[(uint64_t)c * n_total + key0 + i];
         if (ws_scal[kWsBeamKey] == i + 1) v += ws_scal[inst * kWsScalarWords + kWsBallistic] * ball_w;
         const bool is_side = i < n_side;
         const uint64_t j = is_side ? i : i - n_side;
@@ -1076,10 +1086,10 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 // kCopies fixed-point copies of the images of every medium (and of the
 // squared-weight images with MC_SIGMA); a batched launch appends its schedule
 // (one BatchInst per medium).
-uint64_t workspace_words(const mc_detector_t &d, uint64_t n_inst = 1)
+uint64_t workspace_words(const mc_detector_t &d, uint64_t n_inst = 1, uint64_t copies = kCopies)
 {
     const uint64_t n_pix = (uint64_t)d.side_nx * d.side_ny + (uint64_t)d.trans_nx * d.trans_ny;
-    return kWsScalarWords * n_inst + (uint64_t)kCopies * n_pix * n_inst * ((d.flags & MC_SIGMA) ? 2 : 1);
+    return kWsScalarWords * n_inst + copies * n_pix * n_inst * ((d.flags & MC_SIGMA) ? 2 : 1);
 }
 
 // The exit log (MC_EXIT_LOG) follows the workspace words: the fill bytes of
@@ -1223,6 +1233,7 @@ void fill_common(WalkArgs &a, const mc_source_t &src, const mc_geometry_t &geo, 
     a.pix_scale[1] = (float)(det.side_nx / geo.size_mm[2]);
     a.pix_scale[2] = (float)(det.trans_ny / geo.size_mm[1]);
     a.pix_scale[3] = (float)(det.trans_nx / geo.size_mm[0]);
+    a.copy_mask = kCopies - 1;
     a.n_side = (uint32_t)((uint64_t)det.side_nx * det.side_ny);
     a.n_pix_inst = (uint32_t)((uint64_t)det.side_nx * det.side_ny + (uint64_t)det.trans_nx * det.trans_ny);
 }
@@ -1313,14 +1324,15 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     const uint64_t n_pix = a.n_pix_inst, n_side = a.n_side, n_trans = n_pix - n_side;
     const uint64_t n_total = n_pix * n_inst;
     unsigned long long *ws = (unsigned long long *)t.workspace;
+    const uint64_t copies = (uint64_t)a.copy_mask + 1;
     a.ws_scal = ws;
     a.ws_img = ws + kWsScalarWords * n_inst;
-    a.ws_img2 = (det.flags & MC_SIGMA) ? a.ws_img + (uint64_t)kCopies * n_total : nullptr;
+    a.ws_img2 = (det.flags & MC_SIGMA) ? a.ws_img + copies * n_total : nullptr;
     a.n_pix = n_total;
     a.n_inst = n_inst;
 
     const bool use_log = (det.flags & MC_EXIT_LOG) != 0;
-    const uint64_t ws_words = batch ? workspace_words(det, n_inst) : workspace_words(det);
+    const uint64_t ws_words = workspace_words(det, n_inst, copies);
 
     // ---- launch shape: 1024-lane blocks (768 with path moments), two per CU, each with
     // the table (single medium), the scalar words, the per-wave exit queues and
@@ -1455,13 +1467,13 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     const float w0sq = a.w0 * a.w0;
     const unsigned long long ball_w = (unsigned long long)std::llrint((double)a.w0 * kFix);
     const unsigned long long ball_w2 = (unsigned long long)std::llrint((double)w0sq * kFix);
-    hipLaunchKernelGGL(fin, dim3(fin_x, n_inst), dim3(256), 0, st, a.ws_img, n_total, n_pix, (uint32_t)n_side, t.side,
-                       t.trans, ws + MC_S_FACE + 1, ws + MC_S_FACE + 5, kWsScalarWords,
+    hipLaunchKernelGGL(fin, dim3(fin_x, n_inst), dim3(256), 0, st, a.ws_img, (int)copies, n_total, n_pix,
+                       (uint32_t)n_side, t.side, t.trans, ws + MC_S_FACE + 1, ws + MC_S_FACE + 5, kWsScalarWords,
                        (const unsigned long long *)ws, ball_w);
     if (sig)
-        hipLaunchKernelGGL(fin, dim3(fin_x, n_inst), dim3(256), 0, st, a.ws_img2, n_total, n_pix, (uint32_t)n_side,
-                           t.side_w2, t.trans_w2, (unsigned long long *)nullptr, (unsigned long long *)nullptr,
-                           kWsScalarWords, (const unsigned long long *)ws, ball_w2);
+        hipLaunchKernelGGL(fin, dim3(fin_x, n_inst), dim3(256), 0, st, a.ws_img2, (int)copies, n_total, n_pix,
+                           (uint32_t)n_side, t.side_w2, t.trans_w2, (unsigned long long *)nullptr,
+                           (unsigned long long *)nullptr, kWsScalarWords, (const unsigned long long *)ws, ball_w2);
     hipLaunchKernelGGL(finalize_scalars, dim3(n_inst), dim3(64), 0, st, (const unsigned long long *)ws, t.scalars);
     MC_HIP_CHECK(hipGetLastError());
     return MC_OK;
@@ -1538,20 +1550,24 @@ int prepare_batch(const char *fn, const mc_batch_item_t *items, uint32_t n_items
 }  // namespace
 }  // namespace mcmie
 
-extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
-                           const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,
-                           void *stream)
+namespace mcmie {
+namespace {
+
+// The walk of mc_simulate.  With `scratch_ws` set, the caller's workspace is
+// ignored: the images are tallied in one fixed-point copy held in that device
+// array (noalloc callers) instead of in per-XCD copies in the workspace.
+int simulate(const char *fn, const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
+             const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally, void *scratch_ws,
+             void *stream)
 {
-    using namespace mcmie;
     clear_error();
     if (!medium || !source || !geometry || !detector || !run || !tally)
-        return fail(MC_EINVAL, "mc_simulate: null argument");
+        return fail(MC_EINVAL, "%s: null argument", fn);
     const mc_medium_t m = *medium;
     const mc_geometry_t geo = *geometry;
     const mc_detector_t det = *detector;
     const mc_run_t rn = *run;
-    const mc_tally_t t = *tally;
-    const char *fn = "mc_simulate";
+    mc_tally_t t = *tally;
 
     // ---- parameter checks (Sec. 3.1.1) ----
     if (int rc = check_geometry(fn, geo)) return rc;
@@ -1559,36 +1575,48 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     if (int rc = medium_coefficients(fn, m, geo.size_mm[2], coef)) return rc;
     if (m.phase == MC_PHASE_MIE) {
         if (m.n_cdf < 2 || m.n_cdf > MC_MAX_N_CDF)
-            return fail(MC_EINVAL, "mc_simulate: n_cdf %d outside 2..%d", m.n_cdf, MC_MAX_N_CDF);
-        if (!m.inv_cdf) return fail(MC_EINVAL, "mc_simulate: inv_cdf is required for MC_PHASE_MIE");
+            return fail(MC_EINVAL, "%s: n_cdf %d outside 2..%d", fn, m.n_cdf, MC_MAX_N_CDF);
+        if (!m.inv_cdf) return fail(MC_EINVAL, "%s: inv_cdf is required for MC_PHASE_MIE", fn);
     } else if (m.phase == MC_PHASE_HG) {
-        if (!(m.g > -1.0 && m.g < 1.0)) return fail(MC_EINVAL, "mc_simulate: HG g must be in (-1, 1)");
+        if (!(m.g > -1.0 && m.g < 1.0)) return fail(MC_EINVAL, "%s: HG g must be in (-1, 1)", fn);
     } else {
-        return fail(MC_EINVAL, "mc_simulate: unknown phase %d", m.phase);
+        return fail(MC_EINVAL, "%s: unknown phase %d", fn, m.phase);
+    }
+    if (scratch_ws) {
+        // The library's array stands in for the workspace (checked by check_setup).
+        t.workspace = scratch_ws;
+        t.workspace_bytes = kNoAllocWords * 8;
     }
     if (int rc = check_setup(fn, *source, geo, det, rn, t)) return rc;
     if ((det.flags & MC_RECORD) && (rn.record_stride < 1 || (t.rec_rows > 0 && (!t.rec_i || !t.rec_f))))
-        return fail(MC_EINVAL, "mc_simulate: MC_RECORD needs record_stride >= 1 and, for rec_rows > 0, "
-                               "rec_i and rec_f");
-    if (rn.photon_offset > UINT64_MAX - rn.n_photons) return fail(MC_EINVAL, "mc_simulate: photon ids overflow");
+        return fail(MC_EINVAL, "%s: MC_RECORD needs record_stride >= 1 and, for rec_rows > 0, rec_i and rec_f", fn);
+    if (rn.photon_offset > UINT64_MAX - rn.n_photons) return fail(MC_EINVAL, "%s: photon ids overflow", fn);
     if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_RECORD | MC_FIX64 | MC_MOMENTS | MC_MOMENTS_PIXEL2 | MC_EXIT_LOG))
-        return fail(MC_EINVAL, "mc_simulate: unknown detector flags 0x%x", det.flags);
+        return fail(MC_EINVAL, "%s: unknown detector flags 0x%x", fn, det.flags);
     if ((det.flags & MC_EXIT_LOG) && (det.flags & MC_RECORD))
-        return fail(MC_EINVAL, "mc_simulate: MC_EXIT_LOG does not combine with MC_RECORD");
+        return fail(MC_EINVAL, "%s: MC_EXIT_LOG does not combine with MC_RECORD", fn);
     if ((det.flags & MC_MOMENTS) && (!t.side_wk || !t.side_wl))
-        return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS needs side_wk and side_wl");
+        return fail(MC_EINVAL, "%s: MC_MOMENTS needs side_wk and side_wl", fn);
     if ((det.flags & MC_MOMENTS_PIXEL2) && (!(det.flags & MC_MOMENTS) || !t.side_w2k || !t.side_w2l))
-        return fail(MC_EINVAL, "mc_simulate: MC_MOMENTS_PIXEL2 needs MC_MOMENTS, side_w2k and side_w2l");
-    if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < workspace_words(det) * 8)
-        return fail(MC_EINVAL, "mc_simulate: workspace needs %llu bytes, 8-byte aligned",
+        return fail(MC_EINVAL, "%s: MC_MOMENTS_PIXEL2 needs MC_MOMENTS, side_w2k and side_w2l", fn);
+    const uint64_t copies = scratch_ws ? 1 : kCopies;
+    if (!t.workspace || ((uintptr_t)t.workspace & 7) || t.workspace_bytes < workspace_words(det, 1, copies) * 8) {
+        if (scratch_ws)
+            return fail(MC_EINVAL, "%s: the images need %llu bytes of scratch, more than the library's %llu "
+                        "(at most 2^21 pixels over both images, 2^20 with MC_SIGMA)", fn,
+                        (unsigned long long)(workspace_words(det, 1, copies) * 8),
+                        (unsigned long long)(kNoAllocWords * 8));
+        return fail(MC_EINVAL, "%s: workspace needs %llu bytes, 8-byte aligned", fn,
                     (unsigned long long)(workspace_words(det) * 8));
+    }
     if (int rc = check_overflow(fn, rn.n_photons, det, rn)) return rc;
     const uint64_t n_pix = (uint64_t)det.side_nx * det.side_ny + (uint64_t)det.trans_nx * det.trans_ny;
-    if (n_pix >= 0xFFFFFFFFull) return fail(MC_EINVAL, "mc_simulate: images exceed 2^32 - 2 pixels in total");
+    if (n_pix >= 0xFFFFFFFFull) return fail(MC_EINVAL, "%s: images exceed 2^32 - 2 pixels in total", fn);
 
     WalkArgs a{};
     fill_common(a, *source, geo, det, rn);
     fill_medium(a.neg_ln2_over_mu, a.albedo, a.absorb, coef.mu_ext, coef.albedo);
+    a.copy_mask = (uint32_t)(copies - 1);
     a.phase = m.phase;
     a.n_cdf = m.phase == MC_PHASE_MIE ? m.n_cdf : 0;
     a.inv_cdf = m.inv_cdf;
@@ -1607,6 +1635,59 @@ extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source,
     a.rec_rows = (det.flags & MC_RECORD) ? t.rec_rows : 0;
     a.record_stride = rn.record_stride >= 1 ? rn.record_stride : 1;
     return launch_walk(a, det, rn, t, m.phase, 1, rn.n_photons, nullptr, (hipStream_t)stream);
+}
+
+// Address of this device's copy of `scratch`, looked up once per device
+// with the device current (the array's name is a host-side stand-in).
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {nullptr};
+
+int device_scratch(const char *fn, void **out)
+{
+    int dev = 0;
+    MC_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(MC_EDEVICE, "%s: device index %d out of range", fn, dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MC_EDEVICE, "%s: hipGetSymbolAddress(scratch) failed: %s", fn, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MC_OK;
+}
+
+}  // namespace
+}  // namespace mcmie
+
+extern "C" int mc_simulate(const mc_medium_t *medium, const mc_source_t *source, const mc_geometry_t *geometry,
+                           const mc_detector_t *detector, const mc_run_t *run, const mc_tally_t *tally,
+                           void *stream)
+{
+    return mcmie::simulate("mc_simulate", medium, source, geometry, detector, run, tally, nullptr, stream);
+}
+
+extern "C" int mc_simulate_noalloc(const mc_medium_t *medium, const mc_source_t *source,
+                                   const mc_geometry_t *geometry, const mc_detector_t *detector, const mc_run_t *run,
+                                   const mc_tally_t *tally, void *stream)
+{
+    using namespace mcmie;
+    const char *fn = "mc_simulate_noalloc";
+    clear_error();
+    if (!detector || !tally) return fail(MC_EINVAL, "%s: null argument", fn);
+    if (detector->flags & MC_EXIT_LOG)
+        return fail(MC_EINVAL, "%s: MC_EXIT_LOG needs a caller workspace (use mc_simulate)", fn);
+    if (!dims_ok(*detector)) return fail(MC_EINVAL, "%s: image dimensions must be >= 1", fn);
+    if (workspace_words(*detector, 1, 1) > kNoAllocWords)
+        return fail(MC_EINVAL, "%s: the images need %llu bytes of scratch, more than the library's %llu "
+                    "(at most 2^21 pixels over both images, 2^20 with MC_SIGMA)", fn,
+                    (unsigned long long)(workspace_words(*detector, 1, 1) * 8),
+                    (unsigned long long)(kNoAllocWords * 8));
+    void *ws = nullptr;
+    if (int rc = device_scratch(fn, &ws)) return rc;
+    return simulate(fn, medium, source, geometry, detector, run, tally, ws, stream);
 }
 
 extern "C" int mc_medium_coefficients(const mc_medium_t *medium, const mc_geometry_t *geometry, double out[4])

@@ -97,6 +97,8 @@ int main(void)
     expect("overflow bound", mc_simulate(&med, &src, &geo, &det, &r2, &tal, NULL), MC_EINVAL);
     r2 = run; r2.block_size = 100;
     expect("block size", mc_simulate(&med, &src, &geo, &det, &r2, &tal, NULL), MC_EINVAL);
+    d2 = det; d2.flags = MC_SIGMA; d2.side_nx = d2.side_ny = d2.trans_nx = d2.trans_ny = 1024;
+    expect("noalloc size", mc_simulate_noalloc(&med, &src, &geo, &d2, &run, &tal, NULL), MC_EINVAL);
     expect("null", mc_simulate(NULL, &src, &geo, &det, &run, &tal, NULL), MC_EINVAL);
     double grad[3];
     m2 = med; m2.albedo = 0.0;

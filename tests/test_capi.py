@@ -618,3 +618,22 @@ def test_medium_forms_reject_invalid_values(kw):
     tal = _tally_stub(det)
     rc = mc.lib().mc_simulate(C.byref(m), C.byref(src), C.byref(geo), C.byref(det), C.byref(run), C.byref(tal), None)
     assert rc == mc.MC_EINVAL
+
+
+def test_noalloc_walk_refuses_before_any_device_work():
+    """mc_simulate_noalloc checks its fixed scratch size and the exit log on
+    the host: MC_EINVAL without touching a device."""
+    import paper_2507_23189_amd as mc
+    _lib_path()
+    spec, med, src, geo, det, run = _valid_args()
+    tal = _tally_stub(det)
+    det.flags = mc.MC_SIGMA
+    det.side_nx = det.side_ny = det.trans_nx = det.trans_ny = 1024
+    rc = mc.lib().mc_simulate_noalloc(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                                      C.byref(tal), None)
+    assert rc == mc.MC_EINVAL and b"scratch" in mc.lib().mc_last_error()
+    det.flags = mc.MC_EXIT_LOG
+    det.side_nx = det.side_ny = det.trans_nx = det.trans_ny = 64
+    rc = mc.lib().mc_simulate_noalloc(C.byref(med), C.byref(src), C.byref(geo), C.byref(det), C.byref(run),
+                                      C.byref(tal), None)
+    assert rc == mc.MC_EINVAL and b"MC_EXIT_LOG" in mc.lib().mc_last_error()
