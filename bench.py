@@ -14,8 +14,11 @@ The JSON line also carries
                 of the method (counts of steps, interactions, boundary steps
                 and exits, each priced in full-rate FP32 VALU issue slots by
                 instruction class) over its measured average duration (HIP
-                events on the launch stream), against the chip's FP32 VALU
-                peak (the published 157.3 TFLOP/s as fused multiply-adds);
+                events the library records on the launch stream right before
+                and after that kernel), against the chip's FP32 VALU peak (the
+                published 157.3 TFLOP/s as fused multiply-adds); the same
+                census over the whole mc_simulate (with the log binning and
+                finalize kernels) is reported beside it;
   cpu_baseline  the FP64 oracle timed on this host: one thread on a leading
                 sample of the workload and every thread of the CPU share on
                 the whole workload (or a bounded leading part), with the CPU
@@ -28,8 +31,8 @@ The JSON line also carries
                 a gradient (--no-tally-error skips it; both come from the
                 oracle leg, which --no-cpu-baseline skips);
   sweep         the paper-scale workload at optical depths 1, 2 and 8 and the
-                HG run at 4: scatter events/s and census fraction of each
-                (--no-sweep skips it);
+                HG run at 4: scatter events/s over mc_simulate and the census
+                fraction of each walk kernel (--no-sweep skips it);
   adjoint       after the timed steps, the same walk run forward only
                 (mc_simulate, then a stream wait) and forward + adjoint
                 (mc_simulate with the path-moment tallies, then mc_grad for
@@ -362,22 +365,28 @@ def sweep_timing(mc, W, dev, args):
         _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g, flags=tally_flags(mc, args))
         t = mc.Tally.alloc(det, dev, log_photons=w.n_photons)
         ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        wev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        run.time_walk(*wev)
         for _ in range(3):
             mc.mc_simulate(med, src, geo, det, run, t)
-        ms = []
+        ms, wms = [], []
         for _ in range(max(3, args.steps // 2)):
             ev[0].record(stream)
             mc.mc_simulate(med, src, geo, det, run, t)
             ev[1].record(stream)
             torch.cuda.synchronize()
             ms.append(ev[0].elapsed_time(ev[1]))
+            wms.append(wev[0].elapsed_time(wev[1]))
         s = t.scalars.cpu().numpy()
-        kernel_s = sum(ms) / len(ms) * 1e-3
+        sim_s = sum(ms) / len(ms) * 1e-3
+        walk_s = sum(wms) / len(wms) * 1e-3
         slots = census_slots(s, phase == W.PHASE_HG)
         out.append({"workload": w.name, "tau": tau, "phase": "mie" if phase == W.PHASE_MIE else "hg",
                     "photons": w.n_photons, "events_per_photon": float(s[9] / s[10]),
-                    "steps_per_photon": float(s[14] / s[10]), "mc_simulate_ms": kernel_s * 1e3,
-                    "events_per_s": float(s[9]) / kernel_s, "frac": slots / kernel_s / PEAK_SLOTS_PER_S})
+                    "steps_per_photon": float(s[14] / s[10]), "mc_simulate_ms": sim_s * 1e3,
+                    "walk_kernel_ms": walk_s * 1e3, "events_per_s": float(s[9]) / sim_s,
+                    "frac": slots / walk_s / PEAK_SLOTS_PER_S,
+                    "frac_mc_simulate": slots / sim_s / PEAK_SLOTS_PER_S})
     return out
 
 
@@ -605,6 +614,11 @@ def main():
     tallies = [mc.Tally.alloc(det_probe, dev, log_photons=w.n_photons)]
     tallies += [mc.Tally.alloc(det_probe, dev, log_photons=w.n_photons, workspace=tallies[0].workspace)
                 for _ in range(args.warmup + args.steps - 1)]
+    # Per step: HIP events around mc_simulate (init, walk, log binning,
+    # finalize) and, recorded by the library on the same stream, around the
+    # walk kernel alone.
+    sim_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.warmup + args.steps)]
     walk_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.warmup + args.steps)]
 
@@ -622,7 +636,8 @@ def main():
             table = mc.mie_table_build(spec, dev)
         _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g_hg, flags=flags,
                                                            block_size=args.block_size, grid_blocks=args.grid_blocks)
-        e0, e1 = walk_ev[i]
+        run.time_walk(*walk_ev[i])
+        e0, e1 = sim_ev[i]
         e0.record(stream)
         mc.mc_simulate(med, src, geo, det, run, tallies[i])
         e1.record(stream)
@@ -655,8 +670,9 @@ def main():
     events = float(sum(s[9] for s in scal))
     photons = float(sum(s[10] for s in scal))
     elapsed = t1 - t0
-    walk_ms = [walk_ev[i][0].elapsed_time(walk_ev[i][1]) for i in range(args.warmup, args.warmup + args.steps)]
-    walk_avg_s = sum(walk_ms) / len(walk_ms) * 1e-3
+    timed = range(args.warmup, args.warmup + args.steps)
+    walk_avg_s = sum(walk_ev[i][0].elapsed_time(walk_ev[i][1]) for i in timed) / args.steps * 1e-3
+    sim_avg_s = sum(sim_ev[i][0].elapsed_time(sim_ev[i][1]) for i in timed) / args.steps * 1e-3
     slots = census_slots(scal[-1])
     achieved = slots / walk_avg_s
     s_last = scal[-1]
@@ -682,10 +698,13 @@ def main():
                      "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S,
                      "traffic": measured_traffic(args) if (args.tau == 4.0 and args.photons == 100_000_000
                                                            and phase == W.PHASE_MIE) else None,
-                     "kernel": ("mc_simulate (init, walk_kernel, finalize)" if args.atomic_tally else
-                                "mc_simulate (init, walk_kernel, log_bin, finalize)"),
+                     "kernel": "walk_kernel (the photon walk; HIP events the library records around it)",
                      "tally": "atomic" if args.atomic_tally else "exit log",
-                     "kernel_ms": walk_avg_s * 1e3, "slots_per_launch": slots},
+                     "kernel_ms": walk_avg_s * 1e3, "slots_per_launch": slots,
+                     "mc_simulate_ms": sim_avg_s * 1e3,
+                     "frac_mc_simulate": slots / sim_avg_s / PEAK_SLOTS_PER_S,
+                     "mc_simulate": ("init, walk_kernel, finalize" if args.atomic_tally else
+                                     "init, walk_kernel, log_bin, finalize")},
         "photons_per_s": photons / elapsed,
         "events_per_photon": s_last[9] / s_last[10],
         "steps_per_photon": s_last[14] / s_last[10],

@@ -234,8 +234,8 @@ typedef struct {
     double beam_radius_mm; /* 0: pencil beam; > 0: a parallel beam whose photons enter uniformly
                               on the disk of this radius around pos_mm (Sec. 4.1), drawn from each
                               photon's Philox block at the reserved step counter 2^32 - 1 (radius
-                              R sqrt(u0), azimuth 2 pi u1); the disk must lie inside the z = 0 face
-                              and max_steps must then be below 2^32 - 1.  A beam whose refracted
+                              R sqrt(u0), azimuth 2 pi u1, a counter no step reaches); the disk must
+                              lie inside the z = 0 face.  A beam whose refracted
                               direction has no x (y) component must not reach the x = size
                               (y = size) edge of the face: MC_EINVAL */
 } mc_source_t;
@@ -275,7 +275,7 @@ typedef struct {
     uint64_t photon_offset;/* id of the first photon; ids are offset .. offset + n - 1 */
     uint64_t seed;         /* Philox4x32-10 key (seed_lo, seed_hi) */
     uint32_t instance;     /* Philox counter word 1 (independent medium instances) */
-    uint32_t max_steps;    /* step cap per photon, >= 1 */
+    uint32_t max_steps;    /* step cap per photon, 1..2^24 */
     double roulette_w;     /* Russian roulette below this weight (0 disables) */
     double roulette_p;     /* survival probability in (0, 1]; survivors' weight / p */
     uint64_t record_stride;/* MC_RECORD: photon offset + r * stride goes to row r (>= 1) */
@@ -283,6 +283,9 @@ typedef struct {
     int32_t grid_blocks;   /* blocks; 0 = library choice (enough to fill every CU) */
     uint32_t chunk;        /* photons a wave claims at a time, 1..65536; 0 = library choice */
     uint32_t reserved;     /* set to 0 */
+    void *walk_events[2];  /* optional hipEvent_t pair (NULL: none): mc_simulate records them on its
+                              stream right before and right after the walk kernel, so the caller can
+                              time that kernel alone (hipEventElapsedTime) */
 } mc_run_t;
 
 /* Caller-owned DEVICE outputs and workspace. */
@@ -313,11 +316,11 @@ uint64_t mc_workspace_bytes(const mc_detector_t *detector);
 
 /*
  * Bytes of workspace for a walk of n_photons photons with MC_EXIT_LOG set in
- * detector->flags: mc_workspace_bytes plus a log in which each wave of a full
- * launch owns the same number of chunks (64 entries of 8 bytes and a fill
- * byte) in each of 64 key ranges: 1.5 chunks per 64 of the wave's share of
- * photons in a range, plus one (about 12 bytes per photon plus 269 MB).
- * Exits spread over the images normally never find that full.  0 for a NULL
+ * detector->flags: mc_workspace_bytes plus a log in which each block of a
+ * full launch (512 blocks) owns a region of the same number of 8-byte entries
+ * in each of 64 key ranges, 1.5 times its share of photons in a range plus
+ * 256 (about 12 bytes per photon plus 67 MB), and a count per region.  Exits
+ * spread over the images normally never find their region full.  0 for a NULL
  * or invalid detector, or one without MC_EXIT_LOG.  The log is scratch: walks
  * run one after another on one stream may share a workspace.
  */

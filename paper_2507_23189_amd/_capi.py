@@ -84,7 +84,19 @@ class Run(C.Structure):
     _fields_ = [("n_photons", C.c_uint64), ("photon_offset", C.c_uint64), ("seed", C.c_uint64),
                 ("instance", C.c_uint32), ("max_steps", C.c_uint32), ("roulette_w", C.c_double),
                 ("roulette_p", C.c_double), ("record_stride", C.c_uint64), ("block_size", C.c_int32),
-                ("grid_blocks", C.c_int32), ("chunk", C.c_uint32), ("reserved", C.c_uint32)]
+                ("grid_blocks", C.c_int32), ("chunk", C.c_uint32), ("reserved", C.c_uint32),
+                ("walk_events", C.c_void_p * 2)]
+
+    def time_walk(self, start, end):
+        """Have the library record torch.cuda.Events `start` and `end` right
+        before and after the walk kernel (None, None: stop)."""
+        for i, ev in enumerate((start, end)):
+            if ev is None:
+                self.walk_events[i] = None
+                continue
+            if not ev.cuda_event:
+                ev.record()      # creates the underlying event
+            self.walk_events[i] = ev.cuda_event
 
 
 class BatchItem(C.Structure):

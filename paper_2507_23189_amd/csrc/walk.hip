@@ -114,12 +114,12 @@ struct WalkArgs {
     double *side_wk, *side_wl;     // MC_MOMENTS: per side pixel, sum w k and sum w L
     double *side_w2k, *side_w2l;   // MC_MOMENTS_PIXEL2: per side pixel, sum w^2 k and sum w^2 L
     uint64_t rec_rows, record_stride;
-    // Exit log (kOptLog): the fill of every chunk (bytes, zeroed first) and
-    // the entries; chunk (range, wave, j) is (range * waves + wave) * log_chunks + j.
+    // Exit log (kOptLog): block b's entries of key range r occupy
+    // log[(r * gridDim.x + b) * log_cap ...], their number (at most log_cap)
+    // is log_count[r * gridDim.x + b], written when the block ends.
     unsigned long long *log;
-    uint8_t *log_fill;
-    uint32_t log_chunks, log_bits;   // log_bits: scrambled group index width, >= 6
-    uint32_t log_waves;              // waves in the launch
+    uint32_t *log_count;
+    uint32_t log_cap, log_bits;      // log_bits: scrambled group index width, >= 6
     // Batched launch: media in schedule order, work units over all of them.
     const BatchInst *insts;
     uint32_t n_inst;          // media (slots) in the launch
@@ -209,29 +209,22 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 constexpr int kQueue = 64;                 // queued image exits per wave
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;   // free tally-cache slot
 
 constexpr int kOptSigma = 1, kOptRecord = 2, kOptMoments = 4, kOptBatch = 8, kOptLog = 16;
-// Exit log: image exits appended as (key << 32 | weight bits) to chunks of
-// kLogChunk entries.  Keys fall into kLogBuckets ranges; in each range's
-// region every wave of the launch owns log_chunks chunks, which it fills in
-// turn (no claim, no global atomic).  Keys go to ranges by groups of eight
-// (one 64-byte line of a tally copy): the group g is scrambled by
-// p = g * kLogHashMul mod 2^bits (an odd multiplier, so a bijection), its top
-// six bits pick the range and the rest, with the key's place in its group,
-// index the key within the range.  Bright spots of an image thus spread
-// evenly over the ranges.
-constexpr uint32_t kLogChunk = 64;
+// Exit log: image exits appended as (key << 32 | weight bits).  Keys fall
+// into kLogBuckets ranges; every block of the launch owns a region of log_cap
+// entries in each range's part of the log and appends to it at the position a
+// counter in its LDS hands out (no global atomic).  The waves of a block thus
+// fill the same few lines of each range together, which stay in the L2 until
+// they are whole.  Keys go to ranges by groups of eight (one 64-byte line of a
+// tally copy): the group g is scrambled by p = g * kLogHashMul mod 2^bits (an
+// odd multiplier, so a bijection), its top six bits pick the range and the
+// rest, with the key's place in its group, index the key within the range.
+// Bright spots of an image thus spread evenly over the ranges.
 constexpr uint32_t kLogBuckets = 64;
-constexpr uint32_t kLogMaxChunks = 255;    // chunks per wave and range (an 8-bit cursor field)
 constexpr uint32_t kLogHistBits = 13;      // keys per binning block: 2^13 (64 KB of int64 sums)
 constexpr uint32_t kLogHashMul = 0x9E3779B1u;
 __device__ __forceinline__ uint32_t log_scramble(uint32_t key, uint32_t bits)
@@ -271,7 +264,7 @@ void walk_kernel(WalkArgs a)
     // (MC_N_SCALARS, or kBatchScal per medium), tally cache (slots words of
     // weight, [SIGMA] slots words of squared weight, slots uint32 keys),
     // per-wave exit queues (3 x kQueue floats, a fourth for the medium's slot),
-    // with the exit log then 64 16-bit log cursors per wave.
+    // with the exit log then the block's kLogBuckets append counters.
     // (The kernel declares no static LDS: the dynamic array starts at offset 0,
     // and its 16-byte alignment keeps the 64-bit words below aligned.)
     extern __shared__ __attribute__((aligned(16))) float s_table[];
@@ -283,13 +276,10 @@ void walk_kernel(WalkArgs a)
     unsigned long long *s_cw2 = s_cw + (SIGMA ? slots : 0);
     uint32_t *s_key = (uint32_t *)(s_cw2 + slots);
     float *s_queue = (float *)(s_key + slots);
-    // Exit log cursor of each wave and key range, 16 bits (two ranges per
-    // word): open chunk j (of the wave's log_chunks in the range) << 8 |
-    // entries taken (at most 64 between flushes).  j = log_chunks: the wave
-    // has filled all its chunks of the range.
-    uint32_t *s_cur = (uint32_t *)(s_queue + (blockDim.x >> 6) * (kQueueArrays * kQueue));
+    // Exit log: entries the block has appended to each key range.
+    uint32_t *s_lcnt = (uint32_t *)(s_queue + (blockDim.x >> 6) * (kQueueArrays * kQueue));
     if (LOG)
-        for (int i = threadIdx.x; i < (int)(blockDim.x >> 6) * (int)(kLogBuckets / 2); i += blockDim.x) s_cur[i] = 0u;
+        for (int i = threadIdx.x; i < (int)kLogBuckets; i += blockDim.x) s_lcnt[i] = 0u;
 
     if (PHASE == MC_PHASE_MIE && !GLOBAL_TABLE)
         for (int i = threadIdx.x; i < a.n_cdf; i += blockDim.x) s_table[i] = a.inv_cdf[i];
@@ -344,8 +334,6 @@ void walk_kernel(WalkArgs a)
     // slot holds another pixel, a global atomic.  With the exit log the exits
     // are appended to the log instead; a global atomic is then the fallback
     // for a range whose region of the log is full.
-    uint32_t *my_cur = s_cur + (threadIdx.x >> 6) * (kLogBuckets / 2);
-    const uint32_t wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     auto flush = [&](uint32_t n) {
         __builtin_amdgcn_wave_barrier();
         const bool act = (uint32_t)lane < n;
@@ -369,34 +357,18 @@ void walk_kernel(WalkArgs a)
             wq2 = SIGMA ? fix(wf * wf) : 0ull;
         }
         if (LOG) {
-            // Append to the wave's open chunk of the key's range: the LDS
-            // add hands out positions; those past the chunk's end (at most 64
-            // of them) continue in the wave's next chunk, and the lane that
-            // got position 64 records the full chunk and moves the cursor on
-            // by one chunk.  Past the wave's last chunk, exits are added
-            // directly.
+            // Append to the block's region of the key's range at the position
+            // the block's LDS counter hands out; past the region's end, the
+            // exit is added directly.
             const uint32_t bucket = log_bucket(key, a.log_bits);
-            const uint32_t sh = (bucket & 1u) * 16u;
-            uint32_t *word = &my_cur[bucket >> 1];
-            const uint32_t first = (bucket * a.log_waves + wave_id) * a.log_chunks;   // the wave's chunk 0
             bool direct = false;
             if (act) {
-                const uint32_t cur = (atomicAdd(word, 1u << sh) >> sh) & 0xFFFFu;
-                const uint32_t j = cur >> 8, f = cur & 0xFFu;   // f < 128
-                const uint32_t to = j + (f >> 6);
-                if (to < a.log_chunks)
-                    a.log[((uint64_t)(first + to) << 6) | (f & 63u)] =
+                const uint32_t e = atomicAdd(&s_lcnt[bucket], 1u);
+                if (e < a.log_cap)
+                    a.log[(uint64_t)(bucket * gridDim.x + blockIdx.x) * a.log_cap + e] =
                         ((unsigned long long)key << 32) | __float_as_uint(wf);
                 else
                     direct = true;
-                if (f == kLogChunk) {
-                    if (j < a.log_chunks) {
-                        a.log_fill[first + j] = (uint8_t)kLogChunk;
-                        atomicAdd(word, (256u - kLogChunk) << sh);   // j + 1, f - 64
-                    } else {
-                        atomicSub(word, kLogChunk << sh);            // stays past the last chunk
-                    }
-                }
             }
             if (direct) {
                 atomicAdd(my_img + key, fix(wf));
@@ -576,6 +548,22 @@ void walk_kernel(WalkArgs a)
             }
 
             pending = false;
+
+            // Lane counters stay below 2^31: steps bound the others, and a
+            // photon adds at most max_steps <= 2^24.  Past 2^31 they move into
+            // the 64-bit LDS words (batched: of the lane's medium).
+            if (__ballot(acc_steps >= 0x80000000u)) {
+                if (BATCH) {
+                    if (acc_steps >= 0x80000000u) flush_lane();
+                } else {
+                    atomicAdd(&s_scal[MC_S_EVENTS], (unsigned long long)acc_events);
+                    atomicAdd(&s_scal[MC_S_STEPS], (unsigned long long)acc_steps);
+                    atomicAdd(&s_scal[MC_S_REFLECTIONS], (unsigned long long)acc_refl);
+                    atomicAdd(&s_scal[MC_S_PHOTONS], (unsigned long long)acc_photons);
+                    atomicAdd(&s_scal[kLdsBallistic], (unsigned long long)acc_ball);
+                    acc_events = acc_steps = acc_refl = acc_photons = acc_ball = 0;
+                }
+            }
 
             // ---- refill free lanes ---------------------------------------------
             if (q_rem == 0 && !exhausted) {
@@ -770,13 +758,6 @@ void walk_kernel(WalkArgs a)
         }
     }
     flush(q_n);
-    if (LOG) {
-        // Close the wave's open chunks: lane i records the fill of range i's.
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t cur = (my_cur[lane >> 1] >> ((lane & 1) * 16)) & 0xFFFFu;
-        if ((cur >> 8) < a.log_chunks)
-            a.log_fill[(lane * a.log_waves + wave_id) * a.log_chunks + (cur >> 8)] = (uint8_t)(cur & 0xFFu);
-    }
 
     // ---- block-level flush of the scalar tallies and the cache ---------------
     if (BATCH) {
@@ -791,15 +772,19 @@ void walk_kernel(WalkArgs a)
         }
     } else {
         const unsigned long long wabs = wave_sum(acc_abs);
-        const uint32_t wev = wave_sum(acc_events), wst = wave_sum(acc_steps), wrf = wave_sum(acc_refl),
-                       wph = wave_sum(acc_photons), wbl = wave_sum(acc_ball);
+        // Lane counters are below 2^32; their wave sums are taken in 64 bits.
+        const unsigned long long wev = wave_sum((unsigned long long)acc_events);
+        const unsigned long long wst = wave_sum((unsigned long long)acc_steps);
+        const unsigned long long wrf = wave_sum((unsigned long long)acc_refl);
+        const unsigned long long wph = wave_sum((unsigned long long)acc_photons);
+        const unsigned long long wbl = wave_sum((unsigned long long)acc_ball);
         if (lane == 0) {
-            if (wbl) atomicAdd(&s_scal[kLdsBallistic], (unsigned long long)wbl);
+            if (wbl) atomicAdd(&s_scal[kLdsBallistic], wbl);
             atomicAdd(&s_scal[MC_S_ABSORBED], wabs);
-            atomicAdd(&s_scal[MC_S_EVENTS], (unsigned long long)wev);
-            atomicAdd(&s_scal[MC_S_STEPS], (unsigned long long)wst);
-            atomicAdd(&s_scal[MC_S_REFLECTIONS], (unsigned long long)wrf);
-            atomicAdd(&s_scal[MC_S_PHOTONS], (unsigned long long)wph);
+            atomicAdd(&s_scal[MC_S_EVENTS], wev);
+            atomicAdd(&s_scal[MC_S_STEPS], wst);
+            atomicAdd(&s_scal[MC_S_REFLECTIONS], wrf);
+            atomicAdd(&s_scal[MC_S_PHOTONS], wph);
         }
         if (MOMENTS) {
             const double m0 = wave_sum(acc_w2), m1 = wave_sum(acc_w2k), m2 = wave_sum(acc_w2l);
@@ -828,6 +813,10 @@ void walk_kernel(WalkArgs a)
         atomicAdd(my_img + key, s_cw[i]);
         if (SIGMA) atomicAdd(my_img2 + key, s_cw2[i]);
     }
+    // The block's entries in each range of the exit log (all its waves have
+    // appended: the barrier above).
+    if (LOG && threadIdx.x < kLogBuckets)
+        a.log_count[threadIdx.x * gridDim.x + blockIdx.x] = min(s_lcnt[threadIdx.x], a.log_cap);
 }
 
 // Zero the workspace, and the outputs unless accumulating.  (Fill kernels,
@@ -864,17 +853,17 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
 }
 
 // Sum the exit log into the per-XCD image copies.  Block (range b, part p,
-// copy s) takes the s-th eighth of range b's chunks (empty ones have fill 0),
-// adds the fixed-point
-// weights (and squared weights) of the entries whose index within the range
-// lies in part p into an LDS histogram of 2^kLogHistBits sums, then adds the
-// non-zero sums into copy s.  Those keys of copy s have no other writer (the
-// walk's fallback atomics have completed), so plain loads and stores do.
-// The sums are of the same fix() values the walk would have added, so the
-// images equal those of the atomic path bit for bit.
+// copy s) takes the regions of range b that the s-th eighth of the walk's
+// blocks wrote (log_count entries each), adds the fixed-point weights (and
+// squared weights) of the entries whose index within the range lies in part
+// p into an LDS histogram of 2^kLogHistBits sums, then adds the non-zero sums
+// into copy s.  Those keys of copy s have no other writer (the walk's
+// fallback atomics have completed), so plain loads and stores do.  The sums
+// are of the same fix() values the walk would have added, so the images
+// equal those of the atomic path bit for bit.
 template <bool SIGMA>
-__global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, const uint8_t *fill,
-                                                uint64_t per_range_chunks, unsigned long long *copies,
+__global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, const uint32_t *count, uint32_t cap,
+                                                uint32_t walk_blocks, unsigned long long *copies,
                                                 unsigned long long *copies2, uint64_t n_total, uint32_t parts,
                                                 uint32_t bits, uint32_t inv_mul)
 {
@@ -888,30 +877,25 @@ __global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, c
         if (SIGMA) s_hist2[i] = 0ull;
     }
     __syncthreads();
-    const uint64_t c0 = per_range_chunks * s / kCopies, c1 = per_range_chunks * (s + 1) / kCopies;
-    const uint64_t region = (uint64_t)b * per_range_chunks;
+    const uint32_t g0 = (uint32_t)((uint64_t)walk_blocks * s / kCopies);
+    const uint32_t g1 = (uint32_t)((uint64_t)walk_blocks * (s + 1) / kCopies);
     const uint32_t lane = threadIdx.x & 63u, waves = blockDim.x >> 6;
-    constexpr uint32_t U = 4;   // chunks in flight per wave
-    // Each wave reads the fills of 64 chunks at once, then the entries of
-    // the non-empty ones, U chunks at a time.
-    for (uint64_t g = c0 + (uint64_t)(threadIdx.x >> 6) * 64; g < c1; g += (uint64_t)waves * 64) {
-        const uint32_t my_fill = g + lane < c1 ? fill[region + g + lane] : 0u;
-        uint64_t left = __ballot(my_fill != 0u);
-        while (left) {
-            uint32_t at[U], f[U];
+    constexpr uint32_t U = 4;   // entries in flight per lane
+    // Each wave takes every waves-th region and reads its entries U x 64 at a time.
+    for (uint32_t g = g0 + (threadIdx.x >> 6); g < g1; g += waves) {
+        const uint64_t region = (uint64_t)b * walk_blocks + g;
+        const uint32_t n = count[region];
+        const unsigned long long *ent = log + region * cap;
+        for (uint32_t base = 0; base < n; base += U * 64) {
             unsigned long long e[U];
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
-                at[u] = left ? (uint32_t)__builtin_ctzll(left) : 0u;
-                f[u] = left ? __builtin_amdgcn_readlane(my_fill, at[u]) : 0u;
-                left &= left - 1;
+                const uint32_t i = base + u * 64 + lane;
+                e[u] = i < n ? ent[i] : 0ull;
             }
 #pragma unroll
-            for (uint32_t u = 0; u < U; ++u)
-                e[u] = lane < f[u] ? log[(region + g + at[u]) * kLogChunk + lane] : 0ull;
-#pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
-                if (lane >= f[u]) continue;
+                if (base + u * 64 + lane >= n) continue;
                 const uint32_t h = log_index((uint32_t)(e[u] >> 32), bits);
                 if ((h >> kLogHistBits) != part) continue;
                 const float wf = __uint_as_float((uint32_t)e[u]);
@@ -1092,17 +1076,18 @@ uint64_t workspace_words(const mc_detector_t &d, uint64_t n_inst = 1, uint64_t c
     return kWsScalarWords * n_inst + copies * n_pix * n_inst * ((d.flags & MC_SIGMA) ? 2 : 1);
 }
 
-// The exit log (MC_EXIT_LOG) follows the workspace words: the fill bytes of
-// kLogBuckets x waves x K chunks (padded to 8 bytes), then their entries,
-// with K the largest count the caller's workspace holds.
-constexpr uint64_t kLogBytesPerChunk = kLogChunk * 8 + 1;
-constexpr uint64_t kLogSizingWaves = 256 * 32;   // resident waves of a full MI355X launch
-uint32_t log_chunks_for(uint64_t extra_bytes, uint64_t waves)
+// The exit log (MC_EXIT_LOG) follows the workspace words: the counts of
+// kLogBuckets x blocks regions (uint32, padded to 8 bytes), then the regions
+// of cap entries each, with cap the largest the caller's workspace holds.
+constexpr uint64_t kLogSizingBlocks = 256 * 2;   // resident blocks of a full MI355X launch
+uint32_t log_cap_for(uint64_t extra_bytes, uint64_t blocks)
 {
-    if (extra_bytes < 8 || waves == 0) return 0;
-    const uint64_t k = (extra_bytes - 8) / (kLogBuckets * waves * kLogBytesPerChunk);
-    // Chunk indices are 32-bit in the kernel.
-    return (uint32_t)std::min<uint64_t>({k, (uint64_t)kLogMaxChunks, 0xFFFFFFFFull / (kLogBuckets * waves)});
+    const uint64_t regions = kLogBuckets * blocks;
+    const uint64_t count_bytes = (regions * 4 + 7) / 8 * 8;
+    if (blocks == 0 || extra_bytes < count_bytes) return 0;
+    const uint64_t cap = (extra_bytes - count_bytes) / (regions * 8);
+    // Region offsets are formed in 64 bits; entry positions are 32-bit.
+    return (uint32_t)std::min<uint64_t>(cap, 0x7FFFFFFFull);
 }
 
 uint64_t batch_workspace_words(const mc_detector_t &d, uint64_t n_items)
@@ -1159,13 +1144,12 @@ int check_setup(const char *fn, const mc_source_t &src, const mc_geometry_t &geo
         if (entry_dir(src, geo, i) == 0.f && (float)src.pos_mm[i] + (float)R >= (float)geo.size_mm[i])
             return fail(MC_EINVAL, "%s: the beam must not run along the face %s = %g", fn, i ? "y" : "x",
                         geo.size_mm[i]);
-    if (R > 0.0 && rn.max_steps == 0xFFFFFFFFu)
-        return fail(MC_EINVAL, "%s: a finite beam reserves step counter 2^32 - 1 (max_steps must be lower)", fn);
     if (!dims_ok(det)) return fail(MC_EINVAL, "%s: image dimensions must be >= 1", fn);
     if (!t.side || !t.trans || !t.scalars) return fail(MC_EINVAL, "%s: side, trans and scalars are required", fn);
     if ((det.flags & MC_SIGMA) && (!t.side_w2 || !t.trans_w2))
         return fail(MC_EINVAL, "%s: MC_SIGMA needs side_w2 and trans_w2", fn);
-    if (rn.max_steps < 1) return fail(MC_EINVAL, "%s: max_steps must be >= 1", fn);
+    if (rn.max_steps < 1 || rn.max_steps > (1u << 24))
+        return fail(MC_EINVAL, "%s: max_steps must be in 1..2^24", fn);
     if (!(rn.roulette_w >= 0.0) || !(rn.roulette_p > 0.0 && rn.roulette_p <= 1.0))
         return fail(MC_EINVAL, "%s: roulette_w >= 0 and roulette_p in (0, 1] required", fn);
     if (rn.block_size != 0 && (rn.block_size < 64 || rn.block_size > 1024 || rn.block_size % 64))
@@ -1345,7 +1329,7 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     const size_t scal_bytes = (batch ? (size_t)n_inst * kBatchScal : MC_N_SCALARS) * sizeof(double);
     const size_t queue_arrays = batch ? 4 : 3;
     const size_t lds_fixed = table_bytes + scal_bytes + (size_t)(block / 64) * queue_arrays * kQueue * sizeof(float) +
-                             (use_log ? (size_t)(block / 64) * (kLogBuckets / 2) * sizeof(uint32_t) : 0);
+                             (use_log ? (size_t)kLogBuckets * sizeof(uint32_t) : 0);
     const size_t slot_bytes = sizeof(uint32_t) + sizeof(double) * ((det.flags & MC_SIGMA) ? 2 : 1);
     const size_t lds_half_cu = 80 * 1024;
     a.cache_bits = 0;
@@ -1364,16 +1348,15 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     a.chunk = (uint32_t)chunk;
     a.refill_min = kRefillMin;
 
-    // ---- exit log: K chunks per wave and range in what the caller gave
-    // beyond the workspace words; the fill bytes are cleared with the words ----
+    // ---- exit log: a region of log_cap entries per block and key range in
+    // what the caller gave beyond the workspace words (the walk writes every
+    // count, so nothing needs clearing) ----
     uint64_t clear_words = ws_words;
     if (use_log) {
-        a.log_waves = (uint32_t)waves_total;
-        a.log_chunks = log_chunks_for(t.workspace_bytes - ws_words * 8, waves_total);
-        const uint64_t n_chunks = (uint64_t)kLogBuckets * waves_total * a.log_chunks;
-        a.log_fill = (uint8_t *)(ws + ws_words);
-        a.log = ws + ws_words + (n_chunks + 7) / 8;
-        clear_words += (n_chunks + 7) / 8;
+        const uint64_t regions = (uint64_t)kLogBuckets * grid;
+        a.log_cap = log_cap_for(t.workspace_bytes - ws_words * 8, grid);
+        a.log_count = (uint32_t *)(ws + ws_words);
+        a.log = ws + ws_words + (regions * 4 + 7) / 8;
         const uint64_t groups = (n_total + 7) / 8;
         a.log_bits = 6;
         while ((1ull << a.log_bits) < groups) ++a.log_bits;
@@ -1438,11 +1421,13 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
         }
         units = total_photons;
     }
+    if (rn.walk_events[0]) MC_HIP_CHECK(hipEventRecord((hipEvent_t)rn.walk_events[0], st));
     if (units > 0) {
         MC_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, a);
         MC_HIP_CHECK(hipGetLastError());
     }
+    if (rn.walk_events[1]) MC_HIP_CHECK(hipEventRecord((hipEvent_t)rn.walk_events[1], st));
     if (use_log && units > 0) {
         // Keys of a range have indices below 2^(bits - 3); one part per
         // 2^kLogHistBits of them.
@@ -1454,8 +1439,8 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
         auto bin = sig ? log_bin<true> : log_bin<false>;
         MC_HIP_CHECK(hipFuncSetAttribute((const void *)bin, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hist));
         hipLaunchKernelGGL(bin, dim3(kLogBuckets * parts * kCopies), dim3(1024), hist, st,
-                           (const unsigned long long *)a.log, (const uint8_t *)a.log_fill,
-                           (uint64_t)waves_total * a.log_chunks, a.ws_img, a.ws_img2, n_total, parts, a.log_bits, inv);
+                           (const unsigned long long *)a.log, (const uint32_t *)a.log_count, a.log_cap,
+                           (uint32_t)grid, a.ws_img, a.ws_img2, n_total, parts, a.log_bits, inv);
         MC_HIP_CHECK(hipGetLastError());
     }
     // ---- finalize: per-XCD copies to the caller's images, scalars to doubles ----
@@ -1716,13 +1701,12 @@ extern "C" uint64_t mc_workspace_bytes_log(const mc_detector_t *detector, uint64
     if (!detector || !mcmie::dims_ok(*detector) || !(detector->flags & MC_EXIT_LOG)) return 0;
     using namespace mcmie;
     // Each photon leaves through an image at most once.  Spread evenly over
-    // the ranges and the waves of a full launch, a wave adds about
-    // n / (64 x waves) entries to a range; it gets half as many chunks again
-    // as those fill (for uneven spread and unequal shares of photons), plus
-    // one for its partly filled last chunk.
-    const uint64_t per = kLogBuckets * kLogSizingWaves * kLogChunk;
-    const uint64_t k = std::min<uint64_t>((n_photons + n_photons / 2 + per - 1) / per + 1, kLogMaxChunks);
-    return workspace_words(*detector) * 8 + 8 + kLogBuckets * kLogSizingWaves * k * kLogBytesPerChunk;
+    // the ranges and the blocks of a full launch, a block adds about
+    // n / (64 x blocks) entries to a range; its region holds half as many
+    // again (for uneven spread and unequal shares of photons) plus 256.
+    const uint64_t regions = kLogBuckets * kLogSizingBlocks;
+    const uint64_t cap = std::min<uint64_t>((n_photons + n_photons / 2 + regions - 1) / regions + 256, 0x7FFFFFFFull);
+    return workspace_words(*detector) * 8 + (regions * 4 + 7) / 8 * 8 + regions * cap * 8;
 }
 
 extern "C" uint64_t mc_workspace_bytes_batch(const mc_detector_t *detector, uint32_t n_items)

@@ -123,11 +123,9 @@ def test_workspace_size_and_checks():
 
 def test_exit_log_sizes_and_checks():
     """MC_EXIT_LOG: the workspace words are unchanged and the log comes on
-    top, in whole sets of one chunk (64 entries and a fill byte) per range
-    and wave of a full launch (64 ranges, 8192 waves): 1.5 chunks per 64
-    photons of a wave's share, plus one.  The flag is refused with
-    records."""
-    import math
+    top: a 4-byte count per region (64 ranges x 512 blocks of a full
+    launch) and per region 1.5 times a block's share of photons in a range
+    plus 256 entries of 8 bytes.  The flag is refused with records."""
     import paper_2507_23189_amd as mc
     _lib_path()
     spec, med, src, geo, det, run = _valid_args()
@@ -135,10 +133,10 @@ def test_exit_log_sizes_and_checks():
     assert mc.mc_workspace_bytes_log(det, 10**6) == 0           # flag not set
     det.flags = mc.MC_EXIT_LOG
     assert mc.mc_workspace_bytes(det) == base
-    one_set = 64 * 8192 * (64 * 8 + 1)
+    regions = 64 * 512
     for n in (0, 1, 10**6, 10**8, 10**9):
-        k = math.ceil(1.5 * n / (64 * 8192 * 64)) + 1
-        assert mc.mc_workspace_bytes_log(det, n) == base + 8 + k * one_set, n
+        cap = -(-(n + n // 2) // regions) + 256
+        assert mc.mc_workspace_bytes_log(det, n) == base + regions * 4 + regions * cap * 8, n
     assert mc.mc_workspace_bytes_log(mc.Detector(0, 1, 1, 1, mc.MC_EXIT_LOG), 10) == 0
     det.flags = mc.MC_EXIT_LOG | mc.MC_RECORD
     tal = _tally_stub(det)
@@ -381,8 +379,9 @@ def test_finite_beam_validation():
         src.beam_radius_mm = radius
         assert call() == mc.MC_EINVAL
     src.beam_radius_mm = 1.25
-    run.max_steps = 0xFFFFFFFF                           # the reserved step counter
-    assert call() == mc.MC_EINVAL and b"reserves" in mc.lib().mc_last_error()
+    for steps in (0xFFFFFFFF, (1 << 24) + 1):           # the reserved step counter; past the cap
+        run.max_steps = steps
+        assert call() == mc.MC_EINVAL and b"max_steps" in mc.lib().mc_last_error()
 
 
 def test_beam_along_a_far_side_face_is_rejected():

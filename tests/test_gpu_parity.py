@@ -344,3 +344,26 @@ def test_medium_forms_give_the_same_walk(mc, cuda_device):
     for t in outs[1:]:
         assert torch.equal(t.side, outs[0].side) and torch.equal(t.trans, outs[0].trans)
         assert torch.equal(t.scalars, outs[0].scalars)
+
+
+def test_walk_kernel_timing_events(mc, cuda_device):
+    """Events passed in the run are recorded right around the walk kernel:
+    they time less than the whole mc_simulate and leave the results alone."""
+    torch = _torch()
+    w = W.TINY.replace(n_photons=200_000, tau=3.0)
+    spec, *_ = mc.args_from_workload(w)
+    table = mc.mie_table_build(spec, cuda_device)
+    _, med, src, geo, det, run = mc.args_from_workload(w, table, flags=mc.MC_FIX64)
+    a = mc.Tally.alloc(det, cuda_device, fix64=True)
+    mc.mc_simulate(med, src, geo, det, run, a)
+    walk = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    whole = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    run.time_walk(*walk)
+    b = mc.Tally.alloc(det, cuda_device, fix64=True)
+    whole[0].record()
+    mc.mc_simulate(med, src, geo, det, run, b)
+    whole[1].record()
+    torch.cuda.synchronize()
+    t_walk, t_whole = walk[0].elapsed_time(walk[1]), whole[0].elapsed_time(whole[1])
+    assert 0.0 < t_walk <= t_whole
+    assert torch.equal(a.side, b.side) and torch.equal(a.scalars, b.scalars)
