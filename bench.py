@@ -126,8 +126,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # WRITE_SIZE x 1.0); valid only for the tally path and kernel code it was
 # measured on (profiles/walk_tau4_counters.md): the digest covers the walk
 # sources without comments and whitespace, so a comment edit keeps it.
-TRAFFIC = {"tally": "log", "sources_sha256": "1bd222ac92adf83877fca51ca05569852e0c9e28722ef522ea358f8633ba19cb",
-           "fetch_kib": 377.3, "write_kib": 1798653.0, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"tally": "log", "sources_sha256": "d61780306fcb26fcdf6296ff663d4d2921db0edda2249ca8aa702e31e7c4c733",
+           "fetch_kib": 380.1, "write_kib": 540579.8, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 
@@ -447,9 +447,9 @@ def batch_timing(mc, W, dev, args):
     import torch
     ws = W.batch_workloads(256)
     tables = [mc.mie_table_build(mc.args_from_workload(w)[0], dev) for w in ws]
-    _, _, src, geo, det, run = mc.args_from_workload(ws[0])
+    _, _, src, geo, det, run = mc.args_from_workload(ws[0], flags=tally_flags(mc, args))
     items = [mc.batch_item(w, t) for w, t in zip(ws, tables)]
-    tal = mc.Tally.alloc_batch(det, len(ws), dev)
+    tal = mc.Tally.alloc_batch(det, len(ws), dev, log_photons=sum(w.n_photons for w in ws))
     t0 = time.perf_counter()
     blk, chk, best, table = mc.mc_autotune_batch(items, ws[0].n_cdf, src, geo, det, run, tal, 1.0 / 16)
     tune_s = time.perf_counter() - t0
@@ -466,11 +466,12 @@ def batch_timing(mc, W, dev, args):
     scal = tal.scalars.cpu().numpy()
     events = float(scal[:, 9].sum())
     batch_ms = sorted(ms)[len(ms) // 2]
-    # Every medium alone (default launch shape), timed the same way.
+    # Every medium alone (default launch shape, the same tally path), timed
+    # the same way.
     single = []
     for w, t in zip(ws, tables):
-        _, med, s1, g1, d1, r1 = mc.args_from_workload(w, t)
-        one = mc.Tally.alloc(d1, dev)
+        _, med, s1, g1, d1, r1 = mc.args_from_workload(w, t, flags=tally_flags(mc, args))
+        one = mc.Tally.alloc(d1, dev, log_photons=w.n_photons)
         mc.mc_simulate(med, s1, g1, d1, r1, one)
         ev[0].record()
         mc.mc_simulate(med, s1, g1, d1, r1, one)
@@ -480,6 +481,7 @@ def batch_timing(mc, W, dev, args):
         single.append((float(one.scalars[9]) / (t_ms * 1e-3), t_ms))
     best_single = max(r for r, _ in single)
     return {"media": len(ws), "photons": int(sum(w.n_photons for w in ws)), "events": events,
+            "tally": "atomic" if args.atomic_tally else "exit log",
             "batch_ms": batch_ms, "events_per_s": events / (batch_ms * 1e-3),
             "best_single_events_per_s": best_single,
             "ratio_to_best_single": events / (batch_ms * 1e-3) / best_single,
@@ -655,6 +657,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log("bench: timed steps done")
+    sweep = None if args.no_sweep else sweep_timing(mc, W, dev, args)
+    log("bench: optical-depth sweep done")
     adjoint = adjoint_timing(mc, w, dev, args)
     log("bench: adjoint timing done")
     batch = None if args.no_batch else batch_timing(mc, W, dev, args)
@@ -663,8 +667,6 @@ def main():
     log("bench: heavy timing done")
     analysis = None if args.no_analysis else analysis_timing(mc, W, dev, args)
     log("bench: analysis done")
-    sweep = None if args.no_sweep else sweep_timing(mc, W, dev, args)
-    log("bench: optical-depth sweep done")
 
     scal = [t.scalars.cpu().numpy() for t in tallies[args.warmup:]]
     events = float(sum(s[9] for s in scal))
@@ -715,6 +717,8 @@ def main():
         "analysis": analysis,
         "sweep": sweep,
     }
+    if batch is not None:
+        batch["ratio_to_headline"] = batch["events_per_s"] / out["value"]
     if not args.no_cpu_baseline:
         base, err = oracle_leg(mc, W, w, dev, args, out["value"])
         out["cpu_baseline"] = base

@@ -65,7 +65,8 @@ extern "C" {
                                  workspace beyond mc_workspace_bytes (size it with
                                  mc_workspace_bytes_log); exits that find their part of it full
                                  are added directly, so any size is correct.  Not with
-                                 MC_RECORD, nor in batched launches. */
+                                 MC_RECORD; batched launches size it with
+                                 mc_workspace_bytes_batch_log. */
 
 /* Scalar tallies: mc_tally_t.scalars holds MC_N_SCALARS doubles. */
 #define MC_S_FACE 0           /* 0..5: weight leaving faces -x, +x, -y, +y, -z, +z */
@@ -383,8 +384,8 @@ int mc_simulate_noalloc(const mc_medium_t *medium, const mc_source_t *source, co
  * Outputs are item-major: side is n_items x side_ny x side_nx, trans and the
  * MC_SIGMA images likewise, scalars n_items x MC_N_SCALARS.  run->n_photons,
  * photon_offset, instance and record_stride are ignored.  Supported flags:
- * MC_ACCUMULATE, MC_SIGMA, MC_FIX64 (MC_RECORD and MC_MOMENTS give
- * MC_EUNSUPPORTED).  n_items is 1..MC_MAX_BATCH.  Asynchronous.
+ * MC_ACCUMULATE, MC_SIGMA, MC_FIX64, MC_EXIT_LOG (MC_RECORD and MC_MOMENTS
+ * give MC_EUNSUPPORTED).  n_items is 1..MC_MAX_BATCH.  Asynchronous.
  */
 #define MC_MAX_BATCH 512
 typedef struct {
@@ -402,6 +403,12 @@ int mc_simulate_batch(const mc_batch_item_t *items, uint32_t n_items, int32_t n_
 
 /* Workspace bytes mc_simulate_batch needs for n_items media (0 if invalid). */
 uint64_t mc_workspace_bytes_batch(const mc_detector_t *detector, uint32_t n_items);
+
+/* The same with MC_EXIT_LOG in detector->flags: mc_workspace_bytes_batch plus
+ * an exit log sized for total_photons photons over all items, in regions of
+ * key ranges fine enough that each range holds at most 8192 of the batch's
+ * keys (0 if invalid or without MC_EXIT_LOG). */
+uint64_t mc_workspace_bytes_batch_log(const mc_detector_t *detector, uint32_t n_items, uint64_t total_photons);
 
 /*
  * Launch-shape autotuner for mc_simulate_batch.  Runs the batch with every

@@ -14,7 +14,7 @@ from ._capi import (MC_ACCUMULATE, MC_EDEVICE, MC_EINVAL, MC_ENOMEM, MC_EUNSUPPO
                     mc_grad, mc_philox_blocks, mc_simulate, mc_version, mc_workspace_bytes, mie_table_build,
                     mc_workspace_bytes_log,
                     BatchItem, MC_MAX_BATCH, AUTOTUNE_BLOCKS, AUTOTUNE_CHUNKS, mc_simulate_batch,
-                    mc_autotune_batch, mc_workspace_bytes_batch, MiePoly, MC_MAX_BINS, mie_table_build_poly,
+                    mc_autotune_batch, mc_workspace_bytes_batch, mc_workspace_bytes_batch_log, MiePoly, MC_MAX_BINS, mie_table_build_poly,
                     mc_lognormal_bins, Radial, MC_METRICS_N, MC_MAX_ANNULI, image_metrics,
                     mie_table_enqueue, MC_MEDIUM_TAU, MC_MEDIUM_MU, MC_MEDIUM_CONCENTRATION,
                     mc_medium_coefficients, mc_simulate_noalloc, MC_NOALLOC_SCRATCH_BYTES)

@@ -156,6 +156,8 @@ def lib():
         L.mc_workspace_bytes.restype = C.c_uint64
         L.mc_workspace_bytes_batch.argtypes = [C.POINTER(Detector), C.c_uint32]
         L.mc_workspace_bytes_batch.restype = C.c_uint64
+        L.mc_workspace_bytes_batch_log.argtypes = [C.POINTER(Detector), C.c_uint32, C.c_uint64]
+        L.mc_workspace_bytes_batch_log.restype = C.c_uint64
         L.mc_workspace_bytes_log.argtypes = [C.POINTER(Detector), C.c_uint64]
         L.mc_workspace_bytes_log.restype = C.c_uint64
         _batch_args = [C.POINTER(BatchItem), C.c_uint32, C.c_int32, C.POINTER(Source), C.POINTER(Geometry),
@@ -338,6 +340,10 @@ def mc_workspace_bytes_batch(det: Detector, n_items: int) -> int:
     return int(lib().mc_workspace_bytes_batch(C.byref(det), int(n_items)))
 
 
+def mc_workspace_bytes_batch_log(det: Detector, n_items: int, total_photons: int) -> int:
+    return int(lib().mc_workspace_bytes_batch_log(C.byref(det), int(n_items), int(total_photons)))
+
+
 @dataclass
 class Tally:
     """Caller-owned device outputs and workspace of mc_simulate.  Images are
@@ -392,14 +398,20 @@ class Tally:
         return t
 
     @staticmethod
-    def alloc_batch(det: Detector, n_items: int, device="cuda", *, sigma=False, fix64=False) -> "Tally":
-        """Item-major outputs of mc_simulate_batch for n_items media."""
+    def alloc_batch(det: Detector, n_items: int, device="cuda", *, sigma=False, fix64=False,
+                    log_photons=None) -> "Tally":
+        """Item-major outputs of mc_simulate_batch for n_items media; with
+        det.flags & MC_EXIT_LOG the workspace also holds an exit log sized for
+        log_photons photons over all items."""
         import torch
         dev = torch.device(device)
         img = dict(dtype=torch.int64 if fix64 else torch.float64, device=dev)
         probe = Detector(det.side_nx, det.side_ny, det.trans_nx, det.trans_ny,
                          det.flags | (MC_SIGMA if sigma else 0))
-        ws_bytes = mc_workspace_bytes_batch(probe, n_items)
+        if det.flags & MC_EXIT_LOG:
+            ws_bytes = mc_workspace_bytes_batch_log(probe, n_items, int(log_photons or 0))
+        else:
+            ws_bytes = mc_workspace_bytes_batch(probe, n_items)
         if ws_bytes == 0:
             raise ValueError(f"invalid detector or n_items {n_items} (1..{MC_MAX_BATCH})")
         t = Tally(torch.empty((n_items, det.side_ny, det.side_nx), **img),

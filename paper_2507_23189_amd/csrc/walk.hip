@@ -119,7 +119,8 @@ struct WalkArgs {
     // is log_count[r * gridDim.x + b], written when the block ends.
     unsigned long long *log;
     uint32_t *log_count;
-    uint32_t log_cap, log_bits;      // log_bits: scrambled group index width, >= 6
+    uint32_t log_cap, log_bits;      // log_bits: scrambled group index width, >= log_rbits
+    uint32_t log_rbits;              // key ranges: 2^log_rbits
     // Batched launch: media in schedule order, work units over all of them.
     const BatchInst *insts;
     uint32_t n_inst;          // media (slots) in the launch
@@ -215,26 +216,31 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;   // free tally-cache slot
 
 constexpr int kOptSigma = 1, kOptRecord = 2, kOptMoments = 4, kOptBatch = 8, kOptLog = 16;
 // Exit log: image exits appended as (key << 32 | weight bits).  Keys fall
-// into kLogBuckets ranges; every block of the launch owns a region of log_cap
+// into 2^rbits ranges; every block of the launch owns a region of log_cap
 // entries in each range's part of the log and appends to it at the position a
 // counter in its LDS hands out (no global atomic).  The waves of a block thus
 // fill the same few lines of each range together, which stay in the L2 until
 // they are whole.  Keys go to ranges by groups of eight (one 64-byte line of a
 // tally copy): the group g is scrambled by p = g * kLogHashMul mod 2^bits (an
-// odd multiplier, so a bijection), its top six bits pick the range and the
+// odd multiplier, so a bijection), its top rbits bits pick the range and the
 // rest, with the key's place in its group, index the key within the range.
-// Bright spots of an image thus spread evenly over the ranges.
-constexpr uint32_t kLogBuckets = 64;
+// Bright spots of an image thus spread evenly over the ranges.  rbits grows
+// with the images so that a range holds at most 2^kLogHistBits keys where the
+// LDS allows (one binning block per range and copy).
+constexpr uint32_t kLogMinRangeBits = 6;
 constexpr uint32_t kLogHistBits = 13;      // keys per binning block: 2^13 (64 KB of int64 sums)
 constexpr uint32_t kLogHashMul = 0x9E3779B1u;
 __device__ __forceinline__ uint32_t log_scramble(uint32_t key, uint32_t bits)
 {
     return ((key >> 3) * kLogHashMul) & ((1u << bits) - 1u);
 }
-__device__ __forceinline__ uint32_t log_bucket(uint32_t key, uint32_t bits) { return log_scramble(key, bits) >> (bits - 6); }
-__device__ __forceinline__ uint32_t log_index(uint32_t key, uint32_t bits)
+__device__ __forceinline__ uint32_t log_bucket(uint32_t key, uint32_t bits, uint32_t rbits)
 {
-    return ((log_scramble(key, bits) & ((1u << (bits - 6)) - 1u)) << 3) | (key & 7u);
+    return log_scramble(key, bits) >> (bits - rbits);
+}
+__device__ __forceinline__ uint32_t log_index(uint32_t key, uint32_t bits, uint32_t rbits)
+{
+    return ((log_scramble(key, bits) & ((1u << (bits - rbits)) - 1u)) << 3) | (key & 7u);
 }
 constexpr int kBatchScal = 16;             // LDS scalar words per medium in a batched launch
 constexpr uint64_t kWsScalarWords = 32;    // workspace scalar words per medium
@@ -264,7 +270,7 @@ void walk_kernel(WalkArgs a)
     // (MC_N_SCALARS, or kBatchScal per medium), tally cache (slots words of
     // weight, [SIGMA] slots words of squared weight, slots uint32 keys),
     // per-wave exit queues (3 x kQueue floats, a fourth for the medium's slot),
-    // with the exit log then the block's kLogBuckets append counters.
+    // with the exit log then the block's 2^log_rbits append counters.
     // (The kernel declares no static LDS: the dynamic array starts at offset 0,
     // and its 16-byte alignment keeps the 64-bit words below aligned.)
     extern __shared__ __attribute__((aligned(16))) float s_table[];
@@ -279,7 +285,7 @@ void walk_kernel(WalkArgs a)
     // Exit log: entries the block has appended to each key range.
     uint32_t *s_lcnt = (uint32_t *)(s_queue + (blockDim.x >> 6) * (kQueueArrays * kQueue));
     if (LOG)
-        for (int i = threadIdx.x; i < (int)kLogBuckets; i += blockDim.x) s_lcnt[i] = 0u;
+        for (int i = threadIdx.x; i < (1 << a.log_rbits); i += blockDim.x) s_lcnt[i] = 0u;
 
     if (PHASE == MC_PHASE_MIE && !GLOBAL_TABLE)
         for (int i = threadIdx.x; i < a.n_cdf; i += blockDim.x) s_table[i] = a.inv_cdf[i];
@@ -360,7 +366,7 @@ void walk_kernel(WalkArgs a)
             // Append to the block's region of the key's range at the position
             // the block's LDS counter hands out; past the region's end, the
             // exit is added directly.
-            const uint32_t bucket = log_bucket(key, a.log_bits);
+            const uint32_t bucket = log_bucket(key, a.log_bits, a.log_rbits);
             bool direct = false;
             if (act) {
                 const uint32_t e = atomicAdd(&s_lcnt[bucket], 1u);
@@ -815,8 +821,9 @@ void walk_kernel(WalkArgs a)
     }
     // The block's entries in each range of the exit log (all its waves have
     // appended: the barrier above).
-    if (LOG && threadIdx.x < kLogBuckets)
-        a.log_count[threadIdx.x * gridDim.x + blockIdx.x] = min(s_lcnt[threadIdx.x], a.log_cap);
+    if (LOG)
+        for (int i = threadIdx.x; i < (1 << a.log_rbits); i += blockDim.x)
+            a.log_count[i * gridDim.x + blockIdx.x] = min(s_lcnt[i], a.log_cap);
 }
 
 // Zero the workspace, and the outputs unless accumulating.  (Fill kernels,
@@ -865,7 +872,7 @@ template <bool SIGMA>
 __global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, const uint32_t *count, uint32_t cap,
                                                 uint32_t walk_blocks, unsigned long long *copies,
                                                 unsigned long long *copies2, uint64_t n_total, uint32_t parts,
-                                                uint32_t bits, uint32_t inv_mul)
+                                                uint32_t bits, uint32_t rbits, uint32_t inv_mul)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned long long s_hist[];
     constexpr uint32_t H = 1u << kLogHistBits;
@@ -896,7 +903,7 @@ __global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, c
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 if (base + u * 64 + lane >= n) continue;
-                const uint32_t h = log_index((uint32_t)(e[u] >> 32), bits);
+                const uint32_t h = log_index((uint32_t)(e[u] >> 32), bits, rbits);
                 if ((h >> kLogHistBits) != part) continue;
                 const float wf = __uint_as_float((uint32_t)e[u]);
                 atomicAdd(&s_hist[h & (H - 1)], fix(wf));
@@ -907,12 +914,12 @@ __global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, c
     __syncthreads();
     unsigned long long *dst = copies + (uint64_t)s * n_total;
     unsigned long long *dst2 = SIGMA ? copies2 + (uint64_t)s * n_total : nullptr;
-    const uint32_t per_range = 1u << (bits - 3);
+    const uint32_t per_range = 1u << (bits - rbits + 3);
     for (uint32_t i = threadIdx.x; i < H; i += blockDim.x) {
         const uint32_t h = part * H + i;
         if (h >= per_range) break;
         // Undo the scramble: p = range bits | group bits, g = p / kLogHashMul mod 2^bits.
-        const uint32_t p = (b << (bits - 6)) | (h >> 3);
+        const uint32_t p = (b << (bits - rbits)) | (h >> 3);
         const uint64_t key = ((uint64_t)((p * inv_mul) & ((1u << bits) - 1u)) << 3) | (h & 7u);
         if (key >= n_total) continue;
         const unsigned long long v = s_hist[i];
@@ -1076,18 +1083,42 @@ uint64_t workspace_words(const mc_detector_t &d, uint64_t n_inst = 1, uint64_t c
     return kWsScalarWords * n_inst + copies * n_pix * n_inst * ((d.flags & MC_SIGMA) ? 2 : 1);
 }
 
-// The exit log (MC_EXIT_LOG) follows the workspace words: the counts of
-// kLogBuckets x blocks regions (uint32, padded to 8 bytes), then the regions
-// of cap entries each, with cap the largest the caller's workspace holds.
+// The exit log (MC_EXIT_LOG) follows the workspace words (and a batched
+// launch's schedule): the counts of 2^rbits x blocks regions (uint32, padded
+// to 8 bytes), then the regions of cap entries each, with cap the largest
+// the caller's workspace holds.  The key width and range bits follow from
+// the number of keys: a range of at most 2^kLogHistBits keys where the LDS
+// takes 2^rbits counters (up to 2^8 beside a Mie table, 2^12 otherwise).
 constexpr uint64_t kLogSizingBlocks = 256 * 2;   // resident blocks of a full MI355X launch
-uint32_t log_cap_for(uint64_t extra_bytes, uint64_t blocks)
+struct LogShape {
+    uint32_t bits, rbits;
+};
+LogShape log_shape(uint64_t n_keys, bool table_in_lds)
 {
-    const uint64_t regions = kLogBuckets * blocks;
+    const uint64_t groups = (n_keys + 7) / 8;
+    uint32_t bits = 1;
+    while ((1ull << bits) < groups) ++bits;
+    const uint32_t max_r = table_in_lds ? 8u : 12u;
+    const uint32_t want = bits > kLogHistBits - 3 ? bits - (kLogHistBits - 3) : 0u;
+    const uint32_t rbits = std::min(max_r, std::max(kLogMinRangeBits, want));
+    return {std::max(bits, rbits), rbits};
+}
+uint32_t log_cap_for(uint64_t extra_bytes, uint64_t regions)
+{
     const uint64_t count_bytes = (regions * 4 + 7) / 8 * 8;
-    if (blocks == 0 || extra_bytes < count_bytes) return 0;
+    if (regions == 0 || extra_bytes < count_bytes) return 0;
     const uint64_t cap = (extra_bytes - count_bytes) / (regions * 8);
-    // Region offsets are formed in 64 bits; entry positions are 32-bit.
+    // Entry positions are 32-bit.
     return (uint32_t)std::min<uint64_t>(cap, 0x7FFFFFFFull);
+}
+// Log bytes for n_photons over `regions` regions: each photon leaves through an
+// image at most once; spread evenly over the ranges and the blocks of a full
+// launch, a region gets about n / regions entries, and holds half as many again
+// (for uneven spread and unequal shares of photons) plus 64.
+uint64_t log_bytes_for(uint64_t n_photons, uint64_t regions)
+{
+    const uint64_t cap = std::min<uint64_t>((n_photons + n_photons / 2 + regions - 1) / regions + 64, 0x7FFFFFFFull);
+    return (regions * 4 + 7) / 8 * 8 + regions * cap * 8;
 }
 
 uint64_t batch_workspace_words(const mc_detector_t &d, uint64_t n_items)
@@ -1315,30 +1346,44 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     a.n_pix = n_total;
     a.n_inst = n_inst;
 
-    const bool use_log = (det.flags & MC_EXIT_LOG) != 0;
     const uint64_t ws_words = workspace_words(det, n_inst, copies);
+    // A batched launch keeps its schedule after the workspace words; the exit
+    // log follows: its counts, then the regions.  A workspace without room for
+    // the counts takes the atomic path (the same sums).
+    const uint64_t sched_words = batch ? (n_inst * sizeof(BatchInst) + 7) / 8 : 0;
+    const LogShape shape = log_shape(n_total, !batch && phase == MC_PHASE_MIE);
 
     // ---- launch shape: 1024-lane blocks (768 with path moments), two per CU, each with
     // the table (single medium), the scalar words, the per-wave exit queues and
     // as large a tally cache as fits in half the CU's 160 KB LDS (with the exit
-    // log: the log cursors and no cache) ----
+    // log: the block's append counters and no cache) ----
     // Path-moment kernels are built for six waves per SIMD: 768-lane blocks,
     // two per CU.
     const int block = rn.block_size ? rn.block_size : ((det.flags & MC_MOMENTS) ? 768 : 1024);
     const size_t table_bytes = batch ? 0 : (size_t)((a.n_cdf + 3) & ~3) * sizeof(float);
     const size_t scal_bytes = (batch ? (size_t)n_inst * kBatchScal : MC_N_SCALARS) * sizeof(double);
     const size_t queue_arrays = batch ? 4 : 3;
-    const size_t lds_fixed = table_bytes + scal_bytes + (size_t)(block / 64) * queue_arrays * kQueue * sizeof(float) +
-                             (use_log ? (size_t)kLogBuckets * sizeof(uint32_t) : 0);
     const size_t slot_bytes = sizeof(uint32_t) + sizeof(double) * ((det.flags & MC_SIGMA) ? 2 : 1);
     const size_t lds_half_cu = 80 * 1024;
-    a.cache_bits = 0;
-    for (int b = 10; b >= 4 && !use_log; --b)
-        if (lds_fixed + (slot_bytes << b) <= lds_half_cu) { a.cache_bits = b; break; }
-    const size_t lds = lds_fixed + (a.cache_bits ? (slot_bytes << a.cache_bits) : 0);
+    size_t lds = 0;
+    int grid = 0;
+    auto launch_shape = [&](bool log) {
+        const size_t lds_fixed = table_bytes + scal_bytes + (size_t)(block / 64) * queue_arrays * kQueue * sizeof(float) +
+                                 (log ? ((size_t)4 << shape.rbits) : 0);
+        a.cache_bits = 0;
+        for (int b = 10; b >= 4 && !log; --b)
+            if (lds_fixed + (slot_bytes << b) <= lds_half_cu) { a.cache_bits = b; break; }
+        lds = lds_fixed + (a.cache_bits ? (slot_bytes << a.cache_bits) : 0);
+        const int blocks_per_cu = std::max(1, std::min((int)(160 * 1024 / lds), 32 / (block / 64)));
+        grid = rn.grid_blocks > 0 ? rn.grid_blocks : cus * blocks_per_cu;
+    };
+    bool use_log = (det.flags & MC_EXIT_LOG) != 0;
+    launch_shape(use_log);
+    if (use_log && t.workspace_bytes / 8 < ws_words + sched_words + (((uint64_t)grid << shape.rbits) * 4 + 7) / 8) {
+        use_log = false;
+        launch_shape(false);
+    }
     if (lds > 160 * 1024) return fail(MC_EINVAL, "mc_simulate: %zu bytes of LDS per block do not fit a CU", lds);
-    const int blocks_per_cu = std::max(1, std::min((int)(160 * 1024 / lds), 32 / (block / 64)));
-    const int grid = rn.grid_blocks > 0 ? rn.grid_blocks : cus * blocks_per_cu;
     const uint64_t waves_total = (uint64_t)grid * (block / 64);
     uint64_t chunk = rn.chunk;
     if (chunk == 0) {
@@ -1353,13 +1398,13 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     // count, so nothing needs clearing) ----
     uint64_t clear_words = ws_words;
     if (use_log) {
-        const uint64_t regions = (uint64_t)kLogBuckets * grid;
-        a.log_cap = log_cap_for(t.workspace_bytes - ws_words * 8, grid);
-        a.log_count = (uint32_t *)(ws + ws_words);
-        a.log = ws + ws_words + (regions * 4 + 7) / 8;
-        const uint64_t groups = (n_total + 7) / 8;
-        a.log_bits = 6;
-        while ((1ull << a.log_bits) < groups) ++a.log_bits;
+        const uint64_t regions = ((uint64_t)1 << shape.rbits) * grid;
+        const uint64_t log_at = ws_words + sched_words;
+        a.log_cap = t.workspace_bytes > log_at * 8 ? log_cap_for(t.workspace_bytes - log_at * 8, regions) : 0;
+        a.log_count = (uint32_t *)(ws + log_at);
+        a.log = ws + log_at + (regions * 4 + 7) / 8;
+        a.log_bits = shape.bits;
+        a.log_rbits = shape.rbits;
     }
 
     const int zero_all = (det.flags & MC_ACCUMULATE) ? 0 : 1;
@@ -1394,7 +1439,10 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
         MC_HIP_CHECK(hipGetLastError());
         a.insts = dst;
         a.n_units = units;
-        kern = sig ? walk_kernel<MC_PHASE_MIE, kOptBatch | kOptSigma> : walk_kernel<MC_PHASE_MIE, kOptBatch>;
+        static const Kern batch_kernels[4] = {
+            walk_kernel<MC_PHASE_MIE, kOptBatch>, walk_kernel<MC_PHASE_MIE, kOptBatch | kOptSigma>,
+            walk_kernel<MC_PHASE_MIE, kOptBatch | kOptLog>, walk_kernel<MC_PHASE_MIE, kOptBatch | kOptLog | kOptSigma>};
+        kern = batch_kernels[(sig ? 1 : 0) + (use_log ? 2 : 0)];
     } else {
         const int opt = (sig ? kOptSigma : 0) | (rec ? kOptRecord : 0) | ((det.flags & MC_MOMENTS) ? kOptMoments : 0);
         static const Kern mie_kernels[8] = {walk_kernel<MC_PHASE_MIE, 0>, walk_kernel<MC_PHASE_MIE, 1>,
@@ -1429,18 +1477,18 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     }
     if (rn.walk_events[1]) MC_HIP_CHECK(hipEventRecord((hipEvent_t)rn.walk_events[1], st));
     if (use_log && units > 0) {
-        // Keys of a range have indices below 2^(bits - 3); one part per
-        // 2^kLogHistBits of them.
-        const uint64_t per_range = 1ull << (a.log_bits - 3);
+        // Keys of a range have indices below 2^(bits - rbits + 3); one part
+        // per 2^kLogHistBits of them.
+        const uint64_t per_range = 1ull << (a.log_bits - a.log_rbits + 3);
         const uint32_t parts = (uint32_t)((per_range + (1u << kLogHistBits) - 1) >> kLogHistBits);
         uint32_t inv = kLogHashMul;   // inverse of the odd multiplier mod 2^32 (Newton: x <- x (2 - m x))
         for (int i = 0; i < 5; ++i) inv *= 2u - kLogHashMul * inv;
         const size_t hist = ((size_t)8 << kLogHistBits) * (sig ? 2 : 1);
         auto bin = sig ? log_bin<true> : log_bin<false>;
         MC_HIP_CHECK(hipFuncSetAttribute((const void *)bin, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hist));
-        hipLaunchKernelGGL(bin, dim3(kLogBuckets * parts * kCopies), dim3(1024), hist, st,
+        hipLaunchKernelGGL(bin, dim3((1u << a.log_rbits) * parts * kCopies), dim3(1024), hist, st,
                            (const unsigned long long *)a.log, (const uint32_t *)a.log_count, a.log_cap,
-                           (uint32_t)grid, a.ws_img, a.ws_img2, n_total, parts, a.log_bits, inv);
+                           (uint32_t)grid, a.ws_img, a.ws_img2, n_total, parts, a.log_bits, a.log_rbits, inv);
         MC_HIP_CHECK(hipGetLastError());
     }
     // ---- finalize: per-XCD copies to the caller's images, scalars to doubles ----
@@ -1480,10 +1528,9 @@ int prepare_batch(const char *fn, const mc_batch_item_t *items, uint32_t n_items
     const mc_tally_t &t = *tally;
     if (int rc = check_geometry(fn, geo)) return rc;
     if (int rc = check_setup(fn, *source, geo, det, rn, t)) return rc;
-    if (det.flags & (MC_RECORD | MC_MOMENTS | MC_MOMENTS_PIXEL2 | MC_EXIT_LOG))
-        return fail(MC_EUNSUPPORTED, "%s: MC_RECORD, MC_MOMENTS and MC_EXIT_LOG are not available for batched "
-                                     "launches", fn);
-    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_FIX64))
+    if (det.flags & (MC_RECORD | MC_MOMENTS | MC_MOMENTS_PIXEL2))
+        return fail(MC_EUNSUPPORTED, "%s: MC_RECORD and MC_MOMENTS are not available for batched launches", fn);
+    if (det.flags & ~(MC_ACCUMULATE | MC_SIGMA | MC_FIX64 | MC_EXIT_LOG))
         return fail(MC_EINVAL, "%s: unknown detector flags 0x%x", fn, det.flags);
     const uint64_t n_pix = (uint64_t)det.side_nx * det.side_ny + (uint64_t)det.trans_nx * det.trans_ny;
     if (n_pix * n_items >= 0xFFFFFFFFull)
@@ -1700,19 +1747,30 @@ extern "C" uint64_t mc_workspace_bytes_log(const mc_detector_t *detector, uint64
 {
     if (!detector || !mcmie::dims_ok(*detector) || !(detector->flags & MC_EXIT_LOG)) return 0;
     using namespace mcmie;
-    // Each photon leaves through an image at most once.  Spread evenly over
-    // the ranges and the blocks of a full launch, a block adds about
-    // n / (64 x blocks) entries to a range; its region holds half as many
-    // again (for uneven spread and unequal shares of photons) plus 256.
-    const uint64_t regions = kLogBuckets * kLogSizingBlocks;
-    const uint64_t cap = std::min<uint64_t>((n_photons + n_photons / 2 + regions - 1) / regions + 256, 0x7FFFFFFFull);
-    return workspace_words(*detector) * 8 + (regions * 4 + 7) / 8 * 8 + regions * cap * 8;
+    const mc_detector_t &d = *detector;
+    const uint64_t n_keys = (uint64_t)d.side_nx * d.side_ny + (uint64_t)d.trans_nx * d.trans_ny;
+    // The table-in-LDS shape: at most as many ranges as the HG walk takes.
+    const uint64_t regions = ((uint64_t)1 << log_shape(n_keys, true).rbits) * kLogSizingBlocks;
+    return workspace_words(d) * 8 + log_bytes_for(n_photons, regions);
 }
 
 extern "C" uint64_t mc_workspace_bytes_batch(const mc_detector_t *detector, uint32_t n_items)
 {
     if (!detector || !mcmie::dims_ok(*detector) || n_items < 1 || n_items > MC_MAX_BATCH) return 0;
     return mcmie::batch_workspace_words(*detector, n_items) * 8;
+}
+
+extern "C" uint64_t mc_workspace_bytes_batch_log(const mc_detector_t *detector, uint32_t n_items,
+                                                 uint64_t total_photons)
+{
+    using namespace mcmie;
+    if (!detector || !dims_ok(*detector) || !(detector->flags & MC_EXIT_LOG) || n_items < 1 ||
+        n_items > MC_MAX_BATCH)
+        return 0;
+    const mc_detector_t &d = *detector;
+    const uint64_t n_keys = ((uint64_t)d.side_nx * d.side_ny + (uint64_t)d.trans_nx * d.trans_ny) * n_items;
+    const uint64_t regions = ((uint64_t)1 << log_shape(n_keys, false).rbits) * kLogSizingBlocks;
+    return batch_workspace_words(d, n_items) * 8 + log_bytes_for(total_photons, regions);
 }
 
 extern "C" int mc_simulate_batch(const mc_batch_item_t *items, uint32_t n_items, int32_t n_cdf,

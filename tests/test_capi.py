@@ -125,7 +125,10 @@ def test_exit_log_sizes_and_checks():
     """MC_EXIT_LOG: the workspace words are unchanged and the log comes on
     top: a 4-byte count per region (64 ranges x 512 blocks of a full
     launch) and per region 1.5 times a block's share of photons in a range
-    plus 256 entries of 8 bytes.  The flag is refused with records."""
+    plus 64 entries of 8 bytes.  Ranges hold at most 8192 keys where the LDS
+    allows: 64 of them for up to 2^19 keys, 256 at most beside a Mie table
+    (single medium), 4096 at most in a batch.  The flag is refused with
+    records."""
     import paper_2507_23189_amd as mc
     _lib_path()
     spec, med, src, geo, det, run = _valid_args()
@@ -133,10 +136,20 @@ def test_exit_log_sizes_and_checks():
     assert mc.mc_workspace_bytes_log(det, 10**6) == 0           # flag not set
     det.flags = mc.MC_EXIT_LOG
     assert mc.mc_workspace_bytes(det) == base
+    def log_bytes(n, regions):
+        cap = -(-(n + n // 2) // regions) + 64
+        return regions * 4 + regions * cap * 8
     regions = 64 * 512
     for n in (0, 1, 10**6, 10**8, 10**9):
-        cap = -(-(n + n // 2) // regions) + 256
-        assert mc.mc_workspace_bytes_log(det, n) == base + regions * 4 + regions * cap * 8, n
+        assert mc.mc_workspace_bytes_log(det, n) == base + log_bytes(n, regions), n
+    # 1024 x 1024 images: 2^21 keys, 256 ranges.
+    big = mc.Detector(1024, 1024, 1024, 1024, mc.MC_EXIT_LOG)
+    assert mc.mc_workspace_bytes_log(big, 10**9) == mc.mc_workspace_bytes(big) + log_bytes(10**9, 256 * 512)
+    # A batch of 256 media of 256 x 256 + 256 x 256 pixels: 2^25 keys, 4096 ranges.
+    bd = mc.Detector(256, 256, 256, 256, mc.MC_EXIT_LOG)
+    assert mc.mc_workspace_bytes_batch_log(bd, 256, 5 * 10**8) == (mc.mc_workspace_bytes_batch(bd, 256)
+                                                                    + log_bytes(5 * 10**8, 4096 * 512))
+    assert mc.mc_workspace_bytes_batch_log(mc.Detector(256, 256, 256, 256, 0), 256, 10) == 0
     assert mc.mc_workspace_bytes_log(mc.Detector(0, 1, 1, 1, mc.MC_EXIT_LOG), 10) == 0
     det.flags = mc.MC_EXIT_LOG | mc.MC_RECORD
     tal = _tally_stub(det)

@@ -27,14 +27,19 @@ def _tables(mc, ws, dev):
     return [mc.mie_table_build(mc.args_from_workload(w)[0], dev) for w in ws]
 
 
-def _batch(mc, ws, tables, dev, *, fix64=True, sigma=True, block_size=0, chunk=0, grid_blocks=0):
+def _batch(mc, ws, tables, dev, *, fix64=True, sigma=True, block_size=0, chunk=0, grid_blocks=0, log=False,
+           log_photons=None, workspace_bytes=None):
     import torch
-    flags = (mc.MC_FIX64 if fix64 else 0) | (mc.MC_SIGMA if sigma else 0)
+    flags = (mc.MC_FIX64 if fix64 else 0) | (mc.MC_SIGMA if sigma else 0) | (mc.MC_EXIT_LOG if log else 0)
     _, _, src, geo, det, run = mc.args_from_workload(ws[0], flags=flags, block_size=block_size,
                                                      grid_blocks=grid_blocks)
     run.chunk = chunk
     items = [mc.batch_item(w, t) for w, t in zip(ws, tables)]
-    tal = mc.Tally.alloc_batch(det, len(ws), dev, sigma=sigma, fix64=fix64)
+    n_all = sum(w.n_photons for w in ws)
+    tal = mc.Tally.alloc_batch(det, len(ws), dev, sigma=sigma, fix64=fix64,
+                               log_photons=n_all if log_photons is None else log_photons)
+    if workspace_bytes is not None:
+        tal.workspace = torch.empty((workspace_bytes + 7) // 8, dtype=torch.int64, device=dev)
     mc.mc_simulate_batch(items, ws[0].n_cdf, src, geo, det, run, tal)
     torch.cuda.synchronize()
     return tal
@@ -122,3 +127,36 @@ def test_autotuner_picks_a_timed_candidate(mc, cuda_device):
     ref = _batch(mc, ws, tables, cuda_device, sigma=False)
     np.testing.assert_array_equal(tal.side.cpu().numpy(), ref.side.cpu().numpy())
     np.testing.assert_array_equal(tal.scalars.cpu().numpy(), ref.scalars.cpu().numpy())
+
+
+@pytest.mark.parametrize("case", ["full", "no_entries", "no_log", "shape"])
+def test_batch_exit_log_equals_atomic_path(mc, cuda_device, case):
+    """The batched launch with its image exits through the exit log (key
+    ranges over all media's keys, 2^12 of them for 64 media of 256 x 256 +
+    256 x 256 pixels) equals the atomic path bit for bit: with a log sized
+    for the batch, with room for the region counts but no entries (every
+    exit falls back to an atomic), with no room for the log at all (the
+    atomic path) and in another launch shape."""
+    import torch
+    ws = W.batch_workloads(64, photon_scale=1e-2)
+    tables = _tables(mc, ws, cuda_device)
+    ref = _batch(mc, ws, tables, cuda_device)
+    kw = dict(log=True)
+    if case in ("no_entries", "no_log"):
+        _, _, _, _, det, _ = mc.args_from_workload(ws[0], flags=mc.MC_FIX64 | mc.MC_SIGMA)
+        det_s = mc.Detector(det.side_nx, det.side_ny, det.trans_nx, det.trans_ny, det.flags)
+        base = mc.mc_workspace_bytes_batch(det_s, len(ws))
+        grid = 2 * torch.cuda.get_device_properties(cuda_device).multi_processor_count
+        nbytes = base + (((4096 * grid * 4) + 7) // 8 * 8 if case == "no_entries" else 0)
+        kw["workspace_bytes"] = nbytes
+    if case == "shape":
+        kw.update(block_size=512, chunk=256)
+    got = _batch(mc, ws, tables, cuda_device, **kw)
+    for k in ("side", "trans", "side_w2", "trans_w2", "scalars"):
+        np.testing.assert_array_equal(getattr(ref, k).cpu().numpy(), getattr(got, k).cpu().numpy(), err_msg=k)
+    fallback = int(got.workspace[21].item())
+    print(f"{case}: {fallback} exits added directly", flush=True)
+    if case == "no_entries":
+        assert fallback > 0
+    else:
+        assert fallback == 0

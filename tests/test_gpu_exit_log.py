@@ -109,26 +109,27 @@ def test_log_ragged_shapes(mc, cuda_device, table, shape):
     _same(a, b)
 
 
-@pytest.mark.parametrize("cap", [0, 64, 1000, 12000])
+@pytest.mark.parametrize("cap", [-1, 0, 64, 1000, 12000])
 def test_log_capacity_fallback(mc, cuda_device, table, cap):
     """A launch of two 1024-lane blocks whose log holds 0, 64, 1000 or 12000
     entries per block and range: each block adds about 5400 exits to every
     range, so with small regions most of them find the log full and are
-    added directly.  The results do not change."""
+    added directly.  With no room even for the region counts (-1) the walk
+    takes the atomic path.  The results do not change."""
     import torch
     w = W.paper_scale(4.0)
     flags = mc.MC_FIX64 | mc.MC_SIGMA
     n = 1_000_000
     _, _, _, _, det, _ = mc.args_from_workload(w, flags=flags | mc.MC_EXIT_LOG)
     regions = 64 * 2
-    ws_bytes = mc.mc_workspace_bytes(det) + regions * 4 + regions * cap * 8
+    ws_bytes = mc.mc_workspace_bytes(det) + (regions * 4 + regions * cap * 8 if cap >= 0 else 0)
     small = mc.Tally.alloc(det, cuda_device, sigma=True, fix64=True, log_photons=0)
     small.workspace = torch.empty((ws_bytes + 7) // 8, dtype=torch.int64, device=cuda_device)
     a = _run(mc, cuda_device, w, table, flags, n_photons=n, grid_blocks=2)
     b = _run(mc, cuda_device, w, table, flags | mc.MC_EXIT_LOG, n_photons=n, tally=small, grid_blocks=2)
     _same(a, b)
     print(f"cap {cap}: {b['fallback']} exits added directly")
-    if cap <= 1000:
+    if 0 <= cap <= 1000:
         assert b["fallback"] > 0
     else:
         assert b["fallback"] == 0
