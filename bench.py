@@ -78,34 +78,50 @@ METRIC = "Mie MC scatter events/s (τ=4, 1e8 photons); fwd+adjoint vs fwd-only t
 # walk's arithmetic per unit of work, by issue class.  gfx950 issues a wave64
 # full-rate instruction (FP32 add/mul/fma, 32-bit integer add, and/or/xor,
 # move, all operands in vector registers) in 2 SIMD cycles, half-rate ones
-# (compares, selects, min/max/med3, shifts, conversions, 32x32-bit products
-# including v_mad_u64_u32, three-input bit operations) in 4, transcendentals
-# (rcp, sqrt, log, sin, cos) in 8; measured by bench/issue_cost_probe.hip at 2.3-2.6,
-# 3.7-4.4 and 8.0-8.2 cycles.  A slot is one full-rate lane-instruction, so a
-# unit costs full + 2 half + 4 trans slots.
-#   step         Philox4x32-10 (20 products, 20 three-input XORs), the free-path
-#                uniform and its log, three wall distances (reciprocal, two
-#                products and a three-way maximum each), nearest wall (min3),
-#                hit test and step length, move, step count
-#   interaction  weight, absorption and event count, roulette test, two
-#                uniforms, inverse-CDF index, fraction and lerp, cos and
-#                sin of the polar angle, sin and cos of the azimuth, the
-#                orthonormal basis (Duff et al.), new direction, Newton
-#                renormalisation; with Henyey-Greenstein (Eq. 11) the table
-#                index, fraction and lerp (4 full, 2 half: product, two
-#                conversions, fraction, difference, fma) give way to the
-#                closed-form inverse and a clamp of v (4 full, 1 half,
-#                1 transcendental: fma, reciprocal, product, fma, product,
-#                maximum)
-#   boundary     the reflection uniform, wall axis and its direction component,
-#                clamp onto the box, unpolarised Fresnel with TIR, reflect-or-
-#                leave, exit face and reflection count
+# (compares, selects, min/max/med3, shifts and funnel shifts, conversions,
+# 32x32-bit products including v_mad_u64_u32, three-input bit operations) in
+# 4, transcendentals (rcp, sqrt, log, sin, cos) in 8; measured by
+# bench/issue_cost_probe.hip at 2.3-2.6, 3.7-4.4 and 8.0-8.2 cycles.  A slot
+# is one full-rate lane-instruction, so a unit costs full + 2 half + 4 trans
+# slots.  A uniform is one funnel shift (23 random bits under the exponent of
+# 1.0) and one subtraction: 1 full, 1 half.
+#   step         Philox4x32-10 (20 products, 20 three-input XORs: 40 half);
+#                the free-path uniform (1 full, 1 half), its log and the
+#                product by -1/mu (1 full, 1 trans); three wall distances
+#                (per axis a reciprocal, a difference, two products and a
+#                three-way maximum: 9 full, 3 half, 3 trans); nearest wall
+#                (min3), hit test and step length (3 half); move (3 full);
+#                step count (1 full)  = 15 full, 47 half, 4 trans.  (The path
+#                length is summed only by the kernels that tally path
+#                moments or records.)
+#   interaction  event count, absorption and weight (3 full); roulette test
+#                (1 half); two uniforms (2 full, 2 half); inverse-CDF
+#                product, two conversions, fraction, difference and lerp
+#                (4 full, 2 half); cos and sin of the polar angle from
+#                v = 1 - cos (3 full, 1 trans); cos and sin of the azimuth
+#                (2 trans); the orthonormal basis of Duff et al. (copysign,
+#                sum and reciprocal, 9 products and fmas: 9 full, 1 half,
+#                1 trans); new direction (12 full); Newton renormalisation
+#                (7 full)  = 40 full, 6 half, 4 trans.  With Henyey-Greenstein
+#                (Eq. 11) the table's 4 full, 2 half give way to the closed-
+#                form inverse and a clamp of v (4 full, 1 half, 1 trans:
+#                fma, reciprocal, product, fma, product, maximum)
+#                = 40 full, 5 half, 5 trans
+#   boundary     the reflection uniform (1 full, 1 half); wall axis and its
+#                direction component (2 compares, 4 selects); clamp onto the
+#                box (3 med3); unpolarised Fresnel with TIR (cos of
+#                refraction: 3 full, 1 trans; the two amplitude ratios over
+#                one reciprocal of the product of their denominators: 9 full,
+#                1 trans; R: 3 full; TIR compare and select: 2 half);
+#                reflect-or-leave (1 compare, 3 selects); exit face (1
+#                compare, 1 shift-or, 1 select) and reflection count (1 half)
+#                = 16 full, 20 half, 2 trans
 #   exit         imaged faces: pixel row and column (scale, floor, clamp), key,
-#                weight added; other faces: face total
-CENSUS = {"step": {"full": 17, "half": 47, "trans": 4},
-          "interaction": {"full": 41, "half": 7, "trans": 4},
-          "interaction_hg": {"full": 41, "half": 6, "trans": 5},
-          "boundary": {"full": 14, "half": 18, "trans": 3},
+#                weight added (3 full, 5 half); other faces: face total (2 full)
+CENSUS = {"step": {"full": 15, "half": 47, "trans": 4},
+          "interaction": {"full": 40, "half": 6, "trans": 4},
+          "interaction_hg": {"full": 40, "half": 5, "trans": 5},
+          "boundary": {"full": 16, "half": 20, "trans": 2},
           "imaged_exit": {"full": 3, "half": 5, "trans": 0},
           "other_exit": {"full": 2, "half": 0, "trans": 0}}
 SLOTS_PER_CLASS = {"full": 1, "half": 2, "trans": 4}
@@ -126,8 +142,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # WRITE_SIZE x 1.0); valid only for the tally path and kernel code it was
 # measured on (profiles/walk_tau4_counters.md): the digest covers the walk
 # sources without comments and whitespace, so a comment edit keeps it.
-TRAFFIC = {"tally": "log", "sources_sha256": "d61780306fcb26fcdf6296ff663d4d2921db0edda2249ca8aa702e31e7c4c733",
-           "fetch_kib": 380.1, "write_kib": 540579.8, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"tally": "log", "sources_sha256": "f58cdbb450b1d93f6f0f9674deba4b2cd6c025b806279794a103b8dcd0988fd9",
+           "fetch_kib": 375.05, "write_kib": 540384.0, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 

@@ -41,9 +41,11 @@ __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
 
 // Uniform in (0, 1) from one 32-bit word: (2 floor(r / 2^9) + 1) / 2^24,
 // exact in FP32 (23 random bits at the centre of their cell).
+// Built without a conversion: the 23 bits under the exponent field of 1.0
+// give 1 + k 2^-23, and subtracting 1 - 2^-24 is exact (both lie in [1/2, 2]).
 __device__ __forceinline__ float uniform01(uint32_t r)
 {
-    return __builtin_fmaf((float)(r >> 9), 0x1.0p-23f, 0x1.0p-24f);
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, r, 9u)) - 0x1.fffffep-1f;
 }
 
 }  // namespace mcmie

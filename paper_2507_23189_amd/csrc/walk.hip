@@ -172,28 +172,29 @@ __device__ __forceinline__ int pixel_scaled(float coord, float per_mm, int n)
     return min(max(i, 0), n - 1);
 }
 
-// Distance to the nearest wall along d and its axis (ties go to the lower
-// axis).  Per axis, with r = 1/d, the walls at L and at 0 lie (L - p) r and
-// -p r ahead; for p inside the box one of the two is negative, so the larger
-// is the wall the photon moves towards.  It is clamped at 0, so a position
-// that rounding left a hair outside the box is taken back at once.  An axis
-// with d = 0 gives r = inf and so t = inf: it is never hit (short of a
-// position exactly on one of its walls, where 0 x inf makes the far term NaN,
-// the maximum drops it and t is 0; the host keeps the source off that case).
-// No compare or select: three full-rate operations and one three-way maximum
-// per axis.
-__device__ __forceinline__ float wall_distance(float px, float py, float pz, float dx, float dy, float dz,
-                                               float Lx, float Ly, float Lz, int &axis)
+// Distances to the walls ahead along d, per axis.  With r = 1/d, the walls
+// at L and at 0 lie (L - p) r and -p r ahead; for p inside the box one of the
+// two is negative, so the larger is the wall the photon moves towards.  It is
+// clamped at 0, so a position that rounding left a hair outside the box is
+// taken back at once.  An axis with d = 0 gives r = inf and so t = inf: it is
+// never hit (short of a position exactly on one of its walls, where 0 x inf
+// makes the far term NaN, the maximum drops it and t is 0; the host keeps the
+// source off that case).  No compare or select: three full-rate operations
+// and one three-way maximum per axis.
+__device__ __forceinline__ void wall_distances(float px, float py, float pz, float dx, float dy, float dz,
+                                               float Lx, float Ly, float Lz, float &tx, float &ty, float &tz)
 {
     const float rx = __builtin_amdgcn_rcpf(dx), ry = __builtin_amdgcn_rcpf(dy), rz = __builtin_amdgcn_rcpf(dz);
-    const float tx = fmaxf(fmaxf((Lx - px) * rx, -px * rx), 0.f);
-    const float ty = fmaxf(fmaxf((Ly - py) * ry, -py * ry), 0.f);
-    const float tz = fmaxf(fmaxf((Lz - pz) * rz, -pz * rz), 0.f);
-    float db = tx;
-    axis = 0;
-    if (ty < db) { db = ty; axis = 1; }
-    if (tz < db) { db = tz; axis = 2; }
-    return db;
+    tx = fmaxf(fmaxf((Lx - px) * rx, -px * rx), 0.f);
+    ty = fmaxf(fmaxf((Ly - py) * ry, -py * ry), 0.f);
+    tz = fmaxf(fmaxf((Lz - pz) * rz, -pz * rz), 0.f);
+}
+
+// The axis of the nearest wall, db = min(tx, ty, tz) (ties go to the lower
+// axis).  The walk takes it only for the steps that reach a wall.
+__device__ __forceinline__ int wall_axis(float db, float tx, float ty)
+{
+    return db == tx ? 0 : (db == ty ? 1 : 2);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
@@ -304,9 +305,11 @@ void walk_kernel(WalkArgs a)
     // side image while its path moments are tallied).
     int beam_face = -2;   // -2: no face (it matches no photon's face, which is -1 or up)
     {
-        int ax;
-        const float db = wall_distance(a.pos0[0], a.pos0[1], a.pos0[2], a.dir0[0], a.dir0[1], a.dir0[2],
-                                       a.size[0], a.size[1], a.size[2], ax);
+        float tx, ty, tz;
+        wall_distances(a.pos0[0], a.pos0[1], a.pos0[2], a.dir0[0], a.dir0[1], a.dir0[2], a.size[0], a.size[1],
+                       a.size[2], tx, ty, tz);
+        const float db = fminf(fminf(tx, ty), tz);
+        const int ax = wall_axis(db, tx, ty);
         const float bx = fmaf(db, a.dir0[0], a.pos0[0]), by = fmaf(db, a.dir0[1], a.pos0[1]);
         const float bz = fmaf(db, a.dir0[2], a.pos0[2]);
         const float da = ax == 0 ? a.dir0[0] : (ax == 1 ? a.dir0[1] : a.dir0[2]);
@@ -442,6 +445,10 @@ void walk_kernel(WalkArgs a)
     float i_dz = a.dir0[2], i_w = a.w0;
     if (INIT_V)
         asm volatile("" : "+v"(i_px), "+v"(i_py), "+v"(i_pz), "+v"(i_dx), "+v"(i_dy), "+v"(i_dz), "+v"(i_w));
+    // The roulette threshold, compared at every interaction, likewise: in a
+    // scalar register it was spilled and reloaded (four v_readlane) each time.
+    float v_rw = a.roulette_w;
+    if (INIT_V) asm volatile("" : "+v"(v_rw));
     const float *l_tab = a.inv_cdf;
     uint32_t l_ctr = a.instance;
     // Batched: move the lane accumulators into the LDS scalars of its medium.
@@ -471,8 +478,12 @@ void walk_kernel(WalkArgs a)
     int cause = 0, face = -1, axis = 0;
 
     for (;;) {
+        // Free lanes (wave-uniform counts); refill_min <= 64, so a wave whose
+        // lanes are all free always runs the end-of-photon work.
         const uint64_t need = __ballot(!alive);
-        if (need && ((uint32_t)__popcll(need) >= a.refill_min || __ballot(alive) == 0)) {
+        const uint32_t n_need = (uint32_t)__popcll(need);
+        uint32_t n_alive = 64u - n_need;
+        if (n_need >= a.refill_min) {
             // ---- end-of-photon work of the waiting lanes ----------------------
             if (pending) {
                 const uint32_t scal_at = BATCH ? l_slot * kBatchScal : 0u;
@@ -638,11 +649,12 @@ void walk_kernel(WalkArgs a)
                 w = INIT_V ? i_w : a.w0;
                 L = 0.f; A = 0.f; k = 0; step = 0;
             }
-            const uint32_t took = min((uint32_t)__popcll(need), q_rem);
+            const uint32_t took = min(n_need, q_rem);
             q_next += took;
             q_rem -= took;
+            n_alive += took;
         }
-        if (__ballot(alive) == 0) break;
+        if (n_alive == 0) break;
 
         bool ended = false;
         const uint32_t scal_at = BATCH ? l_slot * kBatchScal : 0u;   // the medium's LDS scalars
@@ -661,16 +673,19 @@ void walk_kernel(WalkArgs a)
             ++step;
 
             // Nearest wall along the direction.
-            const float db = wall_distance(px, py, pz, dx, dy, dz, v_lx, v_ly, v_lz, axis);
+            float tx, ty, tz;
+            wall_distances(px, py, pz, dx, dy, dz, v_lx, v_ly, v_lz, tx, ty, tz);
+            const float db = fminf(fminf(tx, ty), tz);
 
             const bool hit = s >= db;
-            const float t = hit ? db : s;
+            const float t = fminf(s, db);
             px = fmaf(t, dx, px); py = fmaf(t, dy, py); pz = fmaf(t, dz, pz);
             L += t;
             if (hit) {
                 // Boundary: clamp into the box (a move that overshot the wall
                 // by rounding lands on it), then reflect (u3 < R) or leave.
                 // Written as selects so the wave runs it without branches.
+                axis = wall_axis(db, tx, ty);
                 const bool on_x = axis == 0, on_y = axis == 1, on_z = axis == 2;
                 const float da = on_x ? dx : (on_y ? dy : dz);
                 const bool pos_side = da > 0.f;
@@ -683,8 +698,10 @@ void walk_kernel(WalkArgs a)
                     const float st2 = v_n12sq * fmaf(-ci, ci, 1.f);
                     // 1 - st2 > 0 wherever R uses ct; under TIR the select drops it.
                     const float ct = __builtin_amdgcn_sqrtf(1.f - st2);
-                    const float rs = (ci - v_n21 * ct) * __builtin_amdgcn_rcpf(ci + v_n21 * ct);
-                    const float rp = (v_n21 * ci - ct) * __builtin_amdgcn_rcpf(v_n21 * ci + ct);
+                    const float ds = fmaf(v_n21, ct, ci), dp = fmaf(v_n21, ci, ct);
+                    const float r = __builtin_amdgcn_rcpf(ds * dp);
+                    const float rs = fmaf(-v_n21, ct, ci) * dp * r;
+                    const float rp = fmaf(v_n21, ci, -ct) * ds * r;
                     R = st2 >= 1.f ? 1.f : 0.5f * fmaf(rs, rs, rp * rp);
                 }
                 const bool refl = u3 < R;
@@ -699,7 +716,7 @@ void walk_kernel(WalkArgs a)
                 ++k;
                 A = fmaf(w, l_abs, A);
                 w *= l_alb;
-                if (w < a.roulette_w) {
+                if (w < v_rw) {
                     if (u3 < a.roulette_p) {
                         const float wn = w * a.inv_roulette_p;
                         atomicAdd(&s_scal[scal_at + MC_S_ROULETTE_NET], fix(wn) - fix(w));
@@ -720,7 +737,8 @@ void walk_kernel(WalkArgs a)
                         // it): i <= n - 2 and entry i + 1 exists.
                         const float tt = u1 * tab_scale;
                         const int i = (int)tt;
-                        const float f = tt - (float)i;
+                        // The fraction from the unrounded product u1 (n - 1).
+                        const float f = fmaf(u1, tab_scale, -(float)i);
                         const float t0 = GLOBAL_TABLE ? l_tab[i] : s_table[i];
                         const float t1 = GLOBAL_TABLE ? l_tab[i + 1] : s_table[i + 1];
                         v = fmaf(f, t1 - t0, t0);
@@ -1318,6 +1336,17 @@ int medium_coefficients(const char *fn, const mc_medium_t &m, double size_z, Med
 // outlive the call).
 constexpr int kInstPerCopy = 32;
 constexpr uint32_t kRefillMin = 16;        // free lanes of a wave that trigger end-of-photon work
+
+// The same for a single medium of optical depth tau along the beam axis.  A
+// photon takes about 1 + tau steps, so thin media end many photons per step
+// and do better with fewer, larger rounds, thick ones with more frequent
+// ones that leave fewer lanes idle (measured optima at 1e8 photons: about 32
+// free lanes at tau = 1, 12 at tau = 4, 8 at tau = 8).
+uint32_t refill_min_for(double tau)
+{
+    if (!(tau >= 0.0)) return kRefillMin;
+    return (uint32_t)std::min(32.0, std::max(8.0, std::round(64.0 / (1.0 + tau))));
+}
 struct InstChunk {
     BatchInst v[kInstPerCopy];
     uint32_t n, first;
@@ -1391,7 +1420,13 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
         chunk = std::max<uint64_t>(64, std::min<uint64_t>(1024, (chunk + 63) / 64 * 64));
     }
     a.chunk = (uint32_t)chunk;
-    a.refill_min = kRefillMin;
+    // Refill threshold from the optical depth; batched launches keep the
+    // fixed one (their threshold from the media's photon-weighted mean depth
+    // measured no faster).
+    a.refill_min = batch ? kRefillMin
+                         : refill_min_for(a.neg_ln2_over_mu < 0.f && std::isfinite(a.neg_ln2_over_mu)
+                                              ? -M_LN2 / (double)a.neg_ln2_over_mu * a.size[2]
+                                              : 0.0);
 
     // ---- exit log: a region of log_cap entries per block and key range in
     // what the caller gave beyond the workspace words (the walk writes every
