@@ -128,7 +128,8 @@ struct WalkArgs {
     uint64_t n_units;
 };
 
-constexpr int kCopies = 8;                 // per-XCD image copies in the workspace
+constexpr int kCopies = 8;                 // per-XCD image copies in the workspace (at most)
+constexpr uint64_t kLogBinBlocks = 512;    // log_bin blocks that fill the chip (two per CU)
 constexpr double kFix = 4294967296.0;      // fixed-point scale 2^32 per unit weight
 
 // w * 2^32 rounded to nearest, ties to even, for 0 <= w < 2^32.  The integer
@@ -877,9 +878,9 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
     for (size_t i = t0; i < (size_t)MC_REC_F_N * n_rec; i += stride) rec_f[i] = 0.f;
 }
 
-// Sum the exit log into the per-XCD image copies.  Block (range b, part p,
-// copy s) takes the regions of range b that the s-th eighth of the walk's
-// blocks wrote (log_count entries each), adds the fixed-point weights (and
+// Sum the exit log into the image copies.  Block (range b, part p, copy s)
+// takes the regions of range b that the s-th of n_copies equal shares of the
+// walk's blocks wrote (log_count entries each), adds the fixed-point weights (and
 // squared weights) of the entries whose index within the range lies in part
 // p into an LDS histogram of 2^kLogHistBits sums, then adds the non-zero sums
 // into copy s.  Those keys of copy s have no other writer (the walk's
@@ -889,21 +890,21 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
 template <bool SIGMA>
 __global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, const uint32_t *count, uint32_t cap,
                                                 uint32_t walk_blocks, unsigned long long *copies,
-                                                unsigned long long *copies2, uint64_t n_total, uint32_t parts,
-                                                uint32_t bits, uint32_t rbits, uint32_t inv_mul)
+                                                unsigned long long *copies2, uint32_t n_copies, uint64_t n_total,
+                                                uint32_t parts, uint32_t bits, uint32_t rbits, uint32_t inv_mul)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned long long s_hist[];
     constexpr uint32_t H = 1u << kLogHistBits;
     unsigned long long *s_hist2 = s_hist + H;
-    const uint32_t s = blockIdx.x % kCopies, rest = blockIdx.x / kCopies;
+    const uint32_t s = blockIdx.x % n_copies, rest = blockIdx.x / n_copies;
     const uint32_t part = rest % parts, b = rest / parts;
     for (uint32_t i = threadIdx.x; i < H; i += blockDim.x) {
         s_hist[i] = 0ull;
         if (SIGMA) s_hist2[i] = 0ull;
     }
     __syncthreads();
-    const uint32_t g0 = (uint32_t)((uint64_t)walk_blocks * s / kCopies);
-    const uint32_t g1 = (uint32_t)((uint64_t)walk_blocks * (s + 1) / kCopies);
+    const uint32_t g0 = (uint32_t)((uint64_t)walk_blocks * s / n_copies);
+    const uint32_t g1 = (uint32_t)((uint64_t)walk_blocks * (s + 1) / n_copies);
     const uint32_t lane = threadIdx.x & 63u, waves = blockDim.x >> 6;
     constexpr uint32_t U = 4;   // entries in flight per lane
     // Each wave takes every waves-th region and reads its entries U x 64 at a time.
@@ -1368,19 +1369,34 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     const uint64_t n_pix = a.n_pix_inst, n_side = a.n_side, n_trans = n_pix - n_side;
     const uint64_t n_total = n_pix * n_inst;
     unsigned long long *ws = (unsigned long long *)t.workspace;
-    const uint64_t copies = (uint64_t)a.copy_mask + 1;
+    const uint64_t max_copies = (uint64_t)a.copy_mask + 1;
     a.ws_scal = ws;
     a.ws_img = ws + kWsScalarWords * n_inst;
-    a.ws_img2 = (det.flags & MC_SIGMA) ? a.ws_img + copies * n_total : nullptr;
     a.n_pix = n_total;
     a.n_inst = n_inst;
 
-    const uint64_t ws_words = workspace_words(det, n_inst, copies);
     // A batched launch keeps its schedule after the workspace words; the exit
     // log follows: its counts, then the regions.  A workspace without room for
     // the counts takes the atomic path (the same sums).
     const uint64_t sched_words = batch ? (n_inst * sizeof(BatchInst) + 7) / 8 : 0;
     const LogShape shape = log_shape(n_total, !batch && phase == MC_PHASE_MIE);
+    // Keys of a range have indices below 2^(bits - rbits + 3); log_bin takes
+    // them in parts of 2^kLogHistBits.
+    const uint64_t per_range = 1ull << (shape.bits - shape.rbits + 3);
+    const uint32_t parts = (uint32_t)((per_range + (1u << kLogHistBits) - 1) >> kLogHistBits);
+    // With the exit log the image copies take log_bin's sums (and the rare
+    // fallback atomics): as many copies as give it kLogBinBlocks blocks, so
+    // that fine key ranges (large images, batches) leave fewer copies to clear
+    // and to sum.  Without it, one per XCD for the image atomics.  The
+    // workspace layout keeps room for all of them either way (the schedule and
+    // the log start at the same place); the copies in use come first.
+    auto copies_for = [&](bool log) -> uint64_t {
+        if (!log) return max_copies;
+        const uint64_t bin_blocks = ((uint64_t)1 << shape.rbits) * parts;
+        uint64_t c = 1;
+        while (c < max_copies && bin_blocks * c < kLogBinBlocks) c <<= 1;
+        return c;
+    };
 
     // ---- launch shape: 1024-lane blocks (768 with path moments), two per CU, each with
     // the table (single medium), the scalar words, the per-wave exit queues and
@@ -1406,12 +1422,16 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
         const int blocks_per_cu = std::max(1, std::min((int)(160 * 1024 / lds), 32 / (block / 64)));
         grid = rn.grid_blocks > 0 ? rn.grid_blocks : cus * blocks_per_cu;
     };
+    const uint64_t ws_words = workspace_words(det, n_inst, max_copies);
     bool use_log = (det.flags & MC_EXIT_LOG) != 0;
     launch_shape(use_log);
     if (use_log && t.workspace_bytes / 8 < ws_words + sched_words + (((uint64_t)grid << shape.rbits) * 4 + 7) / 8) {
         use_log = false;
         launch_shape(false);
     }
+    const uint64_t copies = copies_for(use_log);
+    a.copy_mask = (uint32_t)(copies - 1);
+    a.ws_img2 = (det.flags & MC_SIGMA) ? a.ws_img + copies * n_total : nullptr;
     if (lds > 160 * 1024) return fail(MC_EINVAL, "mc_simulate: %zu bytes of LDS per block do not fit a CU", lds);
     const uint64_t waves_total = (uint64_t)grid * (block / 64);
     uint64_t chunk = rn.chunk;
@@ -1431,7 +1451,7 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     // ---- exit log: a region of log_cap entries per block and key range in
     // what the caller gave beyond the workspace words (the walk writes every
     // count, so nothing needs clearing) ----
-    uint64_t clear_words = ws_words;
+    uint64_t clear_words = workspace_words(det, n_inst, copies);
     if (use_log) {
         const uint64_t regions = ((uint64_t)1 << shape.rbits) * grid;
         const uint64_t log_at = ws_words + sched_words;
@@ -1512,18 +1532,15 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     }
     if (rn.walk_events[1]) MC_HIP_CHECK(hipEventRecord((hipEvent_t)rn.walk_events[1], st));
     if (use_log && units > 0) {
-        // Keys of a range have indices below 2^(bits - rbits + 3); one part
-        // per 2^kLogHistBits of them.
-        const uint64_t per_range = 1ull << (a.log_bits - a.log_rbits + 3);
-        const uint32_t parts = (uint32_t)((per_range + (1u << kLogHistBits) - 1) >> kLogHistBits);
         uint32_t inv = kLogHashMul;   // inverse of the odd multiplier mod 2^32 (Newton: x <- x (2 - m x))
         for (int i = 0; i < 5; ++i) inv *= 2u - kLogHashMul * inv;
         const size_t hist = ((size_t)8 << kLogHistBits) * (sig ? 2 : 1);
         auto bin = sig ? log_bin<true> : log_bin<false>;
         MC_HIP_CHECK(hipFuncSetAttribute((const void *)bin, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hist));
-        hipLaunchKernelGGL(bin, dim3((1u << a.log_rbits) * parts * kCopies), dim3(1024), hist, st,
+        hipLaunchKernelGGL(bin, dim3((1u << a.log_rbits) * parts * (uint32_t)copies), dim3(1024), hist, st,
                            (const unsigned long long *)a.log, (const uint32_t *)a.log_count, a.log_cap,
-                           (uint32_t)grid, a.ws_img, a.ws_img2, n_total, parts, a.log_bits, a.log_rbits, inv);
+                           (uint32_t)grid, a.ws_img, a.ws_img2, (uint32_t)copies, n_total, parts, a.log_bits,
+                           a.log_rbits, inv);
         MC_HIP_CHECK(hipGetLastError());
     }
     // ---- finalize: per-XCD copies to the caller's images, scalars to doubles ----
