@@ -114,14 +114,14 @@ METRIC = "Mie MC scatter events/s (τ=4, 1e8 photons); fwd+adjoint vs fwd-only t
 #                one reciprocal of the product of their denominators: 9 full,
 #                1 trans; R: 3 full; TIR compare and select: 2 half);
 #                reflect-or-leave (1 compare, 3 selects); exit face (1
-#                compare, 1 shift-or, 1 select) and reflection count (1 half)
-#                = 16 full, 20 half, 2 trans
+#                compare, 1 shift-or, 1 select)  = 16 full, 19 half, 2 trans.
+#                (Reflections are not counted per step: steps - events - exits.)
 #   exit         imaged faces: pixel row and column (scale, floor, clamp), key,
 #                weight added (3 full, 5 half); other faces: face total (2 full)
 CENSUS = {"step": {"full": 15, "half": 47, "trans": 4},
           "interaction": {"full": 40, "half": 6, "trans": 4},
           "interaction_hg": {"full": 40, "half": 5, "trans": 5},
-          "boundary": {"full": 16, "half": 20, "trans": 2},
+          "boundary": {"full": 16, "half": 19, "trans": 2},
           "imaged_exit": {"full": 3, "half": 5, "trans": 0},
           "other_exit": {"full": 2, "half": 0, "trans": 0}}
 SLOTS_PER_CLASS = {"full": 1, "half": 2, "trans": 4}
@@ -142,8 +142,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # WRITE_SIZE x 1.0); valid only for the tally path and kernel code it was
 # measured on (profiles/walk_tau4_counters.md): the digest covers the walk
 # sources without comments and whitespace, so a comment edit keeps it.
-TRAFFIC = {"tally": "log", "sources_sha256": "797f35fed71141697ec12ce1e29ea7be4bff7c2f96796a6200a786afbcc15a07",
-           "fetch_kib": 381.4, "write_kib": 540405.0, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"tally": "log", "sources_sha256": "9792409312952a491eb82cdeda36fc8d6776c77f10daced64f986eb1e8981d72",
+           "fetch_kib": 372.2, "write_kib": 540520.0, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 

@@ -424,7 +424,7 @@ void walk_kernel(WalkArgs a)
     uint32_t k = 0, step = 0;
     // Lane accumulators.
     unsigned long long acc_abs = 0ull;
-    uint32_t acc_events = 0, acc_steps = 0, acc_refl = 0, acc_photons = 0, acc_ball = 0;
+    uint32_t acc_events = 0, acc_steps = 0, acc_photons = 0, acc_ball = 0;
     double acc_w2 = 0.0, acc_w2k = 0.0, acc_w2l = 0.0;   // MOMENTS: image-wide second moments
     // The medium of the lane's photon (batched launches change it per photon;
     // otherwise these stay the launch's values).
@@ -450,6 +450,9 @@ void walk_kernel(WalkArgs a)
     // scalar register it was spilled and reloaded (four v_readlane) each time.
     float v_rw = a.roulette_w;
     if (INIT_V) asm volatile("" : "+v"(v_rw));
+    // 1 where the walls have a Fresnel term, 0 where the indices match.
+    float v_fresnel = a.matched ? 0.f : 1.f;
+    if (INIT_V) asm volatile("" : "+v"(v_fresnel));
     const float *l_tab = a.inv_cdf;
     uint32_t l_ctr = a.instance;
     // Batched: move the lane accumulators into the LDS scalars of its medium.
@@ -458,11 +461,10 @@ void walk_kernel(WalkArgs a)
         atomicAdd(&sc[MC_S_ABSORBED], acc_abs);
         atomicAdd(&sc[MC_S_EVENTS], (unsigned long long)acc_events);
         atomicAdd(&sc[MC_S_STEPS], (unsigned long long)acc_steps);
-        atomicAdd(&sc[MC_S_REFLECTIONS], (unsigned long long)acc_refl);
         atomicAdd(&sc[MC_S_PHOTONS], (unsigned long long)acc_photons);
         if (acc_ball) atomicAdd(&sc[kLdsBallistic], (unsigned long long)acc_ball);
         acc_abs = 0ull;
-        acc_events = acc_steps = acc_refl = acc_photons = acc_ball = 0;
+        acc_events = acc_steps = acc_photons = acc_ball = 0;
     };
 
     // A lane whose photon has ended keeps its state until the end-of-photon
@@ -576,10 +578,9 @@ void walk_kernel(WalkArgs a)
                 } else {
                     atomicAdd(&s_scal[MC_S_EVENTS], (unsigned long long)acc_events);
                     atomicAdd(&s_scal[MC_S_STEPS], (unsigned long long)acc_steps);
-                    atomicAdd(&s_scal[MC_S_REFLECTIONS], (unsigned long long)acc_refl);
                     atomicAdd(&s_scal[MC_S_PHOTONS], (unsigned long long)acc_photons);
                     atomicAdd(&s_scal[kLdsBallistic], (unsigned long long)acc_ball);
-                    acc_events = acc_steps = acc_refl = acc_photons = acc_ball = 0;
+                    acc_events = acc_steps = acc_photons = acc_ball = 0;
                 }
             }
 
@@ -693,23 +694,22 @@ void walk_kernel(WalkArgs a)
                 px = __builtin_amdgcn_fmed3f(px, 0.f, v_lx);
                 py = __builtin_amdgcn_fmed3f(py, 0.f, v_ly);
                 pz = __builtin_amdgcn_fmed3f(pz, 0.f, v_lz);
-                float R = 0.f;
-                if (!a.matched) {
-                    const float ci = fabsf(da);
-                    const float st2 = v_n12sq * fmaf(-ci, ci, 1.f);
-                    // 1 - st2 > 0 wherever R uses ct; under TIR the select drops it.
-                    const float ct = __builtin_amdgcn_sqrtf(1.f - st2);
-                    const float ds = fmaf(v_n21, ct, ci), dp = fmaf(v_n21, ci, ct);
-                    const float r = __builtin_amdgcn_rcpf(ds * dp);
-                    const float rs = fmaf(-v_n21, ct, ci) * dp * r;
-                    const float rp = fmaf(v_n21, ci, -ct) * ds * r;
-                    R = st2 >= 1.f ? 1.f : 0.5f * fmaf(rs, rs, rp * rp);
-                }
+                // Index-matched walls reflect nothing: R is scaled by 0 there
+                // (v_fresnel) rather than skipped on a flag the wave would
+                // have to reload from a spilled scalar register every step.
+                const float ci = fabsf(da);
+                const float st2 = v_n12sq * fmaf(-ci, ci, 1.f);
+                // 1 - st2 > 0 wherever R uses ct; under TIR the select drops it.
+                const float ct = __builtin_amdgcn_sqrtf(1.f - st2);
+                const float ds = fmaf(v_n21, ct, ci), dp = fmaf(v_n21, ci, ct);   // both > 0 (ci > 0)
+                const float r = __builtin_amdgcn_rcpf(ds * dp);
+                const float rs = fmaf(-v_n21, ct, ci) * dp * r;
+                const float rp = fmaf(v_n21, ci, -ct) * ds * r;
+                const float R = v_fresnel * (st2 >= 1.f ? 1.f : 0.5f * fmaf(rs, rs, rp * rp));
                 const bool refl = u3 < R;
                 dx = refl && on_x ? -dx : dx;
                 dy = refl && on_y ? -dy : dy;
                 dz = refl && on_z ? -dz : dz;
-                acc_refl += refl ? 1u : 0u;
                 ended = !refl;
                 face = refl ? -1 : 2 * axis + (pos_side ? 1 : 0);
             } else {
@@ -800,7 +800,6 @@ void walk_kernel(WalkArgs a)
         // Lane counters are below 2^32; their wave sums are taken in 64 bits.
         const unsigned long long wev = wave_sum((unsigned long long)acc_events);
         const unsigned long long wst = wave_sum((unsigned long long)acc_steps);
-        const unsigned long long wrf = wave_sum((unsigned long long)acc_refl);
         const unsigned long long wph = wave_sum((unsigned long long)acc_photons);
         const unsigned long long wbl = wave_sum((unsigned long long)acc_ball);
         if (lane == 0) {
@@ -808,7 +807,6 @@ void walk_kernel(WalkArgs a)
             atomicAdd(&s_scal[MC_S_ABSORBED], wabs);
             atomicAdd(&s_scal[MC_S_EVENTS], wev);
             atomicAdd(&s_scal[MC_S_STEPS], wst);
-            atomicAdd(&s_scal[MC_S_REFLECTIONS], wrf);
             atomicAdd(&s_scal[MC_S_PHOTONS], wph);
         }
         if (MOMENTS) {
@@ -1024,7 +1022,13 @@ __global__ void finalize_scalars(const unsigned long long *ws_scal, double *scal
     const int t = threadIdx.x;
     if (t < MC_S_RESERVED) {
         const bool weight = t <= MC_S_CAPPED_W;
-        const long long v = (long long)ws_scal[t];
+        long long v = (long long)ws_scal[t];
+        // Reflections are not counted by the walk: every step interacts or
+        // reaches a wall, and a wall step reflects unless the photon leaves,
+        // which every photon not killed by roulette or capped does once.
+        if (t == MC_S_REFLECTIONS)
+            v = (long long)(ws_scal[MC_S_STEPS] - ws_scal[MC_S_EVENTS] -
+                            (ws_scal[MC_S_PHOTONS] - ws_scal[MC_S_ROULETTE_KILLS] - ws_scal[MC_S_CAPPED]));
         scalars[t] += weight ? (double)v * (1.0 / kFix) : (double)v;
     } else if (t >= MC_S_SIDE_W2 && t <= MC_S_SIDE_W2L) {
         scalars[t] += __longlong_as_double((long long)ws_scal[t]);
@@ -1336,18 +1340,21 @@ int medium_coefficients(const char *fn, const mc_medium_t &m, double size_z, Med
 // whose arguments carry up to kInstPerCopy media each (no host buffer has to
 // outlive the call).
 constexpr int kInstPerCopy = 32;
-constexpr uint32_t kRefillMin = 16;        // free lanes of a wave that trigger end-of-photon work
+constexpr uint32_t kRefillMin = 12;        // free lanes of a wave that trigger end-of-photon work (batched)
 
-// The same for a single medium of optical depth tau along the beam axis.  A
-// photon takes about 1 + tau steps, so thin media end many photons per step
-// and do better with fewer, larger rounds, thick ones with more frequent
-// ones that leave fewer lanes idle (measured optima at 1e8 photons: about 32
-// free lanes at tau = 1, 12 at tau = 4, 8 at tau = 8).
+// The same for a single medium of optical depth tau along the beam axis,
+// from a sweep of thresholds 4..60 at tau = 0.25..16 (1e8 photons, 512 x 512,
+// exit log): 12 is within 2 % of the best from tau = 1.5 to 12.5 and 8 at 16;
+// media up to tau = 1 end most photons within two steps, and there refilling
+// only when 52 lanes are free (nearly the whole wave at once) ran 19 % faster
+// at tau = 1 than 12 and no slower below it.
 uint32_t refill_min_for(double tau)
 {
     if (!(tau >= 0.0)) return kRefillMin;
-    return (uint32_t)std::min(32.0, std::max(8.0, std::round(64.0 / (1.0 + tau))));
+    if (tau <= 1.05) return 52;
+    return tau < 14.0 ? 12 : 8;
 }
+
 struct InstChunk {
     BatchInst v[kInstPerCopy];
     uint32_t n, first;
@@ -1440,9 +1447,8 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
         chunk = std::max<uint64_t>(64, std::min<uint64_t>(1024, (chunk + 63) / 64 * 64));
     }
     a.chunk = (uint32_t)chunk;
-    // Refill threshold from the optical depth; batched launches keep the
-    // fixed one (their threshold from the media's photon-weighted mean depth
-    // measured no faster).
+    // Refill threshold from the optical depth; batched launches take the
+    // fixed one (12 ran 1 % faster there than 16, and 8 and 24 slower).
     a.refill_min = batch ? kRefillMin
                          : refill_min_for(a.neg_ln2_over_mu < 0.f && std::isfinite(a.neg_ln2_over_mu)
                                               ? -M_LN2 / (double)a.neg_ln2_over_mu * a.size[2]
