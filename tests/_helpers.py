@@ -80,25 +80,34 @@ def image_within_3sigma(img_g, img_o, w2_o, n_photons, max_w=1.0):
 
 
 def unmatched_totals(rec, bad):
-    """Per-face exit weight, absorbed weight and scatter events of the
-    photons flagged in `bad`, from one side's per-photon records: subtracted
-    from that side's scalar tallies, they leave the sums over the photons
-    both sides walked alike."""
-    out = np.zeros(10)
+    """Per-face exit weight, absorbed weight, scatter events, roulette kills,
+    capped photons, wall reflections and steps of the photons flagged in
+    `bad`, from one side's per-photon records (a photon's reflections are its
+    steps less its interactions and its exit): subtracted from that side's
+    scalar tallies, they leave the sums over the photons both sides walked
+    alike."""
+    out = np.zeros(15)
     exited = bad & (rec["cause"] == 0)
     for f in range(6):
         out[f] = np.sum(rec["w"][exited & (rec["face"] == f)], dtype=np.float64)
     out[6] = np.sum(rec["A"][bad], dtype=np.float64)
     out[9] = np.sum(rec["k"][bad].astype(np.float64))
+    out[11] = np.sum(bad & (rec["cause"] == 1))
+    out[12] = np.sum(bad & (rec["cause"] == 2))
+    steps = rec["steps"][bad].astype(np.float64)
+    out[13] = np.sum(steps - rec["k"][bad].astype(np.float64)) - np.sum(exited)
+    out[14] = np.sum(steps)
     return out
 
 
 def assert_matched_scalars(g_scal, g_rec, o_scal, o_rec, ok, rtol=1e-4):
     """Scalar tallies restricted to trajectory-matched photons: face totals
-    and absorbed weight agree to rtol (FP32 transport against FP64), scatter
-    events exactly (matched photons have the same k)."""
-    gs = np.asarray(g_scal[:10], dtype=np.float64) - unmatched_totals(g_rec, ~ok)
-    os_ = np.asarray(o_scal[:10], dtype=np.float64) - unmatched_totals(o_rec, ~ok)
+    and absorbed weight agree to rtol (FP32 transport against FP64); scatter
+    events, roulette kills, capped photons, reflections and steps exactly
+    (matched photons take the same path)."""
+    gs = np.asarray(g_scal[:15], dtype=np.float64) - unmatched_totals(g_rec, ~ok)
+    os_ = np.asarray(o_scal[:15], dtype=np.float64) - unmatched_totals(o_rec, ~ok)
     for i in list(range(7)):
         assert abs(gs[i] - os_[i]) <= rtol * abs(os_[i]) + 1e-9, (i, gs[i], os_[i])
-    assert gs[9] == os_[9], (gs[9], os_[9])
+    for i in (9, 11, 12, 13, 14):
+        assert gs[i] == os_[i], (i, gs[i], os_[i])

@@ -165,6 +165,7 @@ def test_trajectory_parity_variants(mc, cuda_device, kw):
     o = _oracle(w)
     ok = trajectory_match(g["rec"], oracle_rec(o), box=max(w.size_mm))
     assert ok.mean() >= 0.999, (kw, ok.mean())
+    assert_matched_scalars(g["scalars"], g["rec"], o.scalars, oracle_rec(o), ok)
     assert image_within_3sigma(g["side"], o.side, o.side_w2, w.n_photons, max_w=10.0).all()
     assert image_within_3sigma(g["trans"], o.trans, o.trans_w2, w.n_photons, max_w=10.0).all()
 
