@@ -33,10 +33,11 @@
 // per wave in LDS and handled 64 at a time by the whole wave, so the pixel
 // arithmetic runs with full lanes instead of on the few lanes that exit in
 // any one step.  A flush then either
-//   * appends them to the exit log (MC_EXIT_LOG): each wave owns a fixed set
-//     of chunks in each of 64 key ranges and appends with one LDS add per
-//     exit; a second kernel (log_bin) sums each range in an LDS histogram and
-//     adds the sums into per-XCD copies of the images with plain stores; or
+//   * appends them to the exit log (MC_EXIT_LOG): each block owns a region
+//     of every key range and appends at the position an LDS counter of the
+//     block hands out (one LDS add and one store per exit); a second kernel
+//     (log_bin) sums each range in an LDS histogram and adds the sums into
+//     image copies with plain stores; or
 //   * adds them into a per-block LDS tally cache (direct-mapped pixel ids
 //     claimed with an LDS compare-and-swap) whose sums go to the images once
 //     per block, with a global atomic into one of eight per-XCD copies of the
@@ -46,7 +47,8 @@
 // through one pixel with one weight and are only counted.  A finalize pass
 // sums the copies in integer arithmetic and converts to the caller's images.
 // Scalar tallies use LDS atomics and lane accumulators, flushed once per
-// block.  The kernel is specialised at compile time on the phase function,
+// block; reflections are not counted but derived from the step, event and
+// exit counts when finalizing.  The kernel is specialised at compile time on the phase function,
 // the squared-weight tally, per-photon records, path moments, batching and
 // the exit log.
 #include <hip/hip_runtime.h>
@@ -469,9 +471,9 @@ void walk_kernel(WalkArgs a)
 
     // A lane whose photon has ended keeps its state until the end-of-photon
     // work (tallies, records, the exit queue) and the refill run for several
-    // lanes at once: when at least refill_min lanes are free, or none is still
-    // walking.  Few lanes finish in any one step, so doing that work every
-    // step would run it with most lanes masked off.
+    // lanes at once: when at least refill_min lanes are free (refill_min <= 64,
+    // so also when none is still walking).  Few lanes finish in any one step,
+    // so doing that work every step would run it with most lanes masked off.
     // An ended photon's face is its exit face (0..5) exactly when it left
     // through a wall (cause 0); roulette kills and the step cap leave it -1.
     // A photon that leaves on its first step met a wall before any
