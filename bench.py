@@ -659,11 +659,12 @@ def main():
     # steps pipeline; the HG step needs g on the host and waits for the table.
     inv_cdf = torch.empty(w.n_cdf, dtype=torch.float32, device=dev)
     result = torch.empty(4, dtype=torch.float64, device=dev)
+    table_work = torch.empty(w.n_angles, dtype=torch.float64, device=dev)
     g_hg = mc.mie_table_build(spec, dev).g if phase == W.PHASE_HG else None
 
     def step(i):
         if phase == W.PHASE_MIE:
-            table = mc.mie_table_enqueue(spec, dev, inv_cdf=inv_cdf, result=result)
+            table = mc.mie_table_enqueue(spec, dev, inv_cdf=inv_cdf, result=result, work=table_work)
         else:
             table = mc.mie_table_build(spec, dev)
         _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g_hg, flags=flags,

@@ -133,6 +133,9 @@ typedef struct {
     int32_t coef_capacity; /* terms coef can hold; must be >= n_terms when coef is set */
     double *result;        /* device, 4 doubles: Q_ext, Q_sca, g, n_terms as computed by the kernel
                               (optional for mie_table_build, required for mie_table_enqueue) */
+    double *work;          /* device, n_angles doubles of scratch: P(theta_j) sin(theta_j), passed from the
+                              angle-grid kernel to the CDF kernel (optional for mie_table_build, which then
+                              uses library scratch; required for mie_table_enqueue) */
 } mie_table_t;
 
 /*
@@ -140,17 +143,22 @@ typedef struct {
  * a_n, b_n by the Bohren-Huffman logarithmic-derivative recurrence (Sec. 2.5),
  * Q_ext/Q_sca/g (Eqs. 12-13), S1/S2 (Eqs. 5-6) and the normalised phase
  * function (Eqs. 9-10) on n_angles angles, its CDF in theta, and the inverse
- * table sampled at n_cdf equally spaced probabilities.  All of it runs in one
- * FP64 kernel on `stream`; the call then waits for the stream so the host
- * scalars of `table` are valid on return.  The device buffers of `table`
- * must hold the sizes stated above.  Returns MC_EINVAL on a bad spec or
- * missing buffer, MC_EDEVICE / MC_ENOMEM on runtime failure.
+ * table sampled at n_cdf equally spaced probabilities.  It runs as two FP64
+ * kernels on `stream` (one lane per angle, then one lane per inverse-table
+ * entry); the call then waits for the stream so the host scalars of `table`
+ * are valid on return.  The device buffers of `table` must hold the sizes
+ * stated above; without result or work it uses per-device library scratch,
+ * held under a lock until the call returns.  Returns MC_EINVAL on a bad spec
+ * (also |m| x below 1e-6) or missing buffer, MC_EDEVICE / MC_ENOMEM on
+ * runtime failure.
  */
 int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void *stream);
 
 /*
  * The same table build, enqueued on `stream` without waiting: the device
- * arrays and table->result are written when the stream reaches the kernel.
+ * arrays and table->result are written when the stream reaches the kernels;
+ * table->result and table->work are required, and work must not be shared
+ * with a build running at the same time.
  * On return the host fields x, m_rel_re, m_rel_im, n_terms and n_cdf are
  * set; the efficiencies, g and cross-sections are NaN (read them from
  * table->result).  For pipelines that need the table only on the device.
@@ -163,14 +171,16 @@ int mie_table_enqueue(const mie_spec_t *spec, mie_table_t *table, void *stream);
  * discretised by n_bins-point Gauss-Hermite quadrature in ln d (bins
  * d_k = d_med exp(sqrt(2) sigma_ln t_k), probabilities p_k = W_k / sqrt(pi);
  * mc_lognormal_bins returns them).  Each bin runs the single-size series and
- * phase function of mie_table_build (one workgroup per bin); the table is
- * built from the scattering-weighted mixture
+ * phase function of mie_table_build (one workgroup per bin and slice of 256
+ * angles); the table is built from the scattering-weighted mixture
  *     P(theta) = sum_k p_k C_sca,k P_k(theta) / sum_k p_k C_sca,k
  * (each P_k normalised as Eq. 10, so P is too), with the number-averaged
  * cross-sections sigma = sum_k p_k Q_k pi d_k^2 / 4 (Eq. 14 per bin) and the
  * same mixture of the per-bin asymmetries (Eq. 12).  The table's q_* are
  * those cross-sections over the median's pi d_med^2 / 4, x is the median's
- * size parameter and n_terms the longest bin series; coef must be NULL.
+ * size parameter and n_terms the longest bin series; coef must be NULL and
+ * table->work is not used (poly->work holds the rows, the bins' scalars and
+ * the mixture's angle grid: n_bins * n_angles + 4 n_bins + n_angles doubles).
  * Waits for the stream (like mie_table_build).
  */
 typedef struct {

@@ -43,7 +43,7 @@ class _MieTableC(C.Structure):
                 ("sigma_ext_mm2", C.c_double), ("sigma_sca_mm2", C.c_double), ("sigma_abs_mm2", C.c_double),
                 ("n_terms", C.c_int32), ("n_cdf", C.c_int32),
                 ("inv_cdf", C.c_void_p), ("phase", C.c_void_p), ("cdf", C.c_void_p), ("coef", C.c_void_p),
-                ("coef_capacity", C.c_int32), ("result", C.c_void_p)]
+                ("coef_capacity", C.c_int32), ("result", C.c_void_p), ("work", C.c_void_p)]
 
 
 class MiePoly(C.Structure):
@@ -251,6 +251,7 @@ class MieTable:
     cdf: "object" = None           # torch float64 (n_angles,)
     coef: "object" = None          # torch float64 (n_terms, 4): Re a, Im a, Re b, Im b
     result: "object" = None        # torch float64 (4,): Q_ext, Q_sca, g, n_terms (device)
+    work: "object" = None          # torch float64 (n_angles,): the enqueued build's angle grid (kept alive here)
 
 
 def mie_table_build(spec: MieSpec, device="cuda", *, phase=False, cdf=False, coef=False,
@@ -302,22 +303,27 @@ def mc_lognormal_bins(median_um: float, sigma_ln: float, n_bins: int):
     return list(d)[: int(n_bins)], list(p)[: int(n_bins)]
 
 
-def mie_table_enqueue(spec: MieSpec, device="cuda", *, inv_cdf=None, result=None, stream=None) -> MieTable:
+def mie_table_enqueue(spec: MieSpec, device="cuda", *, inv_cdf=None, result=None, work=None,
+                      stream=None) -> MieTable:
     """Enqueue the table build without waiting (efficiencies and g stay on
-    the device in `result`).  Reuses the given buffers when passed."""
+    the device in `result`).  Reuses the given buffers when passed; `work`
+    (n_angles doubles) carries the angle grid between the two kernels and
+    must not serve two builds in flight at once."""
     import torch
     dev = torch.device(device)
     inv = inv_cdf if inv_cdf is not None else torch.empty(max(int(spec.n_cdf), 1), dtype=torch.float32, device=dev)
     res = result if result is not None else torch.empty(4, dtype=torch.float64, device=dev)
+    wk = work if work is not None else torch.empty(max(int(spec.n_angles), 1), dtype=torch.float64, device=dev)
     _require(inv, "inv_cdf", torch.float32, min_numel=max(int(spec.n_cdf), 1))
     _require(res, "result", torch.float64, min_numel=4)
-    _on_one_gpu(inv_cdf=inv, result=res)
+    _require(wk, "work", torch.float64, min_numel=max(int(spec.n_angles), 1))
+    _on_one_gpu(inv_cdf=inv, result=res, work=wk)
     t = _MieTableC()
-    t.inv_cdf, t.result = _ptr(inv), _ptr(res)
+    t.inv_cdf, t.result, t.work = _ptr(inv), _ptr(res), _ptr(wk)
     with torch.cuda.device(dev):
         _check(lib().mie_table_enqueue(C.byref(spec), C.byref(t), _stream(stream)))
     return MieTable(t.x, complex(t.m_rel_re, t.m_rel_im), t.q_ext, t.q_sca, t.q_abs, t.g, t.sigma_ext_mm2,
-                    t.sigma_sca_mm2, t.sigma_abs_mm2, t.n_terms, inv, result=res)
+                    t.sigma_sca_mm2, t.sigma_abs_mm2, t.n_terms, inv, result=res, work=wk)
 
 
 def mc_medium_coefficients(medium: Medium, geometry: Geometry) -> dict:

@@ -1,21 +1,31 @@
 // Mie phase-function table on the device, FP64 (Sec. 2.2-2.6, Sec. 3.1.2).
 //
-// One workgroup builds one table:
-//   1. the Bohren-Huffman series (Sec. 2.5): one lane runs the logarithmic
-//      derivative D_n(mx) by downward recurrence while a lane of another wave
-//      runs psi_n(x) and chi_n(x) upward; then every lane forms a_n and b_n
-//      for its n (Eqs. 7-8 divided through by psi_n(mx)), and Q_ext (Eq. 13),
-//      Q_sca and the asymmetry sums (Eq. 12) are added in a fixed order;
-//   2. every lane evaluates S1, S2 (Eqs. 5-6) at its share of the angle grid
-//      with the angular functions pi_n, tau_n by upward recurrence (the
-//      per-n divisions done once beforehand), giving the phase function
-//      normalised so that (1/4pi) int P dOmega = 1 (Eqs. 9-10);
-//   3. the trapezoid CDF of P sin(theta) is a chunked in-place block scan;
+// Two kernels build one table:
+//   mie_phase_kernel, one lane per angle, 256-lane workgroups:
+//   1. every workgroup runs the Bohren-Huffman series (Sec. 2.5) for itself:
+//      one lane runs the logarithmic derivative D_n(mx) by downward
+//      recurrence (in homogeneous form, D_n = P_n / Q_n, so the serial chain
+//      holds no division) while a lane of another wave runs psi_n(x) and
+//      chi_n(x) upward; then every lane forms a_n and b_n for its n (Eqs. 7-8
+//      divided through by psi_n(mx)), and Q_ext (Eq. 13), Q_sca and the
+//      asymmetry sums (Eq. 12) are added in a fixed order;
+//   2. each lane evaluates S1, S2 (Eqs. 5-6) at its angle with the angular
+//      functions pi_n, tau_n by upward recurrence (the per-n divisions done
+//      once beforehand), giving the phase function normalised so that
+//      (1/4pi) int P dOmega = 1 (Eqs. 9-10); P sin(theta) goes to a device
+//      buffer of n_angles doubles;
+//   mie_inverse_kernel, one lane per inverse-table entry, 1024-lane groups:
+//   3. every workgroup reads the whole P sin(theta) grid into LDS and forms
+//      its trapezoid CDF by a block scan;
 //   4. each inverse-table entry u_i = i/(N-1) finds the first angle with
 //      F >= u_i by binary search and interpolates theta linearly; the table
 //      stores v = 1 - cos(theta) = 2 sin^2(theta/2) in FP32.
-// All arrays live in LDS (coefficients 32 KB, 1/(n - 1) 8 KB, angle grid
-// 24 KB at the limits; gfx950 gives a workgroup up to 160 KB).
+// The series is short and serial, so repeating it per workgroup costs no
+// time, while the angle grid and the inverse table, which took a single
+// compute unit's FP64 issue, spread over ~8 and ~16 of them.  Arrays live in
+// LDS (coefficients 32 KB, pi_n recurrence coefficients 16 KB, psi and chi
+// 16 KB, angle grid 24 KB at the limits; gfx950 gives a workgroup up to
+// 160 KB).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -27,9 +37,8 @@
 namespace mcmie {
 namespace {
 
-constexpr int kThreads = 1024;     // workgroup size: angles and inverse-table entries spread over all of it
-constexpr int kBlock = 256;        // the CDF scan's partition: lanes 0..255 own kChunk angles each
-constexpr int kChunk = (MC_MAX_N_ANGLES + kBlock - 1) / kBlock;
+constexpr int kPhaseThreads = 256;    // phase kernels: one angle per lane
+constexpr int kInvThreads = 1024;     // CDF and inverse: one entry per lane, 1..3 angles per lane in the scan
 
 struct cplx {
     double re, im;
@@ -53,13 +62,6 @@ __device__ __forceinline__ cplx operator/(cplx a, cplx b)
     return {(a.re * r + a.im) / den, (a.im * r - a.re) / den};
 }
 __device__ __forceinline__ double norm2(cplx a) { return a.re * a.re + a.im * a.im; }
-// 1 / z with one real division (|z|^2 stays far from overflow for the
-// recurrence it serves: |z| <= n / |mx| + |D_n|).
-__device__ __forceinline__ cplx reciprocal(cplx z)
-{
-    const double r = 1.0 / norm2(z);
-    return {z.re * r, -z.im * r};
-}
 
 // sin(t) for |t| <= pi/2 from its Taylor series through t^19/19!, in Horner
 // form in t^2 (truncation below (pi/2)^21/21! < 3e-16): no range reduction is
@@ -96,17 +98,30 @@ struct MieArgs {
     float *inv_cdf;
     double *phase, *cdf, *coef;
     double *result;          // q_ext, q_sca, g, n_terms
+    double *work;            // n_angles: P(theta_j) sin(theta_j), from the phase kernel to the inverse kernel
 };
 
 // Step 1 by the whole workgroup: the series for size parameter x and relative
 // index m.  The two recurrences are serial and run at once on lanes of two
-// different waves: D_n(mx) downward from n_start (into s_a, n = 1..N at index
-// n - 1) and psi_n(x), chi_n(x) upward (into s_psi, s_chi at index n,
-// n = 0..N).  Then each lane forms a_n and b_n for its n (in place of D_n),
+// different waves: D_n(mx) downward from n_start and psi_n(x), chi_n(x)
+// upward (into s_psi, s_chi at index n, n = 0..N).  One downward step
+//     D_{n-1} = n/(mx) - 1/(D_n + n/(mx))
+// is the Moebius map of the matrix [[k, k^2 - 1], [1, k]], k = n/(mx), so it
+// runs on D_n = P_n / Q_n as Q' = P + k Q, P' = k Q' - Q: eight FMAs and no
+// division on the serial chain (one wave runs it, so its instruction count
+// is its time).  One step grows or shrinks max(|P|, |Q|) by at most
+// (1 + |k|)^2, with |k| < 2e9 for every size and index this library accepts
+// (n_start <= ~1100 where |mx| < n_terms, |mx| >= 1e-6), so rescaling (P, Q)
+// by a power of two every 8 steps keeps both far inside the FP64 range; the
+// scale is exact and cancels in P / Q.  Its rounding matches that of the
+// direct form (checked against a 50-digit evaluation of the recurrence).
+// P_n and Q_n go to s_a and s_b (n = 1..N at index n - 1), and each lane
+// forms D_n = P_n / Q_n for its n.  Then each lane forms a_n and b_n (in
+// place of P_n and Q_n),
 // and the sums of Q_ext (Eq. 13), Q_sca and the asymmetry (Eq. 12) are
 // added per lane, per wave and over the waves in a fixed order.  On return
 // (after a barrier) s_sums holds Q_ext, Q_sca and g for every lane.
-__device__ void mie_series_block(double x, double m_re, double m_im, int N, int n_start, cplx *s_a, cplx *s_b,
+__device__ __forceinline__ void mie_series_block(double x, double m_re, double m_im, int N, int n_start, cplx *s_a, cplx *s_b,
                                  double *s_psi, double *s_chi, double *s_red, double *s_sums)
 {
     const int tid = threadIdx.x;
@@ -114,12 +129,25 @@ __device__ void mie_series_block(double x, double m_re, double m_im, int N, int 
     if (tid == 0) {
         const cplx mx = x * m;
         const cplx inv_mx = cplx{1.0, 0.0} / mx;
-        cplx D = {0.0, 0.0};
-        for (int n = n_start; n >= 1; --n) {
-            // D_{n-1} = n/(mx) - 1 / (D_n + n/(mx)); keep D_n for n <= N.
-            if (n <= N) s_a[n - 1] = D;
-            const cplx nmx = (double)n * inv_mx;
-            D = nmx - reciprocal(D + nmx);
+        cplx P = {0.0, 0.0}, Q = {1.0, 0.0};   // D_{n_start} = 0
+        auto step = [&](int n) {
+            const cplx k = (double)n * inv_mx;
+            const cplx Q1 = {fma(k.re, Q.re, fma(-k.im, Q.im, P.re)), fma(k.re, Q.im, fma(k.im, Q.re, P.im))};
+            P = {fma(k.re, Q1.re, fma(-k.im, Q1.im, -Q.re)), fma(k.re, Q1.im, fma(k.im, Q1.re, -Q.im))};
+            Q = Q1;
+            if ((n & 7) == 0) {
+                int e;
+                (void)frexp(fmax(fmax(fabs(P.re), fabs(P.im)), fmax(fabs(Q.re), fabs(Q.im))), &e);
+                P = {ldexp(P.re, -e), ldexp(P.im, -e)};
+                Q = {ldexp(Q.re, -e), ldexp(Q.im, -e)};
+            }
+        };
+        int n = n_start;
+        for (; n > N; --n) step(n);
+        for (; n >= 1; --n) {   // keep D_n = P_n / Q_n for n <= N
+            s_a[n - 1] = P;
+            s_b[n - 1] = Q;
+            step(n);
         }
     } else if (tid == 64) {
         double psi_prev = cos(x), psi = sin(x);        // psi_{-1}, psi_0
@@ -144,7 +172,7 @@ __device__ void mie_series_block(double x, double m_re, double m_im, int N, int 
         const double psi_n = s_psi[n], psi = s_psi[n - 1];
         const cplx xi_n = {psi_n, -s_chi[n]};
         const cplx xi_nm1 = {psi, -s_chi[n - 1]};
-        const cplx Dn = s_a[n - 1];
+        const cplx Dn = s_a[n - 1] / s_b[n - 1];
         const double nx = (double)n / x;
         const cplx da = Dn * inv_m + nx;
         const cplx db = m * Dn + nx;
@@ -196,47 +224,98 @@ __device__ void mie_series_block(double x, double m_re, double m_im, int N, int 
 }
 
 // Before step 2: fold the angular weight (2n + 1)/(n(n + 1)) of Eqs. 5-6 into
-// a_n and b_n (in place) and tabulate 1/(n - 1) for the pi_n recurrence, so
-// the per-angle loop divides nothing.  Ends with a barrier.
-__device__ void prepare_angular(int N, cplx *s_a, cplx *s_b, double *s_rcp)
+// a_n and b_n (in place) and tabulate the coefficients (2n - 1)/(n - 1) and
+// n/(n - 1) of the pi_n recurrence, so the per-angle loop neither divides nor
+// converts n.  Ends with a barrier.
+__device__ void prepare_angular(int N, cplx *s_a, cplx *s_b, double2 *s_pi)
 {
     for (int n = threadIdx.x + 1; n <= N; n += blockDim.x) {
         const double c = (2.0 * n + 1.0) / ((double)n * (n + 1));
         s_a[n - 1] = c * s_a[n - 1];
         s_b[n - 1] = c * s_b[n - 1];
-        s_rcp[n - 1] = n > 1 ? 1.0 / (double)(n - 1) : 0.0;
+        s_pi[n - 1] = n > 1 ? double2{(2.0 * n - 1.0) / (double)(n - 1), (double)n / (double)(n - 1)}
+                            : double2{0.0, 0.0};
     }
     __syncthreads();
 }
 
-// Step 2 at one angle: |S1|^2 + |S2|^2 (Eqs. 5-6) with pi_n, tau_n upward,
-// on the coefficients prepared above.
-__device__ double mie_intensity(double th, int N, const cplx *s_a, const cplx *s_b, const double *s_rcp)
+// Step 2 at one angle: |S1|^2 + |S2|^2 (Eqs. 5-6) with the angular functions
+// upward, pi_n = ((2n - 1) mu pi_{n-1} - n pi_{n-2}) / (n - 1) from pi_0 = 0,
+// pi_1 = 1, and tau_n = n mu pi_n - (n + 1) pi_{n-1}, on the coefficients
+// prepared above.
+__device__ double mie_intensity(double th, int N, const cplx *s_a, const cplx *s_b, const double2 *s_pi)
 {
     const double mu = cos_0_pi(th);
     double pi_prev = 0.0, pi_n = 1.0;              // pi_0, pi_1
-    cplx S1 = {0.0, 0.0}, S2 = {0.0, 0.0};
-    for (int n = 1; n <= N; ++n) {
-        if (n > 1) {
-            const double p = ((2.0 * n - 1.0) * mu * pi_n - (double)n * pi_prev) * s_rcp[n - 1];
-            pi_prev = pi_n;
-            pi_n = p;
-        }
-        const double tau_n = (double)n * mu * pi_n - (double)(n + 1) * pi_prev;
+    // n = 1: tau_1 = mu
+    cplx S1 = pi_n * s_a[0] + mu * s_b[0];
+    cplx S2 = mu * s_a[0] + pi_n * s_b[0];
+    double dn = 1.0;
+    for (int n = 2; n <= N; ++n) {
+        dn += 1.0;
+        const double2 c = s_pi[n - 1];
+        const double p = fma(c.x * mu, pi_n, -c.y * pi_prev);
+        pi_prev = pi_n;
+        pi_n = p;
+        const double tau_n = fma(dn * mu, pi_n, -(dn + 1.0) * pi_prev);
         const cplx an = s_a[n - 1], bn = s_b[n - 1];
-        S1 = S1 + (pi_n * an + tau_n * bn);
-        S2 = S2 + (tau_n * an + pi_n * bn);
+        S1 = {fma(pi_n, an.re, fma(tau_n, bn.re, S1.re)), fma(pi_n, an.im, fma(tau_n, bn.im, S1.im))};
+        S2 = {fma(tau_n, an.re, fma(pi_n, bn.re, S2.re)), fma(tau_n, an.im, fma(pi_n, bn.im, S2.im))};
     }
     return norm2(S1) + norm2(S2);
 }
 
-// Steps 3-4 by the whole workgroup: s_ang holds P sin(theta) on the na-point
-// grid on entry.  Trapezoid CDF by a chunked in-place scan, written back to
-// s_ang (and to cdf_out if given); then each inverse-table entry
-// u_i = i / (nc - 1) finds the first angle with F >= u_i and interpolates
-// theta linearly, storing v = 1 - cos(theta) = 2 sin^2(theta/2).  Each lane
-// takes a run of consecutive entries: it searches the whole grid for the run's
-// first and last entry, and each entry between them only between those two.
+// Step 2 at angle j of the na-point grid: scale x (|S1|^2 + |S2|^2) to
+// phase_out[j] and, times sin(theta_j), to ang[j] (each if given).
+__device__ void phase_at(int j, int na, int N, double scale, const cplx *s_a, const cplx *s_b, const double2 *s_pi,
+                         double *phase_out, double *ang)
+{
+    const double dth = M_PI / (double)(na - 1);
+    const double th = (double)j * dth;
+    const double P = scale * mie_intensity(th, N, s_a, s_b, s_pi);
+    if (phase_out) phase_out[j] = P;
+    if (ang) ang[j] = P * sin_0_pi(th);
+}
+
+// Steps 1-2 for one size: workgroup b runs the series, workgroup 0 writes the
+// scalar results (and the coefficients if asked), and lane t evaluates angle
+// j = 256 b + t into work[j] = P sin(theta_j) (and phase[j] = P if asked).
+__global__ __launch_bounds__(kPhaseThreads) void mie_phase_kernel(MieArgs a)
+{
+    __shared__ cplx s_a[MC_MAX_TERMS];
+    __shared__ cplx s_b[MC_MAX_TERMS];
+    __shared__ double s_rec[2 * (MC_MAX_TERMS + 1)];   // psi_n, chi_n
+    __shared__ double2 s_pi[MC_MAX_TERMS];              // pi_n recurrence coefficients
+    __shared__ double s_red[3 * (kPhaseThreads / 64)];
+    __shared__ double s_sums[3];                       // Q_ext, Q_sca, g
+
+    const int tid = threadIdx.x;
+    const int N = a.n_terms;
+    const double x = a.x;
+    mie_series_block(x, a.m_re, a.m_im, N, a.n_start, s_a, s_b, s_rec, s_rec + MC_MAX_TERMS + 1, s_red, s_sums);
+    if (blockIdx.x == 0) {
+        if (tid == 0) {
+            a.result[0] = s_sums[0];
+            a.result[1] = s_sums[1];
+            a.result[2] = s_sums[2];
+            a.result[3] = (double)N;
+        }
+        if (a.coef) {
+            for (int n = tid; n < N; n += kPhaseThreads) {
+                a.coef[4 * n + 0] = s_a[n].re;
+                a.coef[4 * n + 1] = s_a[n].im;
+                a.coef[4 * n + 2] = s_b[n].re;
+                a.coef[4 * n + 3] = s_b[n].im;
+            }
+        }
+    }
+    __syncthreads();
+    prepare_angular(N, s_a, s_b, s_pi);
+    // Phase function normalised as Eq. 10: P = 2 (|S1|^2 + |S2|^2) / (x^2 Q_sca).
+    const int j = blockIdx.x * kPhaseThreads + tid;
+    if (j < a.n_angles) phase_at(j, a.n_angles, N, 2.0 / (x * x * s_sums[1]), s_a, s_b, s_pi, a.phase, a.work);
+}
+
 __device__ int first_at_least(const double *f, int l, int r, double u)
 {
     while (l < r) {
@@ -247,125 +326,85 @@ __device__ int first_at_least(const double *f, int l, int r, double u)
     return l;
 }
 
-__device__ void cdf_and_inverse(double *s_ang, double *s_part, double *s_total, int na, int nc, float *inv_cdf,
-                                double *cdf_out)
+// Steps 3-4: ang holds P sin(theta) on the na-point grid.  Every workgroup
+// reads it into LDS and forms the trapezoid CDF F_j in place (F = 1 at pi):
+// each lane adds the increments of its run of at most three angles, a
+// shuffle scan within each wave and a scan of the wave totals give every run
+// the sum before it, and each run is then accumulated in order and divided
+// by the total.  Workgroup 0 writes F to cdf_out (if given).  Then lane i of
+// the grid takes inverse-table entry u_i = i / (nc - 1): the first angle with
+// F >= u_i by binary search, theta interpolated linearly in F, and
+// v = 1 - cos(theta) = 2 sin^2(theta/2) stored in FP32.
+__global__ __launch_bounds__(kInvThreads) void mie_inverse_kernel(const double *ang, int na, int nc, float *inv_cdf,
+                                                                  double *cdf_out)
 {
-    const int tid = threadIdx.x;
+    __shared__ double s_ang[MC_MAX_N_ANGLES];
+    __shared__ double s_wave[kInvThreads / 64];
+    __shared__ double s_total;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int j = tid; j < na; j += kInvThreads) s_ang[j] = ang[j];
+    __syncthreads();
+
     const double dth = M_PI / (double)(na - 1);
-    const int lo = tid * kChunk;
-    const int hi = min(lo + kChunk, na);
-    double f_left = (lo >= 1 && lo < na) ? s_ang[lo - 1] : 0.0;
+    const int per = (na + kInvThreads - 1) / kInvThreads;
+    const int lo = min(tid * per, na), hi = min(lo + per, na);
+    const double f_left = lo >= 1 && lo < na ? s_ang[lo - 1] : 0.0;
     double local = 0.0;
     for (int j = max(lo, 1); j < hi; ++j) {
         const double th_j = (double)j * dth, th_p = (double)(j - 1) * dth;
         local += 0.5 * (th_j - th_p) * (s_ang[j - 1] + s_ang[j]);
     }
-    if (tid < kBlock) s_part[tid] = local;   // lanes past the partition own no angles
+    double incl = local;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    double excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = 0.0;
+    if (lane == 63) s_wave[wave] = incl;
     __syncthreads();
-    if (tid == 0) {   // exclusive scan of the per-lane sums (256 adds)
+    if (tid == 0) {   // exclusive scan of the wave totals
         double run = 0.0;
-        for (int t = 0; t < kBlock; ++t) {
-            const double v = s_part[t];
-            s_part[t] = run;
+        for (int w = 0; w < kInvThreads / 64; ++w) {
+            const double v = s_wave[w];
+            s_wave[w] = run;
             run += v;
         }
-        *s_total = run;
+        s_total = run;
     }
     __syncthreads();
-    if (tid < kBlock) {
-        double acc = s_part[tid];
-        const double total = *s_total;
-        double prev = f_left;
-        for (int j = lo; j < hi; ++j) {
-            const double f = s_ang[j];
-            if (j >= 1) {
-                const double th_j = (double)j * dth, th_p = (double)(j - 1) * dth;
-                acc += 0.5 * (th_j - th_p) * (prev + f);
-            }
-            prev = f;
-            s_ang[j] = (j == na - 1) ? 1.0 : acc / total;
-        }
-    }
-    __syncthreads();
-    if (cdf_out)
-        for (int j = tid; j < na; j += kThreads) cdf_out[j] = s_ang[j];
-    const int per = (nc + kThreads - 1) / kThreads;
-    const int i0 = tid * per, i1 = min(i0 + per, nc);
-    if (i0 >= i1) return;
-    // u <= 1 = F at pi, so only rounding could leave an entry past the grid.
-    const int l_first = min(first_at_least(s_ang, 0, na, (double)i0 / (double)(nc - 1)), na - 1);
-    const int l_last = min(first_at_least(s_ang, l_first, na, (double)(i1 - 1) / (double)(nc - 1)), na - 1);
-    for (int i = i0; i < i1; ++i) {
-        const double u = (double)i / (double)(nc - 1);
-        const int l = i == i0 ? l_first : (i == i1 - 1 ? l_last : first_at_least(s_ang, l_first, l_last, u));
-        double th = 0.0;
-        if (l > 0) {
-            const int j = l;
+    double acc = s_wave[wave] + excl;
+    const double total = s_total;
+    double prev = f_left;
+    for (int j = lo; j < hi; ++j) {
+        const double f = s_ang[j];
+        if (j >= 1) {
             const double th_j = (double)j * dth, th_p = (double)(j - 1) * dth;
-            th = th_p + (u - s_ang[j - 1]) / (s_ang[j] - s_ang[j - 1]) * (th_j - th_p);
+            acc += 0.5 * (th_j - th_p) * (prev + f);
         }
-        const double sh = sin_half_pi(0.5 * th);
-        inv_cdf[i] = (float)(2.0 * sh * sh);
-    }
-}
-
-// Step 2 over the grid by the whole workgroup: scale x (|S1|^2 + |S2|^2) into
-// phase_out (if given) and, times sin(theta), into s_ang (if given).
-__device__ void phase_grid(int na, int N, double scale, const cplx *s_a, const cplx *s_b, const double *s_rcp,
-                           double *phase_out, double *s_ang)
-{
-    const double dth = M_PI / (double)(na - 1);
-    for (int j = threadIdx.x; j < na; j += blockDim.x) {
-        const double th = (double)j * dth;
-        const double P = scale * mie_intensity(th, N, s_a, s_b, s_rcp);
-        if (phase_out) phase_out[j] = P;
-        if (s_ang) s_ang[j] = P * sin_0_pi(th);
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void mie_table_kernel(MieArgs a)
-{
-    __shared__ cplx s_a[MC_MAX_TERMS];
-    __shared__ cplx s_b[MC_MAX_TERMS];
-    __shared__ double s_ang[MC_MAX_N_ANGLES];
-    __shared__ double s_rcp[MC_MAX_TERMS];
-    __shared__ double s_part[kBlock];
-    __shared__ double s_red[3 * (kThreads / 64)];
-    __shared__ double s_sums[4];              // Q_ext, Q_sca, g; the CDF's total
-
-    const int tid = threadIdx.x;
-    const int N = a.n_terms;
-    const double x = a.x;
-
-    // ---- 1. series; psi_n and chi_n borrow the angle grid's LDS ----------
-    mie_series_block(x, a.m_re, a.m_im, N, a.n_start, s_a, s_b, s_ang, s_ang + MC_MAX_TERMS + 1, s_red, s_sums);
-    if (tid == 0) {
-        a.result[0] = s_sums[0];
-        a.result[1] = s_sums[1];
-        a.result[2] = s_sums[2];
-        a.result[3] = (double)N;
-    }
-    if (a.coef) {
-        for (int n = tid; n < N; n += kThreads) {
-            a.coef[4 * n + 0] = s_a[n].re;
-            a.coef[4 * n + 1] = s_a[n].im;
-            a.coef[4 * n + 2] = s_b[n].re;
-            a.coef[4 * n + 3] = s_b[n].im;
-        }
+        prev = f;
+        s_ang[j] = (j == na - 1) ? 1.0 : acc / total;
     }
     __syncthreads();
-    prepare_angular(N, s_a, s_b, s_rcp);
+    if (cdf_out && blockIdx.x == 0)
+        for (int j = tid; j < na; j += kInvThreads) cdf_out[j] = s_ang[j];
 
-    // ---- 2. phase function on the angle grid, normalised (Eq. 10) -----
-    const double pnorm = 2.0 / (x * x * s_sums[1]);
-    phase_grid(a.n_angles, N, pnorm, s_a, s_b, s_rcp, a.phase, s_ang);
-    __syncthreads();
-
-    // ---- 3-4. CDF and inverse table ----------------------------------------
-    cdf_and_inverse(s_ang, s_part, &s_sums[3], a.n_angles, a.n_cdf, a.inv_cdf, a.cdf);
+    const int i = blockIdx.x * kInvThreads + tid;
+    if (i >= nc) return;
+    const double u = (double)i / (double)(nc - 1);
+    // u <= 1 = F at pi, so only rounding could leave an entry past the grid.
+    const int l = min(first_at_least(s_ang, 0, na, u), na - 1);
+    double th = 0.0;
+    if (l > 0) {
+        const double th_j = (double)l * dth, th_p = (double)(l - 1) * dth;
+        th = th_p + (u - s_ang[l - 1]) / (s_ang[l] - s_ang[l - 1]) * (th_j - th_p);
+    }
+    const double sh = sin_half_pi(0.5 * th);
+    inv_cdf[i] = (float)(2.0 * sh * sh);
 }
 
-// ---- polydisperse: one workgroup per size bin, then the mixture ----------
+// ---- polydisperse: the bins, the mixture, then the same inverse ----------
 
 struct PolyArgs {
     double x[MC_MAX_BINS];         // size parameter of each bin
@@ -376,71 +415,91 @@ struct PolyArgs {
     double geo_median;             // geometric cross-section of the median diameter (mm^2)
     double *rows;                  // n_bins x n_angles: c_k Q_sca,k P_k(theta_j)
     double *bins;                  // n_bins x 4: Q_ext,k, Q_sca,k, g_k, N_k
-    float *inv_cdf;
-    double *phase, *cdf;
+    double *ang;                   // n_angles: P(theta_j) sin(theta_j) of the mixture
+    double *phase;
     double *result;                // q_ext, q_sca (over geo_median), g, max N
 };
 
-__global__ __launch_bounds__(kThreads) void mie_bin_kernel(PolyArgs a)
+// Workgroup (s, k) runs bin k's series (workgroup (0, k) writes its scalars to
+// bins) and its lanes evaluate row k at the 256 angles of slice s.
+__global__ __launch_bounds__(kPhaseThreads) void mie_bin_kernel(PolyArgs a)
 {
     __shared__ cplx s_a[MC_MAX_TERMS];
     __shared__ cplx s_b[MC_MAX_TERMS];
     __shared__ double s_rec[2 * (MC_MAX_TERMS + 1)];   // psi_n, chi_n
-    __shared__ double s_rcp[MC_MAX_TERMS];
-    __shared__ double s_red[3 * (kThreads / 64)];
+    __shared__ double2 s_pi[MC_MAX_TERMS];              // pi_n recurrence coefficients
+    __shared__ double s_red[3 * (kPhaseThreads / 64)];
     __shared__ double s_sums[3];
-    const int k = blockIdx.x, tid = threadIdx.x;
+    const int k = blockIdx.y, tid = threadIdx.x;
     const double x = a.x[k];
     const int N = a.n_terms[k];
     mie_series_block(x, a.m_re, a.m_im, N, a.n_start[k], s_a, s_b, s_rec, s_rec + MC_MAX_TERMS + 1, s_red, s_sums);
-    if (tid == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         a.bins[4 * k + 0] = s_sums[0];
         a.bins[4 * k + 1] = s_sums[1];
         a.bins[4 * k + 2] = s_sums[2];
         a.bins[4 * k + 3] = (double)N;
     }
-    prepare_angular(N, s_a, s_b, s_rcp);
+    prepare_angular(N, s_a, s_b, s_pi);
     // c_k Q_sca,k P_k with P_k = 2 (|S1|^2 + |S2|^2) / (x^2 Q_sca,k): the Q_sca,k cancel.
-    phase_grid(a.n_angles, N, a.c[k] * 2.0 / (x * x), s_a, s_b, s_rcp, a.rows + (uint64_t)k * a.n_angles, nullptr);
+    const int j = blockIdx.x * kPhaseThreads + tid;
+    if (j < a.n_angles)
+        phase_at(j, a.n_angles, N, a.c[k] * 2.0 / (x * x), s_a, s_b, s_pi, a.rows + (uint64_t)k * a.n_angles,
+                 nullptr);
 }
 
-__global__ __launch_bounds__(kThreads) void mie_mix_kernel(PolyArgs a)
+// Lane t of workgroup b mixes the rows at angle j = 256 b + t into ang[j]
+// (and phase[j]); every workgroup sums the bins' cross-sections itself, in
+// bin order, and workgroup 0 writes the scalar results.
+__global__ __launch_bounds__(kPhaseThreads) void mie_mix_kernel(PolyArgs a)
 {
-    __shared__ double s_ang[MC_MAX_N_ANGLES];
-    __shared__ double s_part[kBlock];
     __shared__ double s_sca;
     const int tid = threadIdx.x;
     if (tid == 0) {
         // Number-averaged cross-sections and the C_sca-weighted asymmetry, in bin order.
         double ext = 0.0, sca = 0.0, gs = 0.0, nmax = 0.0;
+#pragma unroll 8
         for (int k = 0; k < a.n_bins; ++k) {
-            ext += a.c[k] * a.bins[4 * k + 0];
-            sca += a.c[k] * a.bins[4 * k + 1];
-            gs += a.c[k] * a.bins[4 * k + 1] * a.bins[4 * k + 2];
-            nmax = fmax(nmax, a.bins[4 * k + 3]);
+            const double q_ext = a.bins[4 * k + 0], q_sca = a.bins[4 * k + 1];
+            const double g = a.bins[4 * k + 2], n = a.bins[4 * k + 3];
+            ext += a.c[k] * q_ext;
+            sca += a.c[k] * q_sca;
+            gs += a.c[k] * q_sca * g;
+            nmax = fmax(nmax, n);
         }
         s_sca = sca;
-        a.result[0] = ext / a.geo_median;
-        a.result[1] = sca / a.geo_median;
-        a.result[2] = gs / sca;
-        a.result[3] = nmax;
+        if (blockIdx.x == 0) {
+            a.result[0] = ext / a.geo_median;
+            a.result[1] = sca / a.geo_median;
+            a.result[2] = gs / sca;
+            a.result[3] = nmax;
+        }
     }
     __syncthreads();
     const int na = a.n_angles;
+    const int j = blockIdx.x * kPhaseThreads + tid;
+    if (j >= na) return;
     const double dth = M_PI / (double)(na - 1);
-    const double inv_sca = 1.0 / s_sca;
-    for (int j = tid; j < na; j += kThreads) {
-        double mix = 0.0;
-        for (int k = 0; k < a.n_bins; ++k) mix += a.rows[(uint64_t)k * na + j];
-        const double P = mix * inv_sca;
-        if (a.phase) a.phase[j] = P;
-        s_ang[j] = P * sin_0_pi((double)j * dth);
+    // The rows added in bin order, their loads issued eight at a time.
+    double mix = 0.0;
+    int k = 0;
+    for (; k + 8 <= a.n_bins; k += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = a.rows[(uint64_t)(k + u) * na + j];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mix += v[u];
     }
-    __syncthreads();
-    cdf_and_inverse(s_ang, s_part, &s_sca, na, a.n_cdf, a.inv_cdf, a.cdf);
+    for (; k < a.n_bins; ++k) mix += a.rows[(uint64_t)k * na + j];
+    const double P = mix * (1.0 / s_sca);
+    if (a.phase) a.phase[j] = P;
+    a.ang[j] = P * sin_0_pi((double)j * dth);
 }
 
-// Per-device scratch for the four scalar results (allocated once, kept).
+// Per-device scratch for the scalar results (8 doubles) and the angle grid
+// (MC_MAX_N_ANGLES doubles) of synchronous builds whose caller passes none
+// (allocated once per device, kept until the process ends).
+constexpr size_t kScratchDoubles = 8 + MC_MAX_N_ANGLES;
 std::mutex g_scratch_mu;
 double *g_scratch[64] = {nullptr};
 
@@ -465,6 +524,7 @@ int prepare_table(const mie_spec_t *spec, const mie_table_t *table, MieArgs *arg
     const double m_re = s.m_re / s.n_medium, m_im = s.m_im / s.n_medium;
     const double mx_abs = x * std::hypot(m_re, m_im);
     if (!(x >= 1e-6)) return fail(MC_EINVAL, "%s: size parameter %g below 1e-6", who, x);
+    if (!(mx_abs >= 1e-6)) return fail(MC_EINVAL, "%s: |m| x = %g below 1e-6", who, mx_abs);
     const int n_terms = (int)std::lround(x + 4.0 * std::cbrt(x) + 2.0);   // Wiscombe 1980
     if (n_terms > MC_MAX_TERMS)
         return fail(MC_EINVAL, "%s: %d series terms exceed %d (x = %g)", who, n_terms, MC_MAX_TERMS, x);
@@ -476,15 +536,21 @@ int prepare_table(const mie_spec_t *spec, const mie_table_t *table, MieArgs *arg
                         (int)std::ceil(8.0 * std::cbrt(mx_abs));
 
     *args = MieArgs{x, m_re, m_im, n_terms, n_start, s.n_angles, s.n_cdf,
-                    table->inv_cdf, table->phase, table->cdf, table->coef, nullptr};
+                    table->inv_cdf, table->phase, table->cdf, table->coef, nullptr, nullptr};
     return MC_OK;
 }
 
-// Launch the prepared table kernel on `st`, results to `result` (device).
-int launch_table(MieArgs args, mie_table_t *table, hipStream_t st, double *result)
+// Launch the prepared table kernels on `st`: scalar results to `result`,
+// the angle grid through `work` (both device).
+int launch_table(MieArgs args, mie_table_t *table, hipStream_t st, double *result, double *work)
 {
     args.result = result;
-    hipLaunchKernelGGL(mie_table_kernel, dim3(1), dim3(kThreads), 0, st, args);
+    args.work = work;
+    const int g_phase = (args.n_angles + kPhaseThreads - 1) / kPhaseThreads;
+    const int g_inv = (args.n_cdf + kInvThreads - 1) / kInvThreads;
+    hipLaunchKernelGGL(mie_phase_kernel, dim3(g_phase), dim3(kPhaseThreads), 0, st, args);
+    hipLaunchKernelGGL(mie_inverse_kernel, dim3(g_inv), dim3(kInvThreads), 0, st, (const double *)work, args.n_angles,
+                       args.n_cdf, args.inv_cdf, args.cdf);
     MC_HIP_CHECK(hipGetLastError());
     table->x = args.x;
     table->m_rel_re = args.m_re;
@@ -506,22 +572,27 @@ void set_scalars(mie_table_t *table, const mie_spec_t &s, const double res[3])
     table->sigma_abs_mm2 = (res[0] - res[1]) * geo_mm2;
 }
 
-// The caller's result buffer, or the library's per-device scratch (then
-// `lock` holds the scratch until the results are back on the host).
-int result_buffer(mie_table_t *table, std::unique_lock<std::mutex> &lock, double **out, const char *who)
+// The caller's result buffer and (if `work` is not null) angle-grid buffer,
+// or for each one missing the library's per-device scratch (then `lock`
+// holds the scratch until the results are back on the host).
+int scratch_buffers(const mie_table_t *table, std::unique_lock<std::mutex> &lock, double **result, double **work,
+                    const char *who)
 {
-    *out = table->result;
-    if (*out) return MC_OK;
+    *result = table->result;
+    if (work) *work = table->work;
+    if (*result && (!work || *work)) return MC_OK;
     int dev = 0;
     MC_HIP_CHECK(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return fail(MC_EDEVICE, "device index %d out of range", dev);
     lock.lock();
     if (!g_scratch[dev]) {
         void *p = nullptr;
-        if (hipMalloc(&p, 8 * sizeof(double)) != hipSuccess) return fail(MC_ENOMEM, "%s: scratch allocation failed", who);
+        if (hipMalloc(&p, kScratchDoubles * sizeof(double)) != hipSuccess)
+            return fail(MC_ENOMEM, "%s: scratch allocation failed", who);
         g_scratch[dev] = (double *)p;
     }
-    *out = g_scratch[dev];
+    if (!*result) *result = g_scratch[dev];
+    if (work && !*work) *work = g_scratch[dev] + 8;
     return MC_OK;
 }
 
@@ -616,7 +687,7 @@ int lognormal_bins(double median_um, double sigma_ln, int n, double *d, double *
     return MC_OK;
 }
 
-uint64_t poly_work_words(int n_angles, int n_bins) { return (uint64_t)n_bins * n_angles + 4ull * n_bins; }
+uint64_t poly_work_words(int n_angles, int n_bins) { return (uint64_t)n_bins * n_angles + 4ull * n_bins + n_angles; }
 
 }  // namespace
 }  // namespace mcmie
@@ -675,14 +746,16 @@ extern "C" int mie_table_build_poly(const mie_spec_t *spec, const mie_poly_t *po
     a.geo_median = M_PI * (s.diameter_um * 1e-3) * (s.diameter_um * 1e-3) / 4.0;
     a.rows = q.work;
     a.bins = q.work + (uint64_t)q.n_bins * s.n_angles;
-    a.inv_cdf = table->inv_cdf;
+    a.ang = a.bins + 4ull * q.n_bins;
     a.phase = table->phase;
-    a.cdf = table->cdf;
     std::unique_lock<std::mutex> lock(g_scratch_mu, std::defer_lock);
-    if (int rc = result_buffer(table, lock, &a.result, who)) return rc;
+    if (int rc = scratch_buffers(table, lock, &a.result, nullptr, who)) return rc;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(mie_bin_kernel, dim3(q.n_bins), dim3(kThreads), 0, st, a);
-    hipLaunchKernelGGL(mie_mix_kernel, dim3(1), dim3(kThreads), 0, st, a);
+    const int slices = (s.n_angles + kPhaseThreads - 1) / kPhaseThreads;
+    hipLaunchKernelGGL(mie_bin_kernel, dim3(slices, q.n_bins), dim3(kPhaseThreads), 0, st, a);
+    hipLaunchKernelGGL(mie_mix_kernel, dim3(slices), dim3(kPhaseThreads), 0, st, a);
+    hipLaunchKernelGGL(mie_inverse_kernel, dim3((s.n_cdf + kInvThreads - 1) / kInvThreads), dim3(kInvThreads), 0, st,
+                       (const double *)a.ang, s.n_angles, s.n_cdf, table->inv_cdf, table->cdf);
     MC_HIP_CHECK(hipGetLastError());
     double res[4];
     MC_HIP_CHECK(hipMemcpyAsync(res, a.result, sizeof res, hipMemcpyDeviceToHost, st));
@@ -703,10 +776,10 @@ extern "C" int mie_table_build(const mie_spec_t *spec, mie_table_t *table, void 
     hipStream_t st = (hipStream_t)stream;
     MieArgs args;
     if (int rc = prepare_table(spec, table, &args, "mie_table_build")) return rc;
-    double *result = nullptr;
+    double *result = nullptr, *work = nullptr;
     std::unique_lock<std::mutex> lock(g_scratch_mu, std::defer_lock);
-    if (int rc = result_buffer(table, lock, &result, "mie_table_build")) return rc;
-    if (int rc = launch_table(args, table, st, result)) return rc;
+    if (int rc = scratch_buffers(table, lock, &result, &work, "mie_table_build")) return rc;
+    if (int rc = launch_table(args, table, st, result, work)) return rc;
     double res[4];
     MC_HIP_CHECK(hipMemcpyAsync(res, result, sizeof res, hipMemcpyDeviceToHost, st));
     MC_HIP_CHECK(hipStreamSynchronize(st));
@@ -721,7 +794,8 @@ extern "C" int mie_table_enqueue(const mie_spec_t *spec, mie_table_t *table, voi
     MieArgs args;
     if (int rc = prepare_table(spec, table, &args, "mie_table_enqueue")) return rc;
     if (!table->result) return fail(MC_EINVAL, "mie_table_enqueue: result buffer is required");
-    if (int rc = launch_table(args, table, (hipStream_t)stream, table->result)) return rc;
+    if (!table->work) return fail(MC_EINVAL, "mie_table_enqueue: work buffer (n_angles doubles) is required");
+    if (int rc = launch_table(args, table, (hipStream_t)stream, table->result, table->work)) return rc;
     const double nan3[3] = {NAN, NAN, NAN};
     set_scalars(table, *spec, nan3);
     return MC_OK;

@@ -189,6 +189,7 @@ def test_mc_simulate_requires_tally_buffers():
 @pytest.mark.parametrize("field,value", [
     ("n_medium", 0.0), ("m_re", -1.0), ("m_im", -0.1), ("diameter_um", 0.0), ("wavelength_nm", float("nan")),
     ("n_angles", 2), ("n_angles", 3002), ("n_cdf", 1), ("n_cdf", 16385), ("diameter_um", 500.0),
+    ("m_re", 1e-9),
 ])
 def test_mie_table_build_rejects_invalid_spec(field, value):
     import paper_2507_23189_amd as mc
@@ -202,14 +203,18 @@ def test_mie_table_build_rejects_invalid_spec(field, value):
     assert mc.lib().mc_last_error().startswith(b"mie_table_build")
 
 
-def test_mie_table_enqueue_requires_result_buffer():
+def test_mie_table_enqueue_requires_result_and_work_buffers():
     import paper_2507_23189_amd as mc
     _lib_path()
     spec, *_ = _valid_args()
     t = mc._capi._MieTableC()
     t.inv_cdf = 0x1000
+    t.work = 0x2000
     assert mc.lib().mie_table_enqueue(C.byref(spec), C.byref(t), None) == mc.MC_EINVAL
     assert b"result" in mc.lib().mc_last_error()
+    t.result, t.work = 0x3000, None
+    assert mc.lib().mie_table_enqueue(C.byref(spec), C.byref(t), None) == mc.MC_EINVAL
+    assert b"work" in mc.lib().mc_last_error()
 
 
 def test_mc_grad_validates():
@@ -363,11 +368,11 @@ def test_host_lognormal_bins_and_poly_table_validate():
     spec = mc.MieSpec(n_medium=1.33, m_re=1.59, m_im=0.0, diameter_um=5.0, wavelength_nm=532.0,
                       n_angles=1801, n_cdf=4096)
     q = mc.MiePoly(sigma_ln=0.05, n_bins=64)
-    assert L.mie_poly_work_bytes(C.byref(spec), C.byref(q)) == 8 * (64 * 1801 + 4 * 64)
+    assert L.mie_poly_work_bytes(C.byref(spec), C.byref(q)) == 8 * (64 * 1801 + 4 * 64 + 1801)
     t = mc._capi._MieTableC()
     t.inv_cdf = 0x1000
     assert L.mie_table_build_poly(C.byref(spec), None, C.byref(t), None) == mc.MC_EINVAL
-    q.work, q.work_bytes = 0x1000, 8 * (64 * 1801 + 4 * 64) - 8
+    q.work, q.work_bytes = 0x1000, 8 * (64 * 1801 + 4 * 64 + 1801) - 8
     assert L.mie_table_build_poly(C.byref(spec), C.byref(q), C.byref(t), None) == mc.MC_EINVAL
     assert b"work" in L.mc_last_error()
     q.work_bytes += 8
@@ -518,21 +523,26 @@ def test_mc_simulate_refuses_bad_tally(monkeypatch, case):
     assert ("GPU" in str(e.value)) == (case == "cpu"), e.value
 
 
-@pytest.mark.parametrize("case", ["inv_short", "inv_dtype", "result_short", "cpu"])
+@pytest.mark.parametrize("case", ["inv_short", "inv_dtype", "result_short", "work_short", "work_dtype", "cpu"])
 def test_mie_table_enqueue_refuses_bad_buffers(monkeypatch, case):
     import torch
     cap = _no_library(monkeypatch)
     spec = _valid_args()[0]
     inv = torch.zeros(spec.n_cdf, dtype=torch.float32)
     res = torch.zeros(4, dtype=torch.float64)
+    work = torch.zeros(spec.n_angles, dtype=torch.float64)
     if case == "inv_short":
         inv = inv[:-1]
     elif case == "inv_dtype":
         inv = inv.double()
     elif case == "result_short":
         res = res[:3]
+    elif case == "work_short":
+        work = work[:-1]
+    elif case == "work_dtype":
+        work = work.float()
     with pytest.raises(ValueError) as e:
-        cap.mie_table_enqueue(spec, "cpu", inv_cdf=inv, result=res)
+        cap.mie_table_enqueue(spec, "cpu", inv_cdf=inv, result=res, work=work)
     assert ("GPU" in str(e.value)) == (case == "cpu"), e.value
 
 
