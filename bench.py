@@ -142,8 +142,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # WRITE_SIZE x 1.0); valid only for the tally path and kernel code it was
 # measured on (profiles/walk_tau4_counters.md): the digest covers the walk
 # sources without comments and whitespace, so a comment edit keeps it.
-TRAFFIC = {"tally": "log", "sources_sha256": "9792409312952a491eb82cdeda36fc8d6776c77f10daced64f986eb1e8981d72",
-           "fetch_kib": 372.2, "write_kib": 540520.0, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"tally": "log", "sources_sha256": "8cc2a0c0d8bf9b4ea5fc6268d560e3d23ed82aaa1ddcc989f420fa3895a80360",
+           "fetch_kib": 376.4, "write_kib": 558203.7, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 

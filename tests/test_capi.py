@@ -125,7 +125,8 @@ def test_exit_log_sizes_and_checks():
     """MC_EXIT_LOG: the workspace words are unchanged and the log comes on
     top: a 4-byte count per region (64 ranges x 512 blocks of a full
     launch) and per region 1.5 times a block's share of photons in a range
-    plus 64 entries of 8 bytes.  Ranges hold at most 8192 keys where the LDS
+    plus 64 entries of 8 bytes, rounded up to a multiple of 256 entries from
+    1024 up (else of 64).  Ranges hold at most 8192 keys where the LDS
     allows: 64 of them for up to 2^19 keys, 256 at most beside a Mie table
     (single medium), 4096 at most in a batch.  The flag is refused with
     records."""
@@ -138,6 +139,8 @@ def test_exit_log_sizes_and_checks():
     assert mc.mc_workspace_bytes(det) == base
     def log_bytes(n, regions):
         cap = -(-(n + n // 2) // regions) + 64
+        granule = 256 if cap >= 1024 else 64
+        cap = -(-cap // granule) * granule
         return regions * 4 + regions * cap * 8
     regions = 64 * 512
     for n in (0, 1, 10**6, 10**8, 10**9):
