@@ -879,8 +879,8 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
 }
 
 // Sum the exit log into the image copies.  Block (range b, part p, copy s)
-// takes the regions of range b that the s-th of n_copies equal shares of the
-// walk's blocks wrote (log_count entries each), adds the fixed-point weights (and
+// takes the regions of range b that every n_copies-th of the walk's blocks,
+// from block s, wrote (log_count entries each), adds the fixed-point weights (and
 // squared weights) of the entries whose index within the range lies in part
 // p into an LDS histogram of 2^kLogHistBits sums, then adds the non-zero sums
 // into copy s.  Those keys of copy s have no other writer (the walk's
@@ -903,12 +903,16 @@ __global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, c
         if (SIGMA) s_hist2[i] = 0ull;
     }
     __syncthreads();
-    const uint32_t g0 = (uint32_t)((uint64_t)walk_blocks * s / n_copies);
-    const uint32_t g1 = (uint32_t)((uint64_t)walk_blocks * (s + 1) / n_copies);
     const uint32_t lane = threadIdx.x & 63u, waves = blockDim.x >> 6;
     constexpr uint32_t U = 4;   // entries in flight per lane
-    // Each wave takes every waves-th region and reads its entries U x 64 at a time.
-    for (uint32_t g = g0 + (threadIdx.x >> 6); g < g1; g += waves) {
+    // Copy s takes the walk's blocks s, s + n_copies, s + 2 n_copies, ...:
+    // the walk's blocks log very unequal numbers of exits (work is claimed
+    // per wave, and the older workgroup on a compute unit wins most issue
+    // cycles: at the headline the first 256 of 512 blocks log four times as
+    // many as the rest), so contiguous shares would load some copies 1.6
+    // times the mean.  Each wave takes every waves-th of them and reads its
+    // entries U x 64 at a time.
+    for (uint32_t g = s + n_copies * (threadIdx.x >> 6); g < walk_blocks; g += n_copies * waves) {
         const uint64_t region = (uint64_t)b * walk_blocks + g;
         const uint32_t n = count[region];
         const unsigned long long *ent = log + region * cap;
