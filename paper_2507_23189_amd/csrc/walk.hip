@@ -982,20 +982,26 @@ __global__ __launch_bounds__(256) void finalize_images(const unsigned long long 
         face_trans += inst * face_stride;
     }
     unsigned long long sum_side = 0ull, sum_trans = 0ull;
+    const unsigned long long beam_key = ws_scal[kWsBeamKey];
+    const unsigned long long beam_v = ws_scal[inst * kWsScalarWords + kWsBallistic] * ball_w;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pix;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        unsigned long long v = 0ull;
-        for (int c = 0; c < n_copies; ++c) v += copies[(uint64_t)c * n_total + key0 + i];
-        if (ws_scal[kWsBeamKey] == i + 1) v += ws_scal[inst * kWsScalarWords + kWsBallistic] * ball_w;
+        // All copies' loads (and the output's) are issued before any is used.
+        unsigned long long part[kCopies];
+#pragma unroll
+        for (int c = 0; c < kCopies; ++c) part[c] = c < n_copies ? copies[(uint64_t)c * n_total + key0 + i] : 0ull;
         const bool is_side = i < n_side;
         const uint64_t j = is_side ? i : i - n_side;
-        if (FIX) {
-            long long *out = (long long *)(is_side ? side : trans);
-            out[j] += (long long)v;
-        } else {
-            double *out = (double *)(is_side ? side : trans);
-            out[j] += (double)(long long)v * (1.0 / kFix);
-        }
+        long long *out_fix = (long long *)(is_side ? side : trans);
+        double *out_dbl = (double *)(is_side ? side : trans);
+        const long long prev_fix = FIX ? out_fix[j] : 0ll;
+        const double prev_dbl = FIX ? 0.0 : out_dbl[j];
+        unsigned long long v = 0ull;
+#pragma unroll
+        for (int c = 0; c < kCopies; ++c) v += part[c];
+        if (beam_key == i + 1) v += beam_v;
+        if (FIX) out_fix[j] = prev_fix + (long long)v;
+        else out_dbl[j] = prev_dbl + (double)(long long)v * (1.0 / kFix);
         if (is_side) sum_side += v; else sum_trans += v;
     }
     if (face_side) {
