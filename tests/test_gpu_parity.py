@@ -61,6 +61,11 @@ TABLE_CASES = [
     dict(d=10.0, m_re=1.59, m_im=0.0, n_med=1.33, lam=532.0, na=1801, nc=2),        # x ~ 78.5, smallest table
     dict(d=0.02, m_re=1.5, m_im=0.1, n_med=1.0, lam=532.0, na=3, nc=5),             # Rayleigh, smallest grid
     dict(d=120.0, m_re=1.59, m_im=0.0, n_med=1.33, lam=532.0, na=3001, nc=16384),   # x ~ 942: 984 of the 1024 terms
+    # |m| x ~ 1.6e-5: the downward D_n steps have |k| = n / |mx| up to 1.3e6, so the
+    # homogeneous recurrence's power-of-two rescaling is what keeps P_n, Q_n finite.
+    dict(d=0.02, m_re=1.33e-4, m_im=0.0, n_med=1.33, lam=532.0, na=181, nc=64),
+    dict(d=0.05, m_re=2e-3, m_im=1e-3, n_med=1.0, lam=532.0, na=181, nc=64),     # absorbing, |m| x ~ 6.6e-4
+    dict(d=2.0, m_re=0.05, m_im=0.0, n_med=1.0, lam=532.0, na=1801, nc=4096),    # m < 1 at x ~ 11.8
 ]
 
 
