@@ -36,8 +36,8 @@
 //   * appends them to the exit log (MC_EXIT_LOG): each block owns a region
 //     of every key range and appends at the position an LDS counter of the
 //     block hands out (one LDS add and one store per exit); a second kernel
-//     (log_bin) sums each range in an LDS histogram and adds the sums into
-//     image copies with plain stores; or
+//     (log_bin) sums each range in an LDS histogram and writes the sums into
+//     image copies with plain loads and stores; or
 //   * adds them into a per-block LDS tally cache (direct-mapped pixel ids
 //     claimed with an LDS compare-and-swap) whose sums go to the images once
 //     per block, with a global atomic into one of eight per-XCD copies of the
@@ -845,9 +845,11 @@ void walk_kernel(WalkArgs a)
             a.log_count[i * gridDim.x + blockIdx.x] = min(s_lcnt[i], a.log_cap);
 }
 
-// Zero the workspace, and the outputs unless accumulating.  (Fill kernels,
+// Zero the workspace words [0, n_ws) and [ws2, ws2 + n_ws2), and the outputs
+// unless accumulating.  (Fill kernels,
 // not memset, so the sequence stays valid under stream capture.)
-__global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long long *side, unsigned long long *trans,
+__global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long long *ws2, size_t n_ws2,
+                            unsigned long long *side, unsigned long long *trans,
                             unsigned long long *side_w2, unsigned long long *trans_w2, size_t n_side, size_t n_trans,
                             double *scalars, size_t n_scalars, int32_t *rec_i, float *rec_f, size_t n_rec,
                             double *side_wk,
@@ -856,6 +858,7 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (size_t i = t0; i < n_ws; i += stride) ws[i] = 0ull;
+    for (size_t i = t0; i < n_ws2; i += stride) ws2[i] = 0ull;
     if (!zero_all) return;
     for (size_t i = t0; i < n_side; i += stride) {
         side[i] = 0ull;                 // +0.0 and int64 0 share the bit pattern
@@ -882,11 +885,14 @@ __global__ void init_kernel(unsigned long long *ws, size_t n_ws, unsigned long l
 // takes the regions of range b that every n_copies-th of the walk's blocks,
 // from block s, wrote (log_count entries each), adds the fixed-point weights (and
 // squared weights) of the entries whose index within the range lies in part
-// p into an LDS histogram of 2^kLogHistBits sums, then adds the non-zero sums
-// into copy s.  Those keys of copy s have no other writer (the walk's
-// fallback atomics have completed), so plain loads and stores do.  The sums
-// are of the same fix() values the walk would have added, so the images
-// equal those of the atomic path bit for bit.
+// p into an LDS histogram of 2^kLogHistBits sums, then writes the sums into
+// copy s.  Copy 0 also holds the walk's fallback atomics (exits that found
+// their region full), so it was cleared and takes the non-zero sums as
+// adds; the other copies were not cleared and take every key's sum as a
+// store (the blocks of copy s cover each of its keys exactly once).  No
+// other writer touches those keys now, so plain loads and stores do.  The
+// sums are of the same fix() values the walk would have added, so the
+// images equal those of the atomic path bit for bit.
 template <bool SIGMA>
 __global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, const uint32_t *count, uint32_t cap,
                                                 uint32_t walk_blocks, unsigned long long *copies,
@@ -946,10 +952,13 @@ __global__ __launch_bounds__(1024) void log_bin(const unsigned long long *log, c
         const uint64_t key = ((uint64_t)((p * inv_mul) & ((1u << bits) - 1u)) << 3) | (h & 7u);
         if (key >= n_total) continue;
         const unsigned long long v = s_hist[i];
-        if (v) dst[key] += v;
-        if (SIGMA) {
-            const unsigned long long v2 = s_hist2[i];
-            if (v2) dst2[key] += v2;
+        const unsigned long long v2 = SIGMA ? s_hist2[i] : 0ull;
+        if (s != 0) {
+            dst[key] = v;
+            if (SIGMA) dst2[key] = v2;
+        } else {
+            if (v) dst[key] += v;
+            if (SIGMA && v2) dst2[key] += v2;
         }
     }
 }
@@ -984,25 +993,39 @@ __global__ __launch_bounds__(256) void finalize_images(const unsigned long long 
     unsigned long long sum_side = 0ull, sum_trans = 0ull;
     const unsigned long long beam_key = ws_scal[kWsBeamKey];
     const unsigned long long beam_v = ws_scal[inst * kWsScalarWords + kWsBallistic] * ball_w;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pix;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        // All copies' loads (and the output's) are issued before any is used.
-        unsigned long long part[kCopies];
+    // Each thread takes kFinPix pixels a grid-stride apart per pass and issues
+    // the loads of all their copies and outputs before using any.
+    constexpr int kFinPix = 4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < n_pix; i0 += kFinPix * stride) {
+        unsigned long long part[kFinPix][kCopies];
+        long long prev[kFinPix];
 #pragma unroll
-        for (int c = 0; c < kCopies; ++c) part[c] = c < n_copies ? copies[(uint64_t)c * n_total + key0 + i] : 0ull;
-        const bool is_side = i < n_side;
-        const uint64_t j = is_side ? i : i - n_side;
-        long long *out_fix = (long long *)(is_side ? side : trans);
-        double *out_dbl = (double *)(is_side ? side : trans);
-        const long long prev_fix = FIX ? out_fix[j] : 0ll;
-        const double prev_dbl = FIX ? 0.0 : out_dbl[j];
-        unsigned long long v = 0ull;
+        for (int u = 0; u < kFinPix; ++u) {
+            const uint64_t i = i0 + u * stride;
+            const bool in = i < n_pix, is_side = i < n_side;
+            const uint64_t j = is_side ? i : i - n_side;
+            long long *out = (long long *)(is_side ? side : trans);
 #pragma unroll
-        for (int c = 0; c < kCopies; ++c) v += part[c];
-        if (beam_key == i + 1) v += beam_v;
-        if (FIX) out_fix[j] = prev_fix + (long long)v;
-        else out_dbl[j] = prev_dbl + (double)(long long)v * (1.0 / kFix);
-        if (is_side) sum_side += v; else sum_trans += v;
+            for (int c = 0; c < kCopies; ++c)
+                part[u][c] = in && c < n_copies ? copies[(uint64_t)c * n_total + key0 + i] : 0ull;
+            prev[u] = in ? out[j] : 0ll;   // the output's bits (int64, or a double's)
+        }
+#pragma unroll
+        for (int u = 0; u < kFinPix; ++u) {
+            const uint64_t i = i0 + u * stride;
+            if (i >= n_pix) break;
+            unsigned long long v = 0ull;
+#pragma unroll
+            for (int c = 0; c < kCopies; ++c) v += part[u][c];
+            if (beam_key == i + 1) v += beam_v;
+            const bool is_side = i < n_side;
+            const uint64_t j = is_side ? i : i - n_side;
+            if (FIX) ((long long *)(is_side ? side : trans))[j] = prev[u] + (long long)v;
+            else ((double *)(is_side ? side : trans))[j] =
+                __longlong_as_double(prev[u]) + (double)(long long)v * (1.0 / kFix);
+            if (is_side) sum_side += v; else sum_trans += v;
+        }
     }
     if (face_side) {
         // One atomic per block and face: same-address global atomics serialise.
@@ -1462,7 +1485,9 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
         launch_shape(false);
     }
     const uint64_t copies = copies_for(use_log);
-    a.copy_mask = (uint32_t)(copies - 1);
+    // With the exit log the walk's only image atomics are its fallback ones
+    // (an exit whose region is full): all of them go to copy 0.
+    a.copy_mask = use_log ? 0u : (uint32_t)(copies - 1);
     a.ws_img2 = (det.flags & MC_SIGMA) ? a.ws_img + copies * n_total : nullptr;
     if (lds > 160 * 1024) return fail(MC_EINVAL, "mc_simulate: %zu bytes of LDS per block do not fit a CU", lds);
     const uint64_t waves_total = (uint64_t)grid * (block / 64);
@@ -1482,7 +1507,13 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     // ---- exit log: a region of log_cap entries per block and key range in
     // what the caller gave beyond the workspace words (the walk writes every
     // count, so nothing needs clearing) ----
-    uint64_t clear_words = workspace_words(det, n_inst, copies);
+    // What init clears: the scalar words and every image copy, except when
+    // log_bin will run (the exit log and some photons): then only copy 0 (and
+    // copy 0 of the squared weights), since log_bin stores into the others.
+    const bool bin_stores = use_log && total_photons > 0;
+    const uint64_t clear_words = bin_stores ? kWsScalarWords * n_inst + n_total : workspace_words(det, n_inst, copies);
+    unsigned long long *clear2 = bin_stores && (det.flags & MC_SIGMA) ? a.ws_img2 : nullptr;
+    const uint64_t clear2_words = clear2 ? n_total : 0;
     if (use_log) {
         const uint64_t regions = ((uint64_t)1 << shape.rbits) * grid;
         const uint64_t log_at = ws_words + sched_words;
@@ -1495,8 +1526,8 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
 
     const int zero_all = (det.flags & MC_ACCUMULATE) ? 0 : 1;
     const bool sig = (det.flags & MC_SIGMA) != 0, rec = (det.flags & MC_RECORD) != 0;
-    hipLaunchKernelGGL(init_kernel, dim3(1024), dim3(256), 0, st, ws, (size_t)clear_words,
-                       (unsigned long long *)t.side, (unsigned long long *)t.trans,
+    hipLaunchKernelGGL(init_kernel, dim3(1024), dim3(256), 0, st, ws, (size_t)clear_words, clear2,
+                       (size_t)clear2_words, (unsigned long long *)t.side, (unsigned long long *)t.trans,
                        sig ? (unsigned long long *)t.side_w2 : nullptr, sig ? (unsigned long long *)t.trans_w2 : nullptr,
                        (size_t)(n_side * n_inst), (size_t)(n_trans * n_inst), t.scalars,
                        (size_t)MC_N_SCALARS * n_inst, a.rec_i, a.rec_f, (size_t)a.rec_rows, a.side_wk, a.side_wl,
