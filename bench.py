@@ -142,8 +142,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # WRITE_SIZE x 1.0); valid only for the tally path and kernel code it was
 # measured on (profiles/walk_tau4_counters.md): the digest covers the walk
 # sources without comments and whitespace, so a comment edit keeps it.
-TRAFFIC = {"tally": "log", "sources_sha256": "a5a3b2577e8fd4c279a7329499505c3425d1abb9da08f685cf6d262d0d1b8aa3",
-           "fetch_kib": 373.1, "write_kib": 558893.4, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"tally": "log", "sources_sha256": "86d64b1b0bd136d7045d62c741593e2f34f99d71bf83528fe4487e1b12c5de81",
+           "fetch_kib": 373.7, "write_kib": 558629.7, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 

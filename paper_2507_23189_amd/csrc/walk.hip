@@ -1403,6 +1403,24 @@ uint32_t refill_min_for(double tau)
     return tau < 14.0 ? 12 : 8;
 }
 
+// Photon ids a wave claims at once (single medium, when the caller leaves
+// it to the library): 16 claims per wave, at most 1024.  Every claim is one
+// device-scope atomic on one word, which takes about 78 million per second
+// (at 256 ids per claim the tau = 4 walk took 5.0 ms instead of 2.75); where
+// photons end within a few steps that rate binds, so below tau = 3 a claim
+// takes 2048 ids (up to tau = 1.05) or 3072, but no fewer than four claims
+// per wave.  mc_simulate at 1e8 photons, 512 x 512: tau = 0.5 1.84 -> 1.21
+// ms, tau = 1 1.91 -> 1.58, tau = 2 2.04 -> 1.88; tau = 4 and 8 ran alike
+// from 384 to 1536 ids.
+uint64_t chunk_for(uint64_t total_photons, uint64_t waves_total, double tau)
+{
+    uint64_t chunk = std::min<uint64_t>(1024, total_photons / std::max<uint64_t>(1, waves_total * 16));
+    if (tau >= 0.0 && tau < 3.0)
+        chunk = std::max(chunk, std::min<uint64_t>(tau <= 1.05 ? 2048 : 3072,
+                                                   total_photons / std::max<uint64_t>(1, waves_total * 4)));
+    return std::max<uint64_t>(64, (chunk + 63) / 64 * 64);
+}
+
 struct InstChunk {
     BatchInst v[kInstPerCopy];
     uint32_t n, first;
@@ -1491,18 +1509,16 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
     a.ws_img2 = (det.flags & MC_SIGMA) ? a.ws_img + copies * n_total : nullptr;
     if (lds > 160 * 1024) return fail(MC_EINVAL, "mc_simulate: %zu bytes of LDS per block do not fit a CU", lds);
     const uint64_t waves_total = (uint64_t)grid * (block / 64);
+    // The optical depth along the beam axis (negative for a batch).
+    const double tau_z = !batch && a.neg_ln2_over_mu < 0.f && std::isfinite(a.neg_ln2_over_mu)
+                             ? -M_LN2 / (double)a.neg_ln2_over_mu * a.size[2]
+                             : -1.0;
     uint64_t chunk = rn.chunk;
-    if (chunk == 0) {
-        chunk = total_photons / std::max<uint64_t>(1, waves_total * 16);
-        chunk = std::max<uint64_t>(64, std::min<uint64_t>(1024, (chunk + 63) / 64 * 64));
-    }
+    if (chunk == 0) chunk = chunk_for(total_photons, waves_total, batch ? -1.0 : tau_z);
     a.chunk = (uint32_t)chunk;
     // Refill threshold from the optical depth; batched launches take the
     // fixed one (12 ran 1 % faster there than 16, and 8 and 24 slower).
-    a.refill_min = batch ? kRefillMin
-                         : refill_min_for(a.neg_ln2_over_mu < 0.f && std::isfinite(a.neg_ln2_over_mu)
-                                              ? -M_LN2 / (double)a.neg_ln2_over_mu * a.size[2]
-                                              : 0.0);
+    a.refill_min = batch ? kRefillMin : refill_min_for(tau_z >= 0.0 ? tau_z : 0.0);
 
     // ---- exit log: a region of log_cap entries per block and key range in
     // what the caller gave beyond the workspace words (the walk writes every
