@@ -14,8 +14,8 @@ The JSON line also carries
                 of the method (counts of steps, interactions, boundary steps
                 and exits, each priced in full-rate FP32 VALU issue slots by
                 instruction class) over its measured average duration (HIP
-                events the library records on the launch stream right before
-                and after that kernel), against the chip's FP32 VALU peak (the
+                events the library attaches to that kernel's dispatch on the
+                launch stream), against the chip's FP32 VALU peak (the
                 published 157.3 TFLOP/s as fused multiply-adds); the same
                 census over the whole mc_simulate (with the log binning and
                 finalize kernels) is reported beside it;
@@ -142,8 +142,8 @@ PEAK_SLOTS_PER_S = 256 * 4 * 32 * 2.4e9
 # WRITE_SIZE x 1.0); valid only for the tally path and kernel code it was
 # measured on (profiles/walk_tau4_counters.md): the digest covers the walk
 # sources without comments and whitespace, so a comment edit keeps it.
-TRAFFIC = {"tally": "log", "sources_sha256": "86d64b1b0bd136d7045d62c741593e2f34f99d71bf83528fe4487e1b12c5de81",
-           "fetch_kib": 373.7, "write_kib": 558629.7, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"tally": "log", "sources_sha256": "38c308aadf57ff13455a2aed5542f66d0dec4c300fd06419b7cc5937b107dc34",
+           "fetch_kib": 374.3, "write_kib": 558765.0, "fetch_factor": 2.0, "write_factor": 1.0}
 WALK_SOURCES = ("paper_2507_23189_amd/csrc/walk.hip", "paper_2507_23189_amd/csrc/philox.hpp")
 
 
@@ -373,7 +373,6 @@ def sweep_timing(mc, W, dev, args):
     mc_simulate timed with HIP events on the launch stream."""
     import torch
     out = []
-    stream = torch.cuda.current_stream()
     for tau, phase in [(t, W.PHASE_MIE) for t in W.PAPER_TAUS if t != 4.0] + [(4.0, W.PHASE_HG)]:
         w = W.paper_scale(tau, phase=phase)
         table = mc.mie_table_build(mc.args_from_workload(w)[0], dev)
@@ -383,13 +382,12 @@ def sweep_timing(mc, W, dev, args):
         ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
         wev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
         run.time_walk(*wev)
+        run.time_sim(*ev)
         for _ in range(3):
             mc.mc_simulate(med, src, geo, det, run, t)
         ms, wms = [], []
         for _ in range(max(3, args.steps // 2)):
-            ev[0].record(stream)
             mc.mc_simulate(med, src, geo, det, run, t)
-            ev[1].record(stream)
             torch.cuda.synchronize()
             ms.append(ev[0].elapsed_time(ev[1]))
             wms.append(wev[0].elapsed_time(wev[1]))
@@ -646,13 +644,22 @@ def main():
     tallies = [mc.Tally.alloc(det_probe, dev, log_photons=w.n_photons)]
     tallies += [mc.Tally.alloc(det_probe, dev, log_photons=w.n_photons, workspace=tallies[0].workspace)
                 for _ in range(args.warmup + args.steps - 1)]
-    # Per step: HIP events around mc_simulate (init, walk, log binning,
-    # finalize) and, recorded by the library on the same stream, around the
-    # walk kernel alone.
+    # Per step: HIP events that the library sets to the start and end of the
+    # walk kernel and, on every fourth timed step, to the start of
+    # mc_simulate's first kernel and the end of its last (init, walk, log
+    # binning, finalize).  They ride on the kernels' dispatches; each pair
+    # still costs the device a few microseconds per step (about 3 us for the
+    # walk's, 8 us for the whole call's), hence the sampling of the second.
+    # Each event is created (recorded once) here, outside the timed steps.
     sim_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.warmup + args.steps)]
+    sim_timed = set(range(args.warmup, args.warmup + args.steps, 4))
     walk_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.warmup + args.steps)]
+    for pair in sim_ev + walk_ev:
+        for e in pair:
+            e.record(stream)
+    torch.cuda.synchronize()
 
     # One step = the table build (device) followed by the walk on the same
     # stream.  With the Mie phase the table is enqueued without a host wait, so
@@ -670,10 +677,8 @@ def main():
         _, med, src, geo, det, run = mc.args_from_workload(w, table, g=g_hg, flags=flags,
                                                            block_size=args.block_size, grid_blocks=args.grid_blocks)
         run.time_walk(*walk_ev[i])
-        e0, e1 = sim_ev[i]
-        e0.record(stream)
+        run.time_sim(*(sim_ev[i] if i in sim_timed else (None, None)))
         mc.mc_simulate(med, src, geo, det, run, tallies[i])
-        e1.record(stream)
         return table
 
     log(f"bench: workload {w.name}, warmup {args.warmup}, steps {args.steps}")
@@ -705,7 +710,7 @@ def main():
     elapsed = t1 - t0
     timed = range(args.warmup, args.warmup + args.steps)
     walk_avg_s = sum(walk_ev[i][0].elapsed_time(walk_ev[i][1]) for i in timed) / args.steps * 1e-3
-    sim_avg_s = sum(sim_ev[i][0].elapsed_time(sim_ev[i][1]) for i in timed) / args.steps * 1e-3
+    sim_avg_s = sum(sim_ev[i][0].elapsed_time(sim_ev[i][1]) for i in sim_timed) / len(sim_timed) * 1e-3
     slots = census_slots(scal[-1])
     achieved = slots / walk_avg_s
     s_last = scal[-1]
@@ -731,13 +736,14 @@ def main():
                      "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS_PER_S,
                      "traffic": measured_traffic(args) if (args.tau == 4.0 and args.photons == 100_000_000
                                                            and phase == W.PHASE_MIE) else None,
-                     "kernel": "walk_kernel (the photon walk; HIP events the library records around it)",
+                     "kernel": "walk_kernel (the photon walk; HIP events the library attaches to its dispatch)",
                      "tally": "atomic" if args.atomic_tally else "exit log",
                      "kernel_ms": walk_avg_s * 1e3, "slots_per_launch": slots,
                      "mc_simulate_ms": sim_avg_s * 1e3,
                      "frac_mc_simulate": slots / sim_avg_s / PEAK_SLOTS_PER_S,
                      "mc_simulate": ("init, walk_kernel, finalize" if args.atomic_tally else
-                                     "init, walk_kernel, log_bin, finalize")},
+                                     "init, walk_kernel, log_bin, finalize") +
+                                    f" (every fourth timed step, {len(sim_timed)} of {args.steps})"},
         "photons_per_s": photons / elapsed,
         "events_per_photon": s_last[9] / s_last[10],
         "steps_per_photon": s_last[14] / s_last[10],

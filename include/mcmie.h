@@ -294,9 +294,13 @@ typedef struct {
     int32_t grid_blocks;   /* blocks; 0 = library choice (enough to fill every CU) */
     uint32_t chunk;        /* photons a wave claims at a time, 1..65536; 0 = library choice */
     uint32_t reserved;     /* set to 0 */
-    void *walk_events[2];  /* optional hipEvent_t pair (NULL: none): mc_simulate records them on its
-                              stream right before and right after the walk kernel, so the caller can
-                              time that kernel alone (hipEventElapsedTime) */
+    void *walk_events[2];  /* optional hipEvent_t pair (NULL: none): set to the start and the end of
+                              the walk kernel, so the caller can time that kernel alone
+                              (hipEventElapsedTime); attached to the kernel's dispatch
+                              (hipExtLaunchKernel), so they add no barrier between kernels */
+    void *sim_events[2];   /* optional hipEvent_t pair (NULL: none): set to the start of the call's
+                              first kernel and the end of its last, attached the same way, to time
+                              the whole call on the device */
 } mc_run_t;
 
 /* Caller-owned DEVICE outputs and workspace. */

@@ -85,18 +85,28 @@ class Run(C.Structure):
                 ("instance", C.c_uint32), ("max_steps", C.c_uint32), ("roulette_w", C.c_double),
                 ("roulette_p", C.c_double), ("record_stride", C.c_uint64), ("block_size", C.c_int32),
                 ("grid_blocks", C.c_int32), ("chunk", C.c_uint32), ("reserved", C.c_uint32),
-                ("walk_events", C.c_void_p * 2)]
+                ("walk_events", C.c_void_p * 2), ("sim_events", C.c_void_p * 2)]
 
     def time_walk(self, start, end):
-        """Have the library record torch.cuda.Events `start` and `end` right
-        before and after the walk kernel (None, None: stop)."""
+        """Have the library set torch.cuda.Events `start` and `end` to the
+        start and end of the walk kernel (None, None: stop)."""
+        self._set_events(self.walk_events, start, end)
+
+    def time_sim(self, start, end):
+        """Have the library set torch.cuda.Events `start` and `end` to the
+        start of the call's first kernel and the end of its last (None, None:
+        stop)."""
+        self._set_events(self.sim_events, start, end)
+
+    @staticmethod
+    def _set_events(slots, start, end):
         for i, ev in enumerate((start, end)):
             if ev is None:
-                self.walk_events[i] = None
+                slots[i] = None
                 continue
             if not ev.cuda_event:
                 ev.record()      # creates the underlying event
-            self.walk_events[i] = ev.cuda_event
+            slots[i] = ev.cuda_event
 
 
 class BatchItem(C.Structure):

@@ -52,6 +52,7 @@
 // the squared-weight tally, per-photon records, path moments, batching and
 // the exit log.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdint>
@@ -1542,7 +1543,11 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
 
     const int zero_all = (det.flags & MC_ACCUMULATE) ? 0 : 1;
     const bool sig = (det.flags & MC_SIGMA) != 0, rec = (det.flags & MC_RECORD) != 0;
-    hipLaunchKernelGGL(init_kernel, dim3(1024), dim3(256), 0, st, ws, (size_t)clear_words, clear2,
+    // The caller's timing events ride on the dispatches themselves
+    // (hipExtLaunchKernel): a separate event record would put a barrier, and
+    // several microseconds of idle device, between two kernels.
+    hipExtLaunchKernelGGL(init_kernel, dim3(1024), dim3(256), 0, st, (hipEvent_t)rn.sim_events[0], nullptr, 0u, ws,
+                          (size_t)clear_words, clear2,
                        (size_t)clear2_words, (unsigned long long *)t.side, (unsigned long long *)t.trans,
                        sig ? (unsigned long long *)t.side_w2 : nullptr, sig ? (unsigned long long *)t.trans_w2 : nullptr,
                        (size_t)(n_side * n_inst), (size_t)(n_trans * n_inst), t.scalars,
@@ -1602,13 +1607,16 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
         }
         units = total_photons;
     }
-    if (rn.walk_events[0]) MC_HIP_CHECK(hipEventRecord((hipEvent_t)rn.walk_events[0], st));
     if (units > 0) {
         MC_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, a);
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), (uint32_t)lds, st, (hipEvent_t)rn.walk_events[0],
+                              (hipEvent_t)rn.walk_events[1], 0u, a);
         MC_HIP_CHECK(hipGetLastError());
+    } else {
+        // No walk: the events mark the (empty) place where it would run.
+        if (rn.walk_events[0]) MC_HIP_CHECK(hipEventRecord((hipEvent_t)rn.walk_events[0], st));
+        if (rn.walk_events[1]) MC_HIP_CHECK(hipEventRecord((hipEvent_t)rn.walk_events[1], st));
     }
-    if (rn.walk_events[1]) MC_HIP_CHECK(hipEventRecord((hipEvent_t)rn.walk_events[1], st));
     if (use_log && units > 0) {
         uint32_t inv = kLogHashMul;   // inverse of the odd multiplier mod 2^32 (Newton: x <- x (2 - m x))
         for (int i = 0; i < 5; ++i) inv *= 2u - kLogHashMul * inv;
@@ -1637,7 +1645,8 @@ int launch_walk(WalkArgs &a, const mc_detector_t &det, const mc_run_t &rn, const
         hipLaunchKernelGGL(fin, dim3(fin_x, n_inst), dim3(256), 0, st, a.ws_img2, (int)copies, n_total, n_pix,
                            (uint32_t)n_side, t.side_w2, t.trans_w2, (unsigned long long *)nullptr,
                            (unsigned long long *)nullptr, kWsScalarWords, (const unsigned long long *)ws, ball_w2);
-    hipLaunchKernelGGL(finalize_scalars, dim3(n_inst), dim3(64), 0, st, (const unsigned long long *)ws, t.scalars);
+    hipExtLaunchKernelGGL(finalize_scalars, dim3(n_inst), dim3(64), 0, st, nullptr, (hipEvent_t)rn.sim_events[1], 0u,
+                          (const unsigned long long *)ws, t.scalars);
     MC_HIP_CHECK(hipGetLastError());
     return MC_OK;
 }

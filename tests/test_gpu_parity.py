@@ -353,8 +353,10 @@ def test_medium_forms_give_the_same_walk(mc, cuda_device):
 
 
 def test_walk_kernel_timing_events(mc, cuda_device):
-    """Events passed in the run are recorded right around the walk kernel:
-    they time less than the whole mc_simulate and leave the results alone."""
+    """Events passed in the run are set to the walk kernel's start and end,
+    and to the start and end of the call's kernels: the walk times less than
+    the call's kernels, which time less than the host-recorded bracket, and
+    the results do not change."""
     torch = _torch()
     w = W.TINY.replace(n_photons=200_000, tau=3.0)
     spec, *_ = mc.args_from_workload(w)
@@ -364,12 +366,15 @@ def test_walk_kernel_timing_events(mc, cuda_device):
     mc.mc_simulate(med, src, geo, det, run, a)
     walk = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     whole = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    sim = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     run.time_walk(*walk)
+    run.time_sim(*sim)
     b = mc.Tally.alloc(det, cuda_device, fix64=True)
     whole[0].record()
     mc.mc_simulate(med, src, geo, det, run, b)
     whole[1].record()
     torch.cuda.synchronize()
     t_walk, t_whole = walk[0].elapsed_time(walk[1]), whole[0].elapsed_time(whole[1])
-    assert 0.0 < t_walk <= t_whole
+    t_sim = sim[0].elapsed_time(sim[1])
+    assert 0.0 < t_walk <= t_sim <= t_whole
     assert torch.equal(a.side, b.side) and torch.equal(a.scalars, b.scalars)
