@@ -101,7 +101,7 @@ struct MieArgs {
     double *work;            // n_angles: P(theta_j) sin(theta_j), from the phase kernel to the inverse kernel
 };
 
-// Step 1 by the whole workgroup: the series for size parameter x and relative
+// Step 1 by every lane of a workgroup: the series for size parameter x and relative
 // index m.  The two recurrences are serial and run at once on lanes of two
 // different waves: D_n(mx) downward from n_start and psi_n(x), chi_n(x)
 // upward (into s_psi, s_chi at index n, n = 0..N).  One downward step
