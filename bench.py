@@ -193,8 +193,8 @@ def census_slots(scal, hg=False):
 
 def host_cpu():
     """CPU model, logical CPUs, CPUs this process may run on, and the share of
-    them the benchmark uses: OMP_NUM_THREADS when set (a GPU machine allots each
-    GPU a fixed share of its host cores), else every CPU in the affinity set."""
+    them the benchmark uses: OMP_NUM_THREADS when set (a shared host may allot each
+    GPU a fixed share of its cores), else every CPU in the affinity set."""
     try:
         model = open("/proc/cpuinfo").read().split("model name")[1].split("\n")[0].strip(" :\t")
     except Exception:
@@ -622,7 +622,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the walk shards by photon range across GPUs but this build runs on a single device.",
+              "the walk would shard by photon range across GPUs, but this library runs on a single device.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -41,7 +41,7 @@ extern "C" {
 #define MC_EINVAL (-1)        /* an argument is out of range or inconsistent */
 #define MC_EDEVICE (-2)       /* a HIP runtime call failed */
 #define MC_ENOMEM (-3)        /* device scratch could not be allocated */
-#define MC_EUNSUPPORTED (-4)  /* a valid request this build does not implement */
+#define MC_EUNSUPPORTED (-4)  /* a valid request this library does not implement */
 
 #define MC_PHASE_MIE 0        /* polar angle from the inverse-CDF table */
 #define MC_PHASE_HG 1         /* polar angle from Henyey-Greenstein (Eq. 11) */
